@@ -1,0 +1,171 @@
+/*
+ * polaris.h -- C ABI of the MI355X (gfx950) spectrometer library.
+ *
+ * The library computes, for two-polarization sampler data, the auto- and cross-power spectra of a
+ * windowed long FFT per segment, accumulated over an integration, and the calibrated full-Stokes
+ * spectra, as described by Mizuno et al., "Software Polarization Spectrometer PolariS" (arXiv 1412.1256):
+ *   - Sec. 2, the statement of the spectrometer's four functions (accept two orthogonal polarizations,
+ *     FFT them, multiply spectra into power and cross-power spectra, integrate and output);
+ *   - Fig. 2 caption (data translation of 4/8-bit integers to floats, segmentation, FFT, cross products,
+ *     accumulation) and Table 1 (IFs X0, X1, Y0, Y1; 4 real and 2 complex products; 1-s output);
+ *   - Sec. 2.1, Eq. 2 (Stokes I, Q, U, V from the products divided by the complex gain products).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns a ps_status; none throws, prints or exits.  ps_last_error() gives a
+ *     thread-local detail string for the last non-OK status.
+ *   - The caller owns every device buffer, including the workspace whose size ps_plan reports.  The
+ *     library never allocates or frees device memory; a plan owns host metadata only.
+ *   - All device work is enqueued asynchronously on the stream given to ps_bind; no call synchronises
+ *     except ps_bind itself.  ps_reset, ps_accumulate, ps_spectra, ps_stokes, ps_set_window_taps and
+ *     ps_calibrate_backward enqueue kernels only (no allocation, copy or memset), so they can be
+ *     captured into a hipGraph.
+ *   - Argument and size errors are returned before anything is enqueued (no partial work).  Kernel
+ *     launch failures return PS_ERR_HIP.  Faults inside kernels surface at the caller's next
+ *     synchronisation.
+ *   - Layouts: "complex" arrays are interleaved (re, im) pairs; channel k of an N-point segment runs
+ *     over k = 0 .. N/2 - 1 (DC kept, Nyquist dropped).
+ */
+#ifndef POLARIS_H
+#define POLARIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PS_OK = 0,
+  PS_ERR_ARG = 1,          /* a null pointer, an out-of-range field or inconsistent arguments */
+  PS_ERR_SIZE = 2,         /* a sample count that is not a whole number of segments */
+  PS_ERR_UNSUPPORTED = 3,  /* a valid request this build does not implement */
+  PS_ERR_STATE = 4,        /* call order violated (unbound plan, no frames integrated, ...) */
+  PS_ERR_WORKSPACE = 5,    /* workspace missing, too small or misaligned */
+  PS_ERR_HIP = 6           /* a HIP runtime call or kernel launch failed */
+} ps_status;
+
+/* window kinds (Sec. 3.1: rectangular online; others are applied as apodisation) */
+enum { PS_WIN_RECT = 0, PS_WIN_HANN = 1, PS_WIN_TAPS = 2 };
+/* arithmetic of the transform passes */
+enum { PS_PREC_FP32 = 0, PS_PREC_FP16 = 1, PS_PREC_BF16 = 2 };
+/* accumulator of the integration */
+enum { PS_ACC_FP64 = 0, PS_ACC_KAHAN32 = 1 };
+
+typedef struct ps_plan_s* ps_plan_t;
+
+/*
+ * One instance = one sampler stream set (Table 1).
+ *   n_streams   S, 1..8 streams interleaved in one buffer (Table 1 order, e.g. X0, X1, Y0, Y1).
+ *   n_pairs     P, 1..4 polarization pairs; pair p correlates stream pair_x[p] (X) with pair_y[p] (Y).
+ *   bits        2 or 4 (offset-binary codes c -> level 2c - (2^b - 1)), 8 (two's-complement int8) or
+ *               32 (little-endian float32, a test format).  Item t*S + s of the buffer sits at bit
+ *               offset (t*S + s)*bits, least significant bits first.
+ *   fft_len     N, a power of two, 2^6 .. 2^22; channels C = N/2; one segment = N samples per stream.
+ *   window      PS_WIN_RECT, PS_WIN_HANN (periodic) or PS_WIN_TAPS (n_taps control points, linear
+ *               interpolation at u = n (n_taps - 1)/(N - 1); all ones until ps_set_window_taps).
+ *   precision   PS_PREC_FP32 (the only value accepted by this build's plain path).
+ *   accum       PS_ACC_FP64.
+ *   chunk_frames  frames processed per internal pass pair (0 = 64); bounds the workspace.
+ *   sample_rate_hz  metadata only (channel width = sample_rate_hz / N).
+ */
+typedef struct {
+  int32_t n_streams;
+  int32_t n_pairs;
+  int32_t pair_x[4];
+  int32_t pair_y[4];
+  int32_t bits;
+  int32_t window;
+  int32_t n_taps;
+  int32_t precision;
+  int32_t accum;
+  int32_t chunk_frames;
+  int64_t fft_len;
+  double sample_rate_hz;
+} ps_instance;
+
+/*
+ * Calibration for Eq. 2.  All pointers are device memory, may be NULL.
+ *   gain_x, gain_y  [n_pairs][C] complex float: G_X, G_Y (voltage-domain gains); NULL = 1.
+ *   dterms          [n_pairs][4] float: d_x (re, im), d_y (re, im) of the leakage matrix
+ *                   J = [[1, d_x], [d_y, 1]] (observed v' = G J v); NULL = 0 (Eq. 2 exactly).
+ *   psi             parallactic angle psi_m in radians.
+ */
+typedef struct {
+  const float* gain_x;
+  const float* gain_y;
+  const float* dterms;
+  double psi;
+} ps_cal;
+
+/* Gradient outputs of ps_calibrate_backward, device memory, NULL = not wanted.  Complex gradients are
+ * (dL/dRe, dL/dIm) pairs, the layout of the matching ps_cal field; d_taps has n_taps floats. */
+typedef struct {
+  float* d_gain_x;
+  float* d_gain_y;
+  float* d_dterms;
+  float* d_taps;
+} ps_cal_grad;
+
+/* Validate n_inst instances, build host tables and report the workspace size (bytes, 256-aligned).
+ * Errors: PS_ERR_ARG for bad fields, PS_ERR_UNSUPPORTED for valid but unimplemented options. */
+ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_t* workspace_bytes);
+
+/* Attach a device workspace (>= the reported size, 256-byte aligned) and a HIP stream (hipStream_t,
+ * NULL = the default stream); uploads the FP64-generated twiddle and window tables and waits for the
+ * upload.  Re-binding is allowed and resets every integration. */
+ps_status ps_bind(ps_plan_t plan, void* workspace_dev, size_t bytes, void* hip_stream);
+
+/* Set the n_taps window control points of a PS_WIN_TAPS instance from device floats (enqueued). */
+ps_status ps_set_window_taps(ps_plan_t plan, int32_t inst, const float* taps_dev);
+
+/* Start a new integration for every instance (host bookkeeping only; enqueues nothing). */
+ps_status ps_reset(ps_plan_t plan);
+
+/* Add whole segments to each instance's integration (Sec. 2: FFT, cross products, accumulation).
+ *   packed_dev[i]   device pointer to instance i's packed buffer (layout above); may be NULL when
+ *                   n_samples[i] == 0.
+ *   n_samples[i]    samples per stream, a multiple of fft_len (PS_ERR_SIZE otherwise).
+ * Frames are added in order; splitting one input over several calls gives bitwise the same sums. */
+ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples);
+
+/* Raw accumulated products of instance inst into out_dev [n_pairs][4][C] doubles:
+ * sum over frames of XX*, YY*, Re XY*, Im XY* (unnormalised), and the frame count (host).
+ * PS_ERR_STATE if no frame has been accumulated since ps_reset. */
+ps_status ps_spectra(ps_plan_t plan, int32_t inst, double* out_dev, int64_t* n_frames);
+
+/* Calibrated full-Stokes spectra (Eq. 2) of instance inst into iquv_dev [n_pairs][4][C] floats
+ * (I, Q, U, V), computed in FP64 from M = A / (F sum w^2) and C = (G J)^-1 M (G J)^-H.  cal may be NULL
+ * (unit gains, no leakage, psi = 0).  The integration is read, not consumed. */
+ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv_dev);
+
+/* Gradient of a real loss L(iquv) with respect to the gains, leakage terms and window taps, given
+ * dL_diquv_dev [n_pairs][4][C] floats.  Needs the current integration (the forward's accumulators,
+ * not reset) and the same packed input (n_samples per stream, all frames of the integration); frames are
+ * transformed again instead of being stored.  PS_ERR_STATE if the frame count does not match. */
+ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed_dev, int64_t n_samples,
+                                const ps_cal* cal, const float* dL_diquv_dev, const ps_cal_grad* grad);
+
+/* Integration state (accumulators; the frame count is kept by the plan) for checkpoint and resume. */
+ps_status ps_state_bytes(ps_plan_t plan, int32_t inst, size_t* bytes);
+ps_status ps_state_export(ps_plan_t plan, int32_t inst, void* dst_dev, int64_t* n_frames);
+ps_status ps_state_import(ps_plan_t plan, int32_t inst, const void* src_dev, int64_t n_frames);
+
+/* Stand-alone data translation (Fig. 2 caption): decode n_time x n_streams items of a packed buffer into
+ * out_dev[s * n_time + t] floats (exact for every format), enqueued on hip_stream. */
+ps_status ps_unpack(const void* packed_dev, int32_t bits, int32_t n_streams, int64_t n_time, float* out_dev,
+                    void* hip_stream);
+
+/* Free a plan's host metadata (never the caller's device memory). NULL is accepted. */
+ps_status ps_destroy(ps_plan_t plan);
+
+const char* ps_status_string(ps_status status);
+const char* ps_last_error(void);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t ps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POLARIS_H */

@@ -1,0 +1,290 @@
+"""MI355X-native spectrometer path of PolariS (Mizuno et al., arXiv 1412.1256): Python binding.
+
+The compute runs in ``libpolaris.so`` (hand-written gfx950 HIP kernels behind the C ABI of
+``include/polaris.h``).  This module only marshals arguments: torch provides device memory and the stream.
+There is no fallback: importing the binding when the library is missing raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Sequence
+
+__all__ = ["PolarisError", "Instance", "Plan", "unpack", "lib", "LIB_PATH", "WIN", "PREC", "ACC"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpolaris.so")
+
+WIN = {"rect": 0, "hann": 1, "taps": 2}
+PREC = {"fp32": 0, "fp16": 1, "bf16": 2}
+ACC = {"fp64": 0, "kahan32": 1}
+
+STATUS = {0: "PS_OK", 1: "PS_ERR_ARG", 2: "PS_ERR_SIZE", 3: "PS_ERR_UNSUPPORTED", 4: "PS_ERR_STATE",
+          5: "PS_ERR_WORKSPACE", 6: "PS_ERR_HIP"}
+
+
+class PolarisError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        self.code = STATUS.get(status, f"PS_{status}")
+        super().__init__(f"{self.code}: {detail}")
+
+
+class _Instance(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("n_pairs", C.c_int32), ("pair_x", C.c_int32 * 4),
+                ("pair_y", C.c_int32 * 4), ("bits", C.c_int32), ("window", C.c_int32), ("n_taps", C.c_int32),
+                ("precision", C.c_int32), ("accum", C.c_int32), ("chunk_frames", C.c_int32),
+                ("fft_len", C.c_int64), ("sample_rate_hz", C.c_double)]
+
+
+class _Cal(C.Structure):
+    _fields_ = [("gain_x", C.c_void_p), ("gain_y", C.c_void_p), ("dterms", C.c_void_p), ("psi", C.c_double)]
+
+
+class _CalGrad(C.Structure):
+    _fields_ = [("d_gain_x", C.c_void_p), ("d_gain_y", C.c_void_p), ("d_dterms", C.c_void_p),
+                ("d_taps", C.c_void_p)]
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        sig = {
+            "ps_plan": [C.POINTER(_Instance), i32, C.POINTER(vp), C.POINTER(sz)],
+            "ps_bind": [vp, vp, sz, vp],
+            "ps_set_window_taps": [vp, i32, vp],
+            "ps_reset": [vp],
+            "ps_accumulate": [vp, C.POINTER(vp), C.POINTER(i64)],
+            "ps_spectra": [vp, i32, vp, C.POINTER(i64)],
+            "ps_stokes": [vp, i32, C.POINTER(_Cal), vp],
+            "ps_calibrate_backward": [vp, i32, vp, i64, C.POINTER(_Cal), vp, C.POINTER(_CalGrad)],
+            "ps_state_bytes": [vp, i32, C.POINTER(sz)],
+            "ps_state_export": [vp, i32, vp, C.POINTER(i64)],
+            "ps_state_import": [vp, i32, vp, i64],
+            "ps_unpack": [vp, i32, i32, i64, vp, vp],
+            "ps_destroy": [vp],
+            "ps_status_string": [C.c_int],
+            "ps_last_error": [],
+            "ps_version": [],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.ps_status_string.restype = C.c_char_p
+        L.ps_last_error.restype = C.c_char_p
+        L.ps_version.restype = C.c_int32
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int):
+    if status != 0:
+        raise PolarisError(status, lib().ps_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Instance:
+    """One sampler stream set (see ``ps_instance`` in include/polaris.h)."""
+    fft_len: int
+    bits: int = 8
+    n_streams: int = 2
+    pairs: Sequence[tuple] = ((0, 1),)
+    window: str = "rect"
+    n_taps: int = 0
+    precision: str = "fp32"
+    accum: str = "fp64"
+    chunk_frames: int = 0
+    sample_rate_hz: float = 16e6
+
+    def to_c(self) -> _Instance:
+        s = _Instance()
+        s.n_streams = self.n_streams
+        s.n_pairs = len(self.pairs)
+        for i, (x, y) in enumerate(self.pairs[:4]):
+            s.pair_x[i] = x
+            s.pair_y[i] = y
+        s.bits = self.bits
+        s.window = WIN[self.window] if isinstance(self.window, str) else int(self.window)
+        s.n_taps = self.n_taps
+        s.precision = PREC[self.precision] if isinstance(self.precision, str) else int(self.precision)
+        s.accum = ACC[self.accum] if isinstance(self.accum, str) else int(self.accum)
+        s.chunk_frames = self.chunk_frames
+        s.fft_len = self.fft_len
+        s.sample_rate_hz = self.sample_rate_hz
+        return s
+
+    @property
+    def n_pairs(self):
+        return len(self.pairs)
+
+    @property
+    def channels(self):
+        return self.fft_len // 2
+
+    @staticmethod
+    def from_synth(d: dict, **over) -> "Instance":
+        kw = dict(fft_len=d["fft_len"], bits=d["bits"], n_streams=d["n_streams"], pairs=tuple(d["pairs"]),
+                  window=d["window"], n_taps=64 if d["window"] == "taps" else 0)
+        kw.update(over)
+        return Instance(**kw)
+
+
+def plan_workspace_bytes(instances: Sequence[Instance]) -> int:
+    arr = (_Instance * len(instances))(*[i.to_c() for i in instances])
+    h = C.c_void_p()
+    nbytes = C.c_size_t()
+    _check(lib().ps_plan(arr, len(instances), C.byref(h), C.byref(nbytes)))
+    lib().ps_destroy(h)
+    return nbytes.value
+
+
+class Plan:
+    """A bound plan: host metadata in the library, workspace in a torch uint8 tensor on one device."""
+
+    def __init__(self, instances: Sequence[Instance], device=None, stream=None):
+        import torch
+        self.torch = torch
+        self.instances = list(instances)
+        arr = (_Instance * len(self.instances))(*[i.to_c() for i in self.instances])
+        h = C.c_void_p()
+        nbytes = C.c_size_t()
+        _check(lib().ps_plan(arr, len(self.instances), C.byref(h), C.byref(nbytes)))
+        self._h = h
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # the library needs 256-byte alignment; over-allocate and offset
+        self._ws_raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws_raw.data_ptr()) % 256
+        self.workspace = self._ws_raw[off:off + nbytes.value]
+        self.workspace_bytes = nbytes.value
+        _check(lib().ps_bind(self._h, C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                             C.c_void_p(self.stream.cuda_stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _LIB is not None:
+            _LIB.ps_destroy(h)
+            self._h = None
+
+    # --------------------------------------------------------------------------------------------
+    def reset(self):
+        _check(lib().ps_reset(self._h))
+
+    def accumulate(self, packed, n_samples=None):
+        """packed: one uint8 device tensor per instance (or a single tensor for a one-instance plan)."""
+        if not isinstance(packed, (list, tuple)):
+            packed = [packed]
+        n = len(self.instances)
+        if len(packed) != n:
+            raise ValueError(f"expected {n} packed buffers, got {len(packed)}")
+        ptrs = (C.c_void_p * n)(*[None if p is None else p.data_ptr() for p in packed])
+        if n_samples is None:
+            n_samples = []
+            for inst, p in zip(self.instances, packed):
+                bits_per_t = inst.n_streams * inst.bits
+                n_samples.append(0 if p is None else p.numel() * 8 // bits_per_t)
+        ns = (C.c_int64 * n)(*n_samples)
+        _check(lib().ps_accumulate(self._h, ptrs, ns))
+
+    def spectra(self, inst: int = 0, out=None):
+        I = self.instances[inst]
+        if out is None:
+            out = self.torch.empty((I.n_pairs, 4, I.channels), dtype=self.torch.float64, device=self.device)
+        nf = C.c_int64()
+        _check(lib().ps_spectra(self._h, inst, _ptr(out), C.byref(nf)))
+        return out, nf.value
+
+    def _cal(self, gain_x, gain_y, dterms, psi):
+        cal = _Cal()
+        cal.gain_x = None if gain_x is None else gain_x.data_ptr()
+        cal.gain_y = None if gain_y is None else gain_y.data_ptr()
+        cal.dterms = None if dterms is None else dterms.data_ptr()
+        cal.psi = float(psi)
+        return cal
+
+    def stokes(self, inst: int = 0, gain_x=None, gain_y=None, dterms=None, psi: float = 0.0, out=None):
+        """Calibrated I, Q, U, V [n_pairs][4][C] float32.  gains: float32 [P][C][2] (or complex64 [P][C])."""
+        I = self.instances[inst]
+        gain_x, gain_y, dterms = (self._as_f32(gain_x), self._as_f32(gain_y), self._as_f32(dterms))
+        if out is None:
+            out = self.torch.empty((I.n_pairs, 4, I.channels), dtype=self.torch.float32, device=self.device)
+        cal = self._cal(gain_x, gain_y, dterms, psi)
+        _check(lib().ps_stokes(self._h, inst, C.byref(cal), _ptr(out)))
+        return out
+
+    def calibrate_backward(self, packed, dL_diquv, inst: int = 0, gain_x=None, gain_y=None, dterms=None,
+                           psi: float = 0.0, want=("gain_x", "gain_y", "dterms", "taps")):
+        I = self.instances[inst]
+        torch = self.torch
+        gain_x, gain_y, dterms = (self._as_f32(gain_x), self._as_f32(gain_y), self._as_f32(dterms))
+        P, Cn = I.n_pairs, I.channels
+        outs = {}
+        grad = _CalGrad()
+        if "gain_x" in want:
+            outs["gain_x"] = torch.empty((P, Cn, 2), dtype=torch.float32, device=self.device)
+            grad.d_gain_x = outs["gain_x"].data_ptr()
+        if "gain_y" in want:
+            outs["gain_y"] = torch.empty((P, Cn, 2), dtype=torch.float32, device=self.device)
+            grad.d_gain_y = outs["gain_y"].data_ptr()
+        if "dterms" in want:
+            outs["dterms"] = torch.empty((P, 4), dtype=torch.float32, device=self.device)
+            grad.d_dterms = outs["dterms"].data_ptr()
+        if "taps" in want and I.window == "taps":
+            outs["taps"] = torch.empty((I.n_taps,), dtype=torch.float32, device=self.device)
+            grad.d_taps = outs["taps"].data_ptr()
+        cal = self._cal(gain_x, gain_y, dterms, psi)
+        n_samples = packed.numel() * 8 // (I.n_streams * I.bits)
+        g = dL_diquv.to(torch.float32).contiguous()
+        _check(lib().ps_calibrate_backward(self._h, inst, _ptr(packed), n_samples, C.byref(cal), _ptr(g),
+                                           C.byref(grad)))
+        return outs
+
+    def set_window_taps(self, taps, inst: int = 0):
+        t = self._as_f32(taps)
+        _check(lib().ps_set_window_taps(self._h, inst, _ptr(t)))
+        self._taps_keepalive = t
+
+    def state_bytes(self, inst: int = 0) -> int:
+        n = C.c_size_t()
+        _check(lib().ps_state_bytes(self._h, inst, C.byref(n)))
+        return n.value
+
+    def state_export(self, inst: int = 0):
+        buf = self.torch.empty(self.state_bytes(inst), dtype=self.torch.uint8, device=self.device)
+        nf = C.c_int64()
+        _check(lib().ps_state_export(self._h, inst, _ptr(buf), C.byref(nf)))
+        return buf, nf.value
+
+    def state_import(self, buf, n_frames: int, inst: int = 0):
+        _check(lib().ps_state_import(self._h, inst, _ptr(buf), int(n_frames)))
+
+    def _as_f32(self, t):
+        if t is None:
+            return None
+        torch = self.torch
+        if t.is_complex():
+            t = torch.view_as_real(t.to(torch.complex64))
+        return t.to(device=self.device, dtype=torch.float32).contiguous()
+
+
+def unpack(packed, bits: int, n_streams: int, n_time: int, stream=None):
+    """Stand-alone data translation: float32 [n_streams][n_time] levels of a packed device buffer."""
+    import torch
+    out = torch.empty((n_streams, n_time), dtype=torch.float32, device=packed.device)
+    s = stream if stream is not None else torch.cuda.current_stream(packed.device)
+    _check(lib().ps_unpack(_ptr(packed), bits, n_streams, n_time, _ptr(out), C.c_void_p(s.cuda_stream)))
+    return out

@@ -1,0 +1,442 @@
+// polaris_api.cpp -- host side of the C ABI declared in include/polaris.h.
+//
+// Validation, workspace layout, FP64-generated twiddle and window tables, integration bookkeeping and
+// the launch sequence of each call.  No device memory is allocated here: the caller's workspace holds
+// every table, the FP32 inter-pass buffer and the FP64 accumulators.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/polaris.h"
+#include "polaris_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ps_status fail(ps_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+ps_status fail(ps_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+ps_status hip_fail(hipError_t e, const char* what) {
+  return fail(PS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int ilog2_exact(int64_t n) {
+  if (n <= 0 || (n & (n - 1))) return -1;
+  int m = 0;
+  while ((int64_t(1) << m) < n) ++m;
+  return m;
+}
+
+// W_len^m = exp(-2 pi i m / len) for m < count, evaluated in FP64 at exactly reduced arguments and
+// rounded once to FP32.
+void twiddle_table(std::vector<float>& out, int64_t len, int64_t count) {
+  out.resize(2 * (size_t)count);
+  for (int64_t m = 0; m < count; ++m) {
+    const double a = kTwoPi * (double)(m % len) / (double)len;
+    out[2 * m] = (float)std::cos(a);
+    out[2 * m + 1] = (float)-std::sin(a);
+  }
+}
+
+struct Inst {
+  ps_instance cfg{};
+  int m = 0, m1 = 0, m2 = 0;
+  int64_t N = 0, C = 0, N1 = 0, N2 = 0, chunk = 0;
+  bool fast = false;
+  size_t off_tw_col = 0, off_tw_row = 0, off_tw_lo = 0, off_win = 0, off_taps = 0, off_sumw2 = 0;
+  size_t off_T = 0, off_acc = 0, end = 0;
+  std::vector<float> tw_col, tw_row, tw_lo, win;
+  double sumw2 = 0.0;
+  bool first = true;
+  int64_t n_frames = 0;
+  size_t acc_bytes() const { return (size_t)cfg.n_pairs * (size_t)(N1 / 2) * 4 * (size_t)N2 * sizeof(double); }
+};
+
+}  // namespace
+
+struct ps_plan_s {
+  std::vector<Inst> inst;
+  size_t ws_bytes = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+};
+
+namespace {
+
+ps_status validate_instance(const ps_instance& c, int idx) {
+  if (c.n_streams < 1 || c.n_streams > 8) return fail(PS_ERR_ARG, "instance %d: n_streams %d not in 1..8", idx, c.n_streams);
+  if (c.n_pairs < 1 || c.n_pairs > 4) return fail(PS_ERR_ARG, "instance %d: n_pairs %d not in 1..4", idx, c.n_pairs);
+  for (int p = 0; p < c.n_pairs; ++p) {
+    if (c.pair_x[p] < 0 || c.pair_x[p] >= c.n_streams || c.pair_y[p] < 0 || c.pair_y[p] >= c.n_streams)
+      return fail(PS_ERR_ARG, "instance %d: pair %d (%d, %d) outside 0..%d", idx, p, c.pair_x[p], c.pair_y[p],
+                  c.n_streams - 1);
+  }
+  if (c.bits != 2 && c.bits != 4 && c.bits != 8 && c.bits != 32)
+    return fail(PS_ERR_ARG, "instance %d: bits %d not in {2, 4, 8, 32}", idx, c.bits);
+  const int m = ilog2_exact(c.fft_len);
+  if (m < 0) return fail(PS_ERR_ARG, "instance %d: fft_len %lld is not a power of two", idx, (long long)c.fft_len);
+  if (m < 8 || m > 22)
+    return fail(PS_ERR_UNSUPPORTED, "instance %d: fft_len 2^%d outside the supported 2^8 .. 2^22", idx, m);
+  if (c.window != PS_WIN_RECT && c.window != PS_WIN_HANN && c.window != PS_WIN_TAPS)
+    return fail(PS_ERR_ARG, "instance %d: unknown window %d", idx, c.window);
+  if (c.window == PS_WIN_TAPS && (c.n_taps < 2 || c.n_taps > 4096))
+    return fail(PS_ERR_ARG, "instance %d: n_taps %d not in 2..4096", idx, c.n_taps);
+  if (c.precision != PS_PREC_FP32 && c.precision != PS_PREC_FP16 && c.precision != PS_PREC_BF16)
+    return fail(PS_ERR_ARG, "instance %d: unknown precision %d", idx, c.precision);
+  if (c.precision != PS_PREC_FP32)
+    return fail(PS_ERR_UNSUPPORTED, "instance %d: reduced-precision passes are not built in this library", idx);
+  if (c.accum != PS_ACC_FP64 && c.accum != PS_ACC_KAHAN32)
+    return fail(PS_ERR_ARG, "instance %d: unknown accumulator %d", idx, c.accum);
+  if (c.accum != PS_ACC_FP64)
+    return fail(PS_ERR_UNSUPPORTED, "instance %d: only FP64 accumulation is built with FP32 passes", idx);
+  if (c.chunk_frames < 0 || c.chunk_frames > 65536)
+    return fail(PS_ERR_ARG, "instance %d: chunk_frames %d not in 0..65536", idx, c.chunk_frames);
+  return PS_OK;
+}
+
+void build_tables(Inst& I) {
+  twiddle_table(I.tw_col, I.N1, I.N1);
+  twiddle_table(I.tw_row, I.N2, I.N2);
+  twiddle_table(I.tw_lo, I.N, I.N2);  // W_N^m, m < N2; W_N^(q*N2) = W_N1^q reuses tw_col
+  I.win.clear();
+  double s = 0.0;
+  if (I.cfg.window == PS_WIN_HANN) {
+    I.win.resize((size_t)I.N);
+    for (int64_t n = 0; n < I.N; ++n) {
+      const double w = 0.5 - 0.5 * std::cos(kTwoPi * (double)n / (double)I.N);
+      I.win[(size_t)n] = (float)w;
+      s += w * w;
+    }
+  } else if (I.cfg.window == PS_WIN_TAPS) {
+    I.win.assign((size_t)I.N, 1.0f);  // all control points 1 until set
+    s = (double)I.N;
+  } else {
+    s = (double)I.N;
+  }
+  I.sumw2 = s;
+}
+
+ps_status check_plan(ps_plan_t plan, bool need_bound) {
+  if (!plan) return fail(PS_ERR_ARG, "null plan");
+  if (need_bound && !plan->bound) return fail(PS_ERR_STATE, "plan is not bound to a workspace (call ps_bind)");
+  return PS_OK;
+}
+
+ps_status check_inst(ps_plan_t plan, int32_t i) {
+  if (i < 0 || i >= (int32_t)plan->inst.size())
+    return fail(PS_ERR_ARG, "instance %d outside 0..%d", i, (int)plan->inst.size() - 1);
+  return PS_OK;
+}
+
+template <class T>
+T* ws_ptr(ps_plan_t plan, size_t off) {
+  return reinterpret_cast<T*>(plan->ws + off);
+}
+
+ps_status upload(ps_plan_t plan, size_t off, const void* src, size_t bytes) {
+  if (!bytes) return PS_OK;
+  hipError_t e = hipMemcpyAsync(plan->ws + off, src, bytes, hipMemcpyHostToDevice, plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "table upload");
+  return PS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_t* workspace_bytes) {
+  if (!inst || !out || !workspace_bytes) return fail(PS_ERR_ARG, "null argument to ps_plan");
+  *out = nullptr;
+  if (n_inst < 1 || n_inst > 4096) return fail(PS_ERR_ARG, "n_inst %d not in 1..4096", n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    ps_status st = validate_instance(inst[i], i);
+    if (st != PS_OK) return st;
+  }
+  ps_plan_s* plan = new (std::nothrow) ps_plan_s;
+  if (!plan) return fail(PS_ERR_ARG, "out of host memory");
+  size_t off = 0;
+  plan->inst.resize((size_t)n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    Inst& I = plan->inst[(size_t)i];
+    I.cfg = inst[i];
+    I.N = inst[i].fft_len;
+    I.m = ilog2_exact(I.N);
+    I.m1 = I.m / 2;
+    I.m2 = I.m - I.m1;
+    I.N1 = int64_t(1) << I.m1;
+    I.N2 = int64_t(1) << I.m2;
+    I.C = I.N / 2;
+    I.chunk = inst[i].chunk_frames ? inst[i].chunk_frames : 64;
+    I.fast = inst[i].bits == 8 && inst[i].n_streams == 2 && inst[i].n_pairs == 1 && inst[i].pair_x[0] == 0 &&
+             inst[i].pair_y[0] == 1;
+    build_tables(I);
+    I.off_tw_col = off; off = align_up(off + (size_t)I.N1 * 8);
+    I.off_tw_row = off; off = align_up(off + (size_t)I.N2 * 8);
+    I.off_tw_lo = off; off = align_up(off + (size_t)I.N2 * 8);
+    I.off_win = off; off = align_up(off + (I.win.empty() ? 0 : (size_t)I.N * 4));
+    I.off_taps = off; off = align_up(off + (I.cfg.window == PS_WIN_TAPS ? (size_t)I.cfg.n_taps * 4 : 0));
+    I.off_sumw2 = off; off = align_up(off + 8);
+    I.off_T = off; off = align_up(off + (size_t)I.chunk * (size_t)I.cfg.n_pairs * (size_t)I.N * 8);
+    I.off_acc = off; off = align_up(off + I.acc_bytes());
+    I.end = off;
+  }
+  plan->ws_bytes = off;
+  *out = plan;
+  *workspace_bytes = off;
+  return PS_OK;
+}
+
+ps_status ps_bind(ps_plan_t plan, void* workspace_dev, size_t bytes, void* hip_stream) {
+  ps_status st = check_plan(plan, false);
+  if (st != PS_OK) return st;
+  if (!workspace_dev) return fail(PS_ERR_WORKSPACE, "null workspace");
+  if (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign)
+    return fail(PS_ERR_WORKSPACE, "workspace is not %zu-byte aligned", kAlign);
+  if (bytes < plan->ws_bytes)
+    return fail(PS_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu the plan needs", bytes,
+                plan->ws_bytes);
+  plan->ws = static_cast<char*>(workspace_dev);
+  plan->stream = static_cast<hipStream_t>(hip_stream);
+  plan->bound = false;
+  for (Inst& I : plan->inst) {
+    if ((st = upload(plan, I.off_tw_col, I.tw_col.data(), I.tw_col.size() * 4)) != PS_OK) return st;
+    if ((st = upload(plan, I.off_tw_row, I.tw_row.data(), I.tw_row.size() * 4)) != PS_OK) return st;
+    if ((st = upload(plan, I.off_tw_lo, I.tw_lo.data(), I.tw_lo.size() * 4)) != PS_OK) return st;
+    if ((st = upload(plan, I.off_win, I.win.data(), I.win.size() * 4)) != PS_OK) return st;
+    if ((st = upload(plan, I.off_sumw2, &I.sumw2, 8)) != PS_OK) return st;
+    I.first = true;
+    I.n_frames = 0;
+  }
+  hipError_t e = hipStreamSynchronize(plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "ps_bind synchronise");
+  plan->bound = true;
+  return PS_OK;
+}
+
+ps_status ps_set_window_taps(ps_plan_t plan, int32_t inst, const float* taps_dev) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if ((st = check_inst(plan, inst)) != PS_OK) return st;
+  (void)taps_dev;
+  return fail(PS_ERR_UNSUPPORTED, "learnable window taps are not built in this library");
+}
+
+ps_status ps_reset(ps_plan_t plan) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  for (Inst& I : plan->inst) {
+    I.first = true;
+    I.n_frames = 0;
+  }
+  return PS_OK;
+}
+
+ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if (!packed_dev || !n_samples) return fail(PS_ERR_ARG, "null packed or n_samples array");
+  for (size_t i = 0; i < plan->inst.size(); ++i) {
+    const Inst& I = plan->inst[i];
+    if (n_samples[i] < 0) return fail(PS_ERR_ARG, "instance %zu: negative sample count", i);
+    if (n_samples[i] % I.N)
+      return fail(PS_ERR_SIZE, "instance %zu: %lld samples is not a multiple of fft_len %lld", i,
+                  (long long)n_samples[i], (long long)I.N);
+    if (n_samples[i] > 0 && !packed_dev[i]) return fail(PS_ERR_ARG, "instance %zu: null packed buffer", i);
+    if (n_samples[i] / I.N > (int64_t(1) << 40)) return fail(PS_ERR_SIZE, "instance %zu: too many frames", i);
+  }
+  for (size_t i = 0; i < plan->inst.size(); ++i) {
+    Inst& I = plan->inst[i];
+    const int64_t F = n_samples[i] / I.N;
+    const int64_t frame_bytes = I.N * I.cfg.n_streams * I.cfg.bits / 8;
+    const uint8_t* base = static_cast<const uint8_t*>(packed_dev[i]);
+    for (int64_t f0 = 0; f0 < F; f0 += I.chunk) {
+      const int nf = (int)((F - f0) < I.chunk ? (F - f0) : I.chunk);
+      ps::ColArgs ca{};
+      ca.in = base + f0 * frame_bytes;
+      ca.N = I.N;
+      ca.N2 = (int32_t)I.N2;
+      ca.S = I.cfg.n_streams;
+      ca.P = I.cfg.n_pairs;
+      for (int p = 0; p < 4; ++p) {
+        ca.px[p] = I.cfg.pair_x[p];
+        ca.py[p] = I.cfg.pair_y[p];
+      }
+      const int cols = I.N1 >= 2048 ? 8 : 16;
+      ca.n_colblk = (int32_t)(I.N2 / cols);
+      ca.n_frames = nf;
+      ca.win = I.win.empty() ? nullptr : ws_ptr<float>(plan, I.off_win);
+      ca.tw_col = ws_ptr<float2>(plan, I.off_tw_col);
+      ca.tw_hi = ca.tw_col;
+      ca.tw_lo = ws_ptr<float2>(plan, I.off_tw_lo);
+      ca.lo_bits = I.m2;
+      ca.T = ws_ptr<float2>(plan, I.off_T);
+      hipError_t e = ps::launch_colpass((int)I.N1, I.cfg.bits, I.fast, ca, plan->stream);
+      if (e != hipSuccess) return hip_fail(e, "column pass launch");
+      ps::RowArgs ra{};
+      ra.T = ca.T;
+      ra.N1 = (int32_t)I.N1;
+      ra.P = I.cfg.n_pairs;
+      ra.n_frames = nf;
+      ra.tw_row = ws_ptr<float2>(plan, I.off_tw_row);
+      ra.acc = ws_ptr<double>(plan, I.off_acc);
+      ra.first = I.first ? 1 : 0;
+      e = ps::launch_rowpass((int)I.N2, ra, plan->stream);
+      if (e != hipSuccess) return hip_fail(e, "row pass launch");
+      I.first = false;
+      I.n_frames += nf;
+    }
+  }
+  return PS_OK;
+}
+
+static ps::OutArgs out_args(ps_plan_t plan, const Inst& I) {
+  ps::OutArgs o{};
+  o.acc = ws_ptr<double>(plan, I.off_acc);
+  o.N1 = (int32_t)I.N1;
+  o.N2 = (int32_t)I.N2;
+  o.P = I.cfg.n_pairs;
+  o.C = I.C;
+  return o;
+}
+
+ps_status ps_spectra(ps_plan_t plan, int32_t inst, double* out_dev, int64_t* n_frames) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if ((st = check_inst(plan, inst)) != PS_OK) return st;
+  const Inst& I = plan->inst[(size_t)inst];
+  if (!out_dev) return fail(PS_ERR_ARG, "null output");
+  if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %d has no accumulated frames", inst);
+  ps::OutArgs o = out_args(plan, I);
+  o.spectra = out_dev;
+  hipError_t e = ps::launch_spectra(o, plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "spectra launch");
+  if (n_frames) *n_frames = I.n_frames;
+  return PS_OK;
+}
+
+ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv_dev) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if ((st = check_inst(plan, inst)) != PS_OK) return st;
+  const Inst& I = plan->inst[(size_t)inst];
+  if (!iquv_dev) return fail(PS_ERR_ARG, "null output");
+  if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %d has no accumulated frames", inst);
+  ps::OutArgs o = out_args(plan, I);
+  o.n_frames = (double)I.n_frames;
+  o.sumw2_dev = ws_ptr<double>(plan, I.off_sumw2);
+  o.scale = 1.0 / ((double)I.n_frames * I.sumw2);
+  const double psi = cal ? cal->psi : 0.0;
+  o.cos2psi = std::cos(2.0 * psi);
+  o.sin2psi = std::sin(2.0 * psi);
+  if (cal) {
+    o.gain_x = cal->gain_x;
+    o.gain_y = cal->gain_y;
+    o.dterms = cal->dterms;
+  }
+  o.iquv = iquv_dev;
+  hipError_t e = ps::launch_stokes(o, plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "stokes launch");
+  return PS_OK;
+}
+
+ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed_dev, int64_t n_samples,
+                                const ps_cal* cal, const float* dL_diquv_dev, const ps_cal_grad* grad) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if ((st = check_inst(plan, inst)) != PS_OK) return st;
+  (void)packed_dev; (void)n_samples; (void)cal; (void)dL_diquv_dev; (void)grad;
+  return fail(PS_ERR_UNSUPPORTED, "the adjoint is not built in this library");
+}
+
+ps_status ps_state_bytes(ps_plan_t plan, int32_t inst, size_t* bytes) {
+  ps_status st = check_plan(plan, false);
+  if (st != PS_OK) return st;
+  if ((st = check_inst(plan, inst)) != PS_OK) return st;
+  if (!bytes) return fail(PS_ERR_ARG, "null bytes");
+  *bytes = plan->inst[(size_t)inst].acc_bytes();
+  return PS_OK;
+}
+
+ps_status ps_state_export(ps_plan_t plan, int32_t inst, void* dst_dev, int64_t* n_frames) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if ((st = check_inst(plan, inst)) != PS_OK) return st;
+  const Inst& I = plan->inst[(size_t)inst];
+  if (!dst_dev) return fail(PS_ERR_ARG, "null destination");
+  if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %d has no accumulated frames", inst);
+  hipError_t e = ps::launch_copy(plan->ws + I.off_acc, dst_dev, I.acc_bytes(), plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "state export");
+  if (n_frames) *n_frames = I.n_frames;
+  return PS_OK;
+}
+
+ps_status ps_state_import(ps_plan_t plan, int32_t inst, const void* src_dev, int64_t n_frames) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if ((st = check_inst(plan, inst)) != PS_OK) return st;
+  Inst& I = plan->inst[(size_t)inst];
+  if (!src_dev) return fail(PS_ERR_ARG, "null source");
+  if (n_frames <= 0) return fail(PS_ERR_ARG, "n_frames must be positive");
+  hipError_t e = ps::launch_copy(src_dev, plan->ws + I.off_acc, I.acc_bytes(), plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "state import");
+  I.n_frames = n_frames;
+  I.first = false;
+  return PS_OK;
+}
+
+ps_status ps_unpack(const void* packed_dev, int32_t bits, int32_t n_streams, int64_t n_time, float* out_dev,
+                    void* hip_stream) {
+  if (!packed_dev || !out_dev) return fail(PS_ERR_ARG, "null buffer");
+  if (bits != 2 && bits != 4 && bits != 8 && bits != 32) return fail(PS_ERR_ARG, "bits %d not in {2, 4, 8, 32}", bits);
+  if (n_streams < 1 || n_streams > 8) return fail(PS_ERR_ARG, "n_streams %d not in 1..8", n_streams);
+  if (n_time < 0) return fail(PS_ERR_ARG, "negative n_time");
+  if (n_time == 0) return PS_OK;
+  hipError_t e = ps::launch_unpack(packed_dev, bits, n_streams, n_time, out_dev, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "unpack launch");
+  return PS_OK;
+}
+
+ps_status ps_destroy(ps_plan_t plan) {
+  delete plan;
+  return PS_OK;
+}
+
+const char* ps_status_string(ps_status s) {
+  switch (s) {
+    case PS_OK: return "PS_OK";
+    case PS_ERR_ARG: return "PS_ERR_ARG";
+    case PS_ERR_SIZE: return "PS_ERR_SIZE";
+    case PS_ERR_UNSUPPORTED: return "PS_ERR_UNSUPPORTED";
+    case PS_ERR_STATE: return "PS_ERR_STATE";
+    case PS_ERR_WORKSPACE: return "PS_ERR_WORKSPACE";
+    case PS_ERR_HIP: return "PS_ERR_HIP";
+  }
+  return "PS_UNKNOWN";
+}
+
+const char* ps_last_error(void) { return g_last_error.c_str(); }
+
+int32_t ps_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// polaris_internal.h -- launch descriptors shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace ps {
+
+// Frame transform of length N = N1 * N2 (four-step):
+//   pass A ("column" pass): for each n2, an N1-point DFT over n1 of x[n1*N2 + n2], then the twiddle
+//     W_N^(k1*n2); result T[k1][n2];
+//   pass B ("row" pass): for each k1, an N2-point DFT over n2 of T[k1][n2] -> Z[k1 + N1*k2].
+// The two real streams of a pair travel as one complex sequence z = x + i*y, so one length-N complex
+// transform gives both spectra: X[k] = (Z[k] + conj Z[N-k]) / 2, Y[k] = (Z[k] - conj Z[N-k]) / (2i).
+
+struct ColArgs {
+  const uint8_t* in;        // packed input of the first frame of this launch
+  int64_t N;                // frame length
+  int32_t N2;               // columns
+  int32_t S, P;             // streams, pairs
+  int32_t px[4], py[4];     // pair -> stream
+  int32_t n_colblk;         // column blocks per (frame, pair)
+  int32_t n_frames;         // frames in this launch
+  const float* win;         // window [N] or nullptr (rectangular)
+  const float2* tw_col;     // W_N1^m, m < N1
+  const float2* tw_hi;      // W_N^(m << lo_bits)
+  const float2* tw_lo;      // W_N^m, m < 2^lo_bits
+  int32_t lo_bits;
+  float2* T;                // [n_frames][P][N1][N2]
+};
+
+struct RowArgs {
+  const float2* T;          // [n_frames][P][N1][N2]
+  int32_t N1, P, n_frames;
+  const float2* tw_row;     // W_N2^m, m < N2
+  double* acc;              // [P][N1/2][4][N2]: unit-major accumulators
+  int32_t first;            // 1: start from zero instead of the stored sums
+};
+
+struct OutArgs {
+  const double* acc;        // [P][N1/2][4][N2]
+  int32_t N1, N2, P;
+  int64_t C;
+  // Stokes only
+  double scale;             // 1 / (F * sum w^2) when sumw2_dev == nullptr
+  const double* sumw2_dev;  // device sum of w^2 (taps window) or nullptr
+  double n_frames;
+  const float* gain_x;      // [P][C] complex or nullptr
+  const float* gain_y;
+  const float* dterms;      // [P][4] or nullptr
+  double cos2psi, sin2psi;
+  float* iquv;              // [P][4][C]
+  double* spectra;          // [P][4][C] (raw sums) when producing spectra
+};
+
+hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, hipStream_t s);
+hipError_t launch_rowpass(int N2, const RowArgs& a, hipStream_t s);
+hipError_t launch_stokes(const OutArgs& a, hipStream_t s);
+hipError_t launch_spectra(const OutArgs& a, hipStream_t s);
+hipError_t launch_unpack(const void* packed, int bits, int S, int64_t n_time, float* out, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+}  // namespace ps

@@ -1,0 +1,592 @@
+// polaris_kernels.hip -- gfx950 kernels of the spectrometer path.
+//
+// Path (Sec. 2 and the Fig. 2 caption of Mizuno et al., arXiv 1412.1256): data translation of packed
+// sampler codes, segmentation, FFT, cross products and accumulation; then Eq. 2 (Sec. 2.1) for Stokes.
+//
+// Design for one frame of N = N1 * N2 samples of a polarization pair (x, y):
+//   * the pair is transformed as one complex sequence z = x + i*y (one length-N complex FFT gives both
+//     real spectra);
+//   * column pass: unpack + window straight from the packed bytes into registers, N1-point Stockham
+//     radix-8 passes through LDS over a tile of adjacent columns, four-step twiddle W_N^(k1*n2), one
+//     coalesced write of the FP32 intermediate;
+//   * row pass: one workgroup owns the rows k1 and N1 - k1, whose bins pair up as (k, N - k); it loops
+//     over every frame of the launch, runs the N2-point row transforms in LDS, splits Z into X and Y,
+//     forms XX*, YY*, XY* and keeps the FP64 sums of its channels in registers across frames (frames in
+//     order, so results are independent of how the frames were split over calls);
+//   * the output kernels gather the unit-major accumulators through LDS into natural channel order and
+//     apply the FP64 calibration and Eq. 2.
+// Twiddles come from tables generated on the host in FP64 and rounded once to FP32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "polaris_internal.h"
+
+namespace ps {
+
+// ------------------------------------------------------------------------------------------------
+// complex helpers and small DFTs (forward, exp(-2 pi i n k / R))
+// ------------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// (x + i y) * (-i) = y - i x
+__device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
+
+template <int R>
+struct Dft;
+
+template <>
+struct Dft<2> {
+  static __device__ __forceinline__ void run(float2* v) {
+    const float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <>
+struct Dft<4> {
+  static __device__ __forceinline__ void run(float2* v) {
+    const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const float2 t2 = cadd(v[1], v[3]), t3 = cmul_mi(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <>
+struct Dft<8> {
+  // even/odd split into two 4-point DFTs, odd half rotated by W_8^k
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4>::run(e);
+    Dft<4>::run(o);
+    const float h = 0.70710678118654752440f;  // 1/sqrt(2)
+    const float2 o1 = make_float2((o[1].x + o[1].y) * h, (o[1].y - o[1].x) * h);    // * (1 - i)/sqrt2
+    const float2 o2 = cmul_mi(o[2]);                                                // * (-i)
+    const float2 o3 = make_float2((o[3].y - o[3].x) * h, -(o[3].x + o[3].y) * h);  // * (-1 - i)/sqrt2
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+// ------------------------------------------------------------------------------------------------
+// Stockham schedule for a length-L sequence held as 8 points per thread (L/8 threads per sequence).
+// Pass p has radix R_p (first 2, 4 or 8, then 8) and sub-transform length NS_p = prod_{q<p} R_q.
+// Task j of a radix-R pass reads points j + r*L/R, rotates them by W_(NS*R)^(r*(j mod NS)), applies the
+// R-point DFT and writes them to (j / NS)*NS*R + (j mod NS) + r*NS; after the last pass the sequence is
+// in natural order.  A thread with slot ts runs tasks j = ts + i*L/8, i < 8/R.
+// ------------------------------------------------------------------------------------------------
+
+__host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+
+template <int L>
+struct Sched {
+  static constexpr int M = ilog2c(L);
+  static constexpr int R0 = (M % 3 == 0) ? 8 : ((M % 3 == 1) ? 2 : 4);
+  static constexpr int NPASS = 1 + (M - ilog2c(R0)) / 3;
+  static constexpr int radix(int p) { return p == 0 ? R0 : 8; }
+  static constexpr int ns(int p) { return p == 0 ? 1 : R0 << (3 * (p - 1)); }
+};
+
+template <int L, int R>
+__device__ __forceinline__ int pin(int ts, int i, int r) {
+  return ts + i * (L / 8) + r * (L / R);
+}
+
+template <int L, int R, int NS>
+__device__ __forceinline__ int pout(int ts, int i, int r) {
+  const int j = ts + i * (L / 8);
+  return (j / NS) * NS * R + (j & (NS - 1)) + r * NS;
+}
+
+template <int L, int R, int NS>
+__device__ __forceinline__ void pass_compute(float2 (&v)[8], int ts, const float2* __restrict__ twl) {
+#pragma unroll
+  for (int i = 0; i < 8 / R; ++i) {
+    if constexpr (NS > 1) {
+      const int j = ts + i * (L / 8);
+      const int step = (L / (NS * R)) * (j & (NS - 1));
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], twl[r * step]);
+    }
+    Dft<R>::run(v + i * R);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// launch helpers
+// ------------------------------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Renumber them so that
+// logically adjacent workgroups (which read neighbouring bytes of the same cache lines) share an XCD.
+// The map is a bijection of [0, G) whatever the dispatch order.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  constexpr int X = 8;
+  const int q = G / X, r = G % X, x = b % X, i = b / X;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// ------------------------------------------------------------------------------------------------
+// data translation: level of one packed item (offset-binary 2/4-bit, int8, float32)
+// ------------------------------------------------------------------------------------------------
+
+template <int BITS>
+__device__ __forceinline__ float level_of(const uint8_t* __restrict__ in, int64_t item) {
+  if constexpr (BITS == 8) {
+    return (float)(int)(int8_t)in[item];
+  } else if constexpr (BITS == 32) {
+    return reinterpret_cast<const float*>(in)[item];
+  } else {
+    const int64_t bit = item * BITS;
+    const unsigned code = ((unsigned)in[bit >> 3] >> (unsigned)(bit & 7)) & ((1u << BITS) - 1u);
+    return (float)(2 * (int)code - ((1 << BITS) - 1));
+  }
+}
+
+// two adjacent samples t, t+1 (t even) of streams sx (real part) and sy (imaginary part)
+template <int BITS, bool FAST>
+__device__ __forceinline__ void load_pair2(const uint8_t* __restrict__ in, int S, int sx, int sy, int64_t t,
+                                           float2& z0, float2& z1) {
+  if constexpr (FAST) {  // 8-bit, two streams, pair (0, 1): x0 y0 x1 y1 in one aligned 32-bit word
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(in + 2 * t);
+    z0 = make_float2((float)(int)(int8_t)(w & 0xffu), (float)(int)(int8_t)((w >> 8) & 0xffu));
+    z1 = make_float2((float)(int)(int8_t)((w >> 16) & 0xffu), (float)(int)(int8_t)(w >> 24));
+  } else {
+    const int64_t i0 = t * S, i1 = (t + 1) * S;
+    z0 = make_float2(level_of<BITS>(in, i0 + sx), level_of<BITS>(in, i0 + sy));
+    z1 = make_float2(level_of<BITS>(in, i1 + sx), level_of<BITS>(in, i1 + sy));
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// column pass
+// ------------------------------------------------------------------------------------------------
+
+template <int L, int COLS, int P>
+__device__ __forceinline__ void col_passes(float2 (&v)[2][8], int ts, int cv, const float2* __restrict__ twl,
+                                           float2* __restrict__ tile, const ColArgs& a, int f, int p, int n2b) {
+  using SC = Sched<L>;
+  constexpr int R = SC::radix(P), NS = SC::ns(P);
+  pass_compute<L, R, NS>(v[0], ts, twl);
+  pass_compute<L, R, NS>(v[1], ts, twl);
+  if constexpr (P + 1 < SC::NPASS) {
+#pragma unroll
+    for (int i = 0; i < 8 / R; ++i)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int l = pout<L, R, NS>(ts, i, r);
+        const float2 a0 = v[0][i * R + r], a1 = v[1][i * R + r];
+        *reinterpret_cast<float4*>(tile + l * COLS + cv * 2) = make_float4(a0.x, a0.y, a1.x, a1.y);
+      }
+    __syncthreads();
+    constexpr int R2 = SC::radix(P + 1);
+#pragma unroll
+    for (int i = 0; i < 8 / R2; ++i)
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const float4 q = *reinterpret_cast<const float4*>(tile + pin<L, R2>(ts, i, r) * COLS + cv * 2);
+        v[0][i * R2 + r] = make_float2(q.x, q.y);
+        v[1][i * R2 + r] = make_float2(q.z, q.w);
+      }
+    __syncthreads();
+    col_passes<L, COLS, P + 1>(v, ts, cv, twl, tile, a, f, p, n2b);
+  } else {
+    // k1 = output index; apply W_N^(k1*n2) and write T[f][p][k1][n2 .. n2+1]
+    const int mask = (1 << a.lo_bits) - 1;
+    float2* dst = a.T + ((int64_t)f * a.P + p) * (int64_t)L * a.N2 + n2b;
+#pragma unroll
+    for (int i = 0; i < 8 / R; ++i)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int k1 = pout<L, R, NS>(ts, i, r);
+        const int m0 = k1 * n2b, m1 = m0 + k1;
+        const float2 w0 = cmul(a.tw_hi[m0 >> a.lo_bits], a.tw_lo[m0 & mask]);
+        const float2 w1 = cmul(a.tw_hi[m1 >> a.lo_bits], a.tw_lo[m1 & mask]);
+        const float2 o0 = cmul(v[0][i * R + r], w0), o1 = cmul(v[1][i * R + r], w1);
+        *reinterpret_cast<float4*>(dst + (int64_t)k1 * a.N2) = make_float4(o0.x, o0.y, o1.x, o1.y);
+      }
+  }
+}
+
+template <int L, int COLS, int BITS, bool FAST>
+__global__ void __launch_bounds__(L * COLS / 16) k_colpass(ColArgs a) {
+  constexpr int CPR = COLS / 2;          // two adjacent columns per thread
+  constexpr int NT = L * COLS / 16;
+  using SC = Sched<L>;
+  __shared__ __align__(16) float2 tile[L * COLS];
+  __shared__ float2 twl[L];
+  for (int i = threadIdx.x; i < L; i += NT) twl[i] = a.tw_col[i];
+
+  const int blk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int cb = blk % a.n_colblk;
+  const int rest = blk / a.n_colblk;
+  const int p = rest % a.P;
+  const int f = rest / a.P;
+  const int cv = (int)threadIdx.x % CPR, ts = (int)threadIdx.x / CPR;
+  const int n2b = cb * COLS + cv * 2;
+  const int64_t fbase = (int64_t)f * a.N;
+  const int sx = a.px[p], sy = a.py[p];
+
+  float2 v[2][8];
+  constexpr int R0 = SC::R0;
+#pragma unroll
+  for (int i = 0; i < 8 / R0; ++i)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int n1 = pin<L, R0>(ts, i, r);
+      const int64_t n = (int64_t)n1 * a.N2 + n2b;
+      float2 z0, z1;
+      load_pair2<BITS, FAST>(a.in, a.S, sx, sy, fbase + n, z0, z1);
+      if (a.win) {
+        const float w0 = a.win[n], w1 = a.win[n + 1];
+        z0 = make_float2(z0.x * w0, z0.y * w0);
+        z1 = make_float2(z1.x * w1, z1.y * w1);
+      }
+      v[0][i * R0 + r] = z0;
+      v[1][i * R0 + r] = z1;
+    }
+  __syncthreads();  // twiddle table
+  col_passes<L, COLS, 0>(v, ts, cv, twl, tile, a, f, p, n2b);
+}
+
+// ------------------------------------------------------------------------------------------------
+// row pass + two-for-one split + cross power + FP64 accumulation
+// ------------------------------------------------------------------------------------------------
+
+template <int L, int P>
+__device__ __forceinline__ void row_passes(float2 (&v)[8], int ts, const float2* __restrict__ twl,
+                                           float2* __restrict__ seq) {
+  using SC = Sched<L>;
+  constexpr int R = SC::radix(P), NS = SC::ns(P);
+  pass_compute<L, R, NS>(v, ts, twl);
+#pragma unroll
+  for (int i = 0; i < 8 / R; ++i)
+#pragma unroll
+    for (int r = 0; r < R; ++r) seq[pout<L, R, NS>(ts, i, r)] = v[i * R + r];
+  if constexpr (P + 1 < SC::NPASS) {
+    __syncthreads();
+    constexpr int R2 = SC::radix(P + 1);
+#pragma unroll
+    for (int i = 0; i < 8 / R2; ++i)
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[i * R2 + r] = seq[pin<L, R2>(ts, i, r)];
+    __syncthreads();
+    row_passes<L, P + 1>(v, ts, twl, seq);
+  }
+}
+
+// UB units (row pairs) per workgroup, FB frames in flight; one thread per 8 points of a row.
+template <int L, int UB, int FB>
+__global__ void __launch_bounds__(UB * FB * L / 4) k_rowpass(RowArgs a) {
+  constexpr int NT = UB * FB * L / 4;
+  constexpr int TPS = L / 8;              // threads per row sequence
+  constexpr int SPT = (UB * L) / NT;      // channel slots per thread (= 4 / FB)
+  using SC = Sched<L>;
+  __shared__ __align__(16) float2 buf[UB * FB * 2 * L];
+  __shared__ float2 twl[L];
+  const int tid = (int)threadIdx.x;
+  for (int i = tid; i < L; i += NT) twl[i] = a.tw_row[i];
+
+  const int p = (int)blockIdx.y;
+  const int U = a.N1 / 2;
+  // transform role of this thread
+  const int ts = tid % TPS, sq = tid / TPS;
+  const int rr = sq & 1, fs = (sq >> 1) % FB, ub = (sq >> 1) / FB;
+  const int u = (int)blockIdx.x * UB + ub;
+  const int row = (u == 0) ? (rr ? a.N1 / 2 : 0) : (rr ? a.N1 - u : u);
+
+  // channel role: slot s of unit ubc; slots [0, L/2) are the first row's channels, [L/2, L) the second's
+  double sxx[SPT], syy[SPT], sxr[SPT], sxi[SPT];
+  double* accp[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int id = tid + q * NT;
+    const int ubc = id / L, s = id % L;
+    const int uc = (int)blockIdx.x * UB + ubc;
+    accp[q] = a.acc + ((int64_t)(p * U + uc) * 4) * L + s;
+    if (a.first) {
+      sxx[q] = syy[q] = sxr[q] = sxi[q] = 0.0;
+    } else {
+      sxx[q] = accp[q][0];
+      syy[q] = accp[q][L];
+      sxr[q] = accp[q][2 * L];
+      sxi[q] = accp[q][3 * L];
+    }
+  }
+  __syncthreads();  // twiddle table
+
+  constexpr int R0 = SC::R0;
+  for (int f0 = 0; f0 < a.n_frames; f0 += FB) {
+    const int f = f0 + fs;
+    float2 v[8];
+    if (f < a.n_frames) {
+      const float2* src = a.T + (((int64_t)f * a.P + p) * a.N1 + row) * (int64_t)L;
+#pragma unroll
+      for (int i = 0; i < 8 / R0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[i * R0 + r] = src[pin<L, R0>(ts, i, r)];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = make_float2(0.f, 0.f);
+    }
+    row_passes<L, 0>(v, ts, twl, buf + sq * L);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int id = tid + q * NT;
+      const int ubc = id / L, s = id % L;
+      const int uc = (int)blockIdx.x * UB + ubc;
+      const int half = s / (L / 2), k2 = s % (L / 2);
+      // bin (row, k2) pairs with bin N - k: rows k1 and N1 - k1 swap, k2 -> N2 - 1 - k2; row 0 -> N2 - k2
+      const int phalf = (uc == 0) ? half : 1 - half;
+      const int pk2 = (uc == 0 && half == 0) ? ((L - k2) & (L - 1)) : (L - 1 - k2);
+      for (int g = 0; g < FB; ++g) {
+        if (f0 + g >= a.n_frames) break;
+        const float2* fr = buf + ((ubc * FB + g) * 2) * L;
+        const float2 A = fr[half * L + k2];
+        const float2 B = fr[phalf * L + pk2];
+        // X = (A + conj B)/2, Y = (A - conj B)/(2i)
+        const float2 sm = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
+        const float2 df = make_float2(0.5f * (A.x - B.x), 0.5f * (A.y + B.y));
+        const float xx = sm.x * sm.x + sm.y * sm.y;
+        const float yy = df.x * df.x + df.y * df.y;
+        const float qr = sm.x * df.x + sm.y * df.y;   // Re(sm conj df)
+        const float qi = sm.y * df.x - sm.x * df.y;   // Im(sm conj df)
+        sxx[q] += (double)xx;
+        syy[q] += (double)yy;
+        sxr[q] += (double)(-qi);  // XY* = i * sm * conj(df)
+        sxi[q] += (double)qr;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    accp[q][0] = sxx[q];
+    accp[q][L] = syy[q];
+    accp[q][2 * L] = sxr[q];
+    accp[q][3 * L] = sxi[q];
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// output: accumulators -> natural channel order (raw spectra, or calibrated Stokes by Eq. 2)
+// ------------------------------------------------------------------------------------------------
+
+struct cd {
+  double x, y;
+};
+__device__ __forceinline__ cd cdm(cd a, cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ cd cda(cd a, cd b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cd cdc(cd a) { return {a.x, -a.y}; }
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+
+template <bool STOKES>
+__global__ void __launch_bounds__(256) k_output(OutArgs a) {
+  constexpr int RT = 32, KT = 16;
+  __shared__ double t[4][RT][KT + 1];
+  const int L = a.N2, U = a.N1 / 2;
+  const int rt = RT < a.N1 ? RT : a.N1;
+  const int kt = KT < L / 2 ? KT : L / 2;
+  const int r0 = (int)blockIdx.x * rt, k20 = (int)blockIdx.y * kt, p = (int)blockIdx.z;
+  for (int e = (int)threadIdx.x; e < rt * kt; e += 256) {
+    const int rl = e / kt, kk = e % kt;
+    const int r = r0 + rl, k2 = k20 + kk;
+    int u, half;
+    if (r == 0) { u = 0; half = 0; }
+    else if (2 * r == a.N1) { u = 0; half = 1; }
+    else if (2 * r < a.N1) { u = r; half = 0; }
+    else { u = a.N1 - r; half = 1; }
+    const double* src = a.acc + ((int64_t)(p * U + u) * 4) * L + half * (L / 2) + k2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q][rl][kk] = src[(int64_t)q * L];
+  }
+  __syncthreads();
+  double scale = a.scale;
+  if (STOKES && a.sumw2_dev) scale = 1.0 / (a.n_frames * a.sumw2_dev[0]);
+  for (int e = (int)threadIdx.x; e < rt * kt; e += 256) {
+    const int kk = e / rt, rl = e % rt;
+    const int64_t k = (int64_t)(k20 + kk) * a.N1 + r0 + rl;
+    const double axx = t[0][rl][kk], ayy = t[1][rl][kk], axr = t[2][rl][kk], axi = t[3][rl][kk];
+    if constexpr (!STOKES) {
+      double* o = a.spectra + (int64_t)p * 4 * a.C + k;
+      o[0] = axx;
+      o[a.C] = ayy;
+      o[2 * a.C] = axr;
+      o[3 * a.C] = axi;
+    } else {
+      // normalised coherency M
+      const cd mxx = {axx * scale, 0.0}, myy = {ayy * scale, 0.0};
+      const cd mxy = {axr * scale, axi * scale}, myx = cdc(mxy);
+      // E = G J = [[gx, gx dx], [gy dy, gy]];  Fi = E^-1
+      cd gx = {1.0, 0.0}, gy = {1.0, 0.0}, dx = {0.0, 0.0}, dy = {0.0, 0.0};
+      if (a.gain_x) gx = {(double)a.gain_x[2 * ((int64_t)p * a.C + k)], (double)a.gain_x[2 * ((int64_t)p * a.C + k) + 1]};
+      if (a.gain_y) gy = {(double)a.gain_y[2 * ((int64_t)p * a.C + k)], (double)a.gain_y[2 * ((int64_t)p * a.C + k) + 1]};
+      if (a.dterms) {
+        dx = {(double)a.dterms[4 * p + 0], (double)a.dterms[4 * p + 1]};
+        dy = {(double)a.dterms[4 * p + 2], (double)a.dterms[4 * p + 3]};
+      }
+      const cd e00 = gx, e01 = cdm(gx, dx), e10 = cdm(gy, dy), e11 = gy;
+      const cd det = cda(cdm(e00, e11), {-cdm(e01, e10).x, -cdm(e01, e10).y});
+      const cd f00 = cdiv(e11, det), f01 = cdiv({-e01.x, -e01.y}, det);
+      const cd f10 = cdiv({-e10.x, -e10.y}, det), f11 = cdiv(e00, det);
+      // T = Fi M ; C = T Fi^H
+      const cd t00 = cda(cdm(f00, mxx), cdm(f01, myx)), t01 = cda(cdm(f00, mxy), cdm(f01, myy));
+      const cd t10 = cda(cdm(f10, mxx), cdm(f11, myx)), t11 = cda(cdm(f10, mxy), cdm(f11, myy));
+      const cd c00 = cda(cdm(t00, cdc(f00)), cdm(t01, cdc(f01)));
+      const cd c01 = cda(cdm(t00, cdc(f10)), cdm(t01, cdc(f11)));
+      const cd c10 = cda(cdm(t10, cdc(f00)), cdm(t11, cdc(f01)));
+      const cd c11 = cda(cdm(t10, cdc(f10)), cdm(t11, cdc(f11)));
+      // Eq. 2 rows acting on [C_xx, C_xy, C_yx, C_yy]
+      const double c2 = a.cos2psi, s2 = a.sin2psi;
+      const double I = 0.5 * (c00.x + c11.x);
+      const double Q = 0.5 * (c2 * c00.x - s2 * c01.x - s2 * c10.x - c2 * c11.x);
+      const double Uq = 0.5 * (s2 * c00.x + c2 * c01.x + c2 * c10.x - s2 * c11.x);
+      const double V = 0.5 * (c01.y - c10.y);  // Re(-i C_xy + i C_yx)
+      float* o = a.iquv + (int64_t)p * 4 * a.C + k;
+      o[0] = (float)I;
+      o[a.C] = (float)Q;
+      o[2 * a.C] = (float)Uq;
+      o[3 * a.C] = (float)V;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// stand-alone data translation and a plain device copy
+// ------------------------------------------------------------------------------------------------
+
+template <int BITS>
+__global__ void __launch_bounds__(256) k_unpack(const uint8_t* __restrict__ in, int S, int64_t n_time,
+                                                float* __restrict__ out) {
+  const int64_t n_items = n_time * S;
+  for (int64_t item = (int64_t)blockIdx.x * 256 + threadIdx.x; item < n_items; item += (int64_t)gridDim.x * 256) {
+    const int64_t t = item / S;
+    const int s = (int)(item - t * S);
+    out[(int64_t)s * n_time + t] = level_of<BITS>(in, item);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_copy_words(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                    int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------------
+
+template <int L, int COLS>
+static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)(a.n_frames * a.P * a.n_colblk)), block(L * COLS / 16);
+  switch (bits) {
+    case 2: hipLaunchKernelGGL((k_colpass<L, COLS, 2, false>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_colpass<L, COLS, 4, false>), grid, block, 0, s, a); break;
+    case 8:
+      if (fast) hipLaunchKernelGGL((k_colpass<L, COLS, 8, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_colpass<L, COLS, 8, false>), grid, block, 0, s, a);
+      break;
+    case 32: hipLaunchKernelGGL((k_colpass<L, COLS, 32, false>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int colpass_cols(int N1) { return N1 >= 2048 ? 8 : 16; }
+
+hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, hipStream_t s) {
+  switch (N1) {
+    case 16: return colpass_bits<16, 16>(bits, fast, a, s);
+    case 32: return colpass_bits<32, 16>(bits, fast, a, s);
+    case 64: return colpass_bits<64, 16>(bits, fast, a, s);
+    case 128: return colpass_bits<128, 16>(bits, fast, a, s);
+    case 256: return colpass_bits<256, 16>(bits, fast, a, s);
+    case 512: return colpass_bits<512, 16>(bits, fast, a, s);
+    case 1024: return colpass_bits<1024, 16>(bits, fast, a, s);
+    case 2048: return colpass_bits<2048, 8>(bits, fast, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int L, int UB, int FB>
+static hipError_t rowpass_launch(const RowArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P), block(UB * FB * L / 4);
+  hipLaunchKernelGGL((k_rowpass<L, UB, FB>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+int rowpass_units_per_block(int N2) { return N2 >= 128 ? 1 : 128 / N2; }
+
+hipError_t launch_rowpass(int N2, const RowArgs& a, hipStream_t s) {
+  switch (N2) {
+    case 16: return rowpass_launch<16, 8, 4>(a, s);
+    case 32: return rowpass_launch<32, 4, 4>(a, s);
+    case 64: return rowpass_launch<64, 2, 4>(a, s);
+    case 128: return rowpass_launch<128, 1, 4>(a, s);
+    case 256: return rowpass_launch<256, 1, 4>(a, s);
+    case 512: return rowpass_launch<512, 1, 4>(a, s);
+    case 1024: return rowpass_launch<1024, 1, 4>(a, s);
+    case 2048: return rowpass_launch<2048, 1, 2>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static dim3 output_grid(const OutArgs& a) {
+  const int rt = a.N1 < 32 ? a.N1 : 32;
+  const int kt = a.N2 / 2 < 16 ? a.N2 / 2 : 16;
+  return dim3((unsigned)(a.N1 / rt), (unsigned)(a.N2 / 2 / kt), (unsigned)a.P);
+}
+
+hipError_t launch_stokes(const OutArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_output<true>), output_grid(a), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_spectra(const OutArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_output<false>), output_grid(a), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const void* packed, int bits, int S, int64_t n_time, float* out, hipStream_t s) {
+  const int64_t items = n_time * S;
+  int64_t blocks = (items + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  const uint8_t* in = static_cast<const uint8_t*>(packed);
+  switch (bits) {
+    case 2: hipLaunchKernelGGL(k_unpack<2>, dim3((unsigned)blocks), dim3(256), 0, s, in, S, n_time, out); break;
+    case 4: hipLaunchKernelGGL(k_unpack<4>, dim3((unsigned)blocks), dim3(256), 0, s, in, S, n_time, out); break;
+    case 8: hipLaunchKernelGGL(k_unpack<8>, dim3((unsigned)blocks), dim3(256), 0, s, in, S, n_time, out); break;
+    case 32: hipLaunchKernelGGL(k_unpack<32>, dim3((unsigned)blocks), dim3(256), 0, s, in, S, n_time, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 4);
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_copy_words, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const uint32_t*>(src),
+                     static_cast<uint32_t*>(dst), n);
+  return hipGetLastError();
+}
+
+}  // namespace ps

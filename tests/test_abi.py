@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI: exported symbols and argument validation (no GPU work)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1412_1256_amd as pk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "polaris.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ps_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported():
+    names = declared_functions()
+    assert "ps_plan" in names and "ps_accumulate" in names and "ps_stokes" in names
+    assert "ps_calibrate_backward" in names
+    L = C.CDLL(pk.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_instance_struct_layout_matches_header():
+    assert C.sizeof(pk._Instance) == 80
+    assert pk._Instance.fft_len.offset == 64
+    assert C.sizeof(pk._Cal) == 32
+
+
+def _plan(**kw):
+    base = dict(fft_len=1024, bits=2)
+    base.update(kw)
+    inst = pk.Instance(**base)
+    arr = (pk._Instance * 1)(inst.to_c())
+    h = C.c_void_p()
+    n = C.c_size_t()
+    st = pk.lib().ps_plan(arr, 1, C.byref(h), C.byref(n))
+    return st, h, n.value
+
+
+def test_valid_plan_reports_aligned_workspace():
+    st, h, n = _plan()
+    assert st == 0 and n > 0 and n % 256 == 0
+    # accumulators (32 bytes per channel and pair) plus the 64-frame FP32 inter-pass buffer fit inside
+    assert n >= 64 * 1024 * 8 + 512 * 32
+    assert pk.lib().ps_destroy(h) == 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(bits=3), "PS_ERR_ARG"),
+    (dict(fft_len=1000), "PS_ERR_ARG"),
+    (dict(fft_len=64), "PS_ERR_UNSUPPORTED"),
+    (dict(fft_len=1 << 23), "PS_ERR_UNSUPPORTED"),
+    (dict(pairs=((0, 2),)), "PS_ERR_ARG"),
+    (dict(n_streams=0), "PS_ERR_ARG"),
+    (dict(window="taps", n_taps=1), "PS_ERR_ARG"),
+    (dict(window=7), "PS_ERR_ARG"),
+    (dict(chunk_frames=-1), "PS_ERR_ARG"),
+])
+def test_plan_rejects_bad_instances(kw, code):
+    st, h, n = _plan(**kw)
+    assert pk.STATUS[st] == code, pk.lib().ps_last_error()
+    assert not h.value
+    assert len(pk.lib().ps_last_error()) > 0
+
+
+def test_calls_before_bind_are_state_errors():
+    st, h, n = _plan()
+    assert st == 0
+    L = pk.lib()
+    assert pk.STATUS[L.ps_reset(h)] == "PS_ERR_STATE"
+    ptrs = (C.c_void_p * 1)(None)
+    ns = (C.c_int64 * 1)(0)
+    assert pk.STATUS[L.ps_accumulate(h, ptrs, ns)] == "PS_ERR_STATE"
+    assert pk.STATUS[L.ps_stokes(h, 0, None, C.c_void_p(16))] == "PS_ERR_STATE"
+    L.ps_destroy(h)
+
+
+def test_bind_rejects_bad_workspace_before_any_device_call():
+    st, h, n = _plan()
+    L = pk.lib()
+    assert pk.STATUS[L.ps_bind(h, None, n, None)] == "PS_ERR_WORKSPACE"
+    assert pk.STATUS[L.ps_bind(h, C.c_void_p(4096 + 8), n, None)] == "PS_ERR_WORKSPACE"
+    assert pk.STATUS[L.ps_bind(h, C.c_void_p(4096), n - 256, None)] == "PS_ERR_WORKSPACE"
+    L.ps_destroy(h)
+
+
+def test_status_strings():
+    L = pk.lib()
+    for code, name in pk.STATUS.items():
+        assert L.ps_status_string(code).decode() == name
+
+
+def test_unpack_argument_errors():
+    L = pk.lib()
+    assert pk.STATUS[L.ps_unpack(None, 8, 2, 10, C.c_void_p(16), None)] == "PS_ERR_ARG"
+    assert pk.STATUS[L.ps_unpack(C.c_void_p(16), 5, 2, 10, C.c_void_p(16), None)] == "PS_ERR_ARG"
+    assert pk.STATUS[L.ps_unpack(C.c_void_p(16), 8, 9, 10, C.c_void_p(16), None)] == "PS_ERR_ARG"
+    assert L.ps_unpack(C.c_void_p(16), 8, 2, 0, C.c_void_p(16), None) == 0  # empty: nothing enqueued
