@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark of the spectrometer hot path on one MI355X.
+
+One step = one whole integration of the paper-shaped workload: reset, accumulate 61 frames of two int8
+streams (16 Msps, 2^18-point frames: 0.999424 s of data), then calibrated Stokes.  Input is resident in
+HBM before timing starts.  Prints one JSON line with the throughput (input Gsamples/s), the real-time
+factor, the per-kernel roofline of the dominant kernel (timed live with hipEvents on the plan's stream),
+and the FP64 CPU oracle timed on the host on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+  python bench.py --copy-probe BYTES   # plain device copy, for calibrating HBM byte counters
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "input Gsamples/s (×real-time) FFT+Stokes at 2^18 pts; fwd+bwd vs plain"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+SAMPLE_RATE = 16e6             # per stream
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-reps", type=int, default=5, help="oracle repetitions of the whole integration")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
+    return ap.parse_args()
+
+
+def copy_probe(nbytes: int, steps: int):
+    import torch
+    dev = torch.device("cuda:0")
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    print(json.dumps({"copy_probe_bytes": nbytes, "read_bytes": nbytes, "write_bytes": nbytes,
+                      "ms": dt * 1e3, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}), flush=True)
+
+
+def kernel_bytes(kind: str, inst: dict, frames: int) -> float:
+    """Algorithmic HBM bytes of one launch of a kernel kind over `frames` frames."""
+    N, S, P, b = inst["fft_len"], inst["n_streams"], len(inst["pairs"]), inst["bits"]
+    C = N // 2
+    if kind == "colpass":   # packed input once + FP32 complex intermediate written once
+        win = 0 if inst["window"] == "rect" else N * 4
+        return frames * N * S * b / 8 + frames * P * N * 8 + win
+    if kind == "rowpass":   # intermediate read once + FP64 accumulators written (first call: no read)
+        return frames * P * N * 8 + P * C * 32
+    if kind == "stokes":    # FP64 accumulators read + FP32 I, Q, U, V written
+        return P * C * 32 + P * C * 16
+    if kind == "spectra":
+        return P * C * 32 * 2
+    return float("nan")
+
+
+def cpu_baseline(inst: dict, reps: int):
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    # one untimed run builds/loads the oracle
+    acc, nf, s2, _ = oracle.run_instance(inst, nthreads=threads)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        acc, nf, s2, _ = oracle.run_instance(inst, nthreads=threads)
+        oracle.stokes(acc, nf, s2, psi=0.25)
+    dt = time.perf_counter() - t0
+    samples = inst["n_samples"] * inst["n_streams"] * reps
+    return {"value": samples / dt / 1e9, "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} full integrations of the paper-shaped workload ({inst['n_frames']} frames of "
+                      f"2x2^18 int8 samples each), FP64 radix-2 oracle incl. Stokes",
+            "seconds": dt, "x_realtime": reps * inst["n_samples"] / SAMPLE_RATE / dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path: "
+              "each GPU would run its own pairs/instances independently (see the sharding notes).", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe, args.steps)
+        return
+
+    import torch
+
+    import paper_1412_1256_amd as pk
+    import synth
+
+    pk.lib()  # fail loudly when the HIP library is missing
+    dev = torch.device("cuda:0")
+    inst = synth.make_paper()
+    N, S, F = inst["fft_len"], inst["n_streams"], inst["n_frames"]
+    samples = F * N * S
+    packed = torch.from_numpy(inst["packed"]).to(dev)
+    plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev)
+    iquv = torch.empty((1, 4, N // 2), dtype=torch.float32, device=dev)
+
+    def step():
+        plan.reset()
+        plan.accumulate(packed)
+        plan.stokes(psi=0.25, out=iquv)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize(dev)
+    dt = (time.perf_counter() - t0) / args.steps
+
+    # per-kernel durations, hipEvents around each launch on the plan's stream
+    plan.profile_enable(True)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize(dev)
+    dt_prof = (time.perf_counter() - t0) / args.steps
+    prof = plan.profile_read()
+    plan.profile_enable(False)
+    kernels = {}
+    for k, (ms, n) in prof.items():
+        avg_s = ms / n / 1e3
+        nbytes = kernel_bytes(k, inst, F)
+        kernels[k] = {"launches_per_step": n / args.steps, "avg_us": avg_s * 1e6,
+                      "alg_bytes": nbytes, "GBps": nbytes / avg_s / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches_per_step"])
+    kd = kernels[dom]
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": None}
+
+    value = samples / dt / 1e9
+    nominal_flop = S * F * 5 * N * math.log2(N)      # 5 N log2 N per N-point real frame per stream
+    path_bytes = sum(kernel_bytes(k, inst, F) for k in ("colpass", "rowpass", "stokes"))
+    out = {
+        "metric": METRIC, "value": value, "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "paper-shaped integration: 2 int8 streams at 16 Msps, 2^18-pt rect frames, "
+                               "61 frames (0.999424 s), FP32 passes + FP64 accumulation, Stokes",
+                   "n_streams": S, "bits": 8, "fft_len": N, "frames": F, "samples_per_step": samples},
+        "x_realtime": (F * N / SAMPLE_RATE) / dt,
+        "fft_tflops_nominal_5NlogN": nominal_flop / dt / 1e12,
+        "path_alg_bytes_per_step": path_bytes,
+        "path_GBps": path_bytes / dt / 1e9,
+        "path_frac_hbm": path_bytes / dt / 1e9 / HBM_PEAK_GBS,
+        "ms_per_step_with_kernel_events": dt_prof * 1e3,
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_reps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

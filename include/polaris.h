@@ -61,7 +61,7 @@ typedef struct ps_plan_s* ps_plan_t;
  *   bits        2 or 4 (offset-binary codes c -> level 2c - (2^b - 1)), 8 (two's-complement int8) or
  *               32 (little-endian float32, a test format).  Item t*S + s of the buffer sits at bit
  *               offset (t*S + s)*bits, least significant bits first.
- *   fft_len     N, a power of two, 2^6 .. 2^22; channels C = N/2; one segment = N samples per stream.
+ *   fft_len     N, a power of two, 2^8 .. 2^22; channels C = N/2; one segment = N samples per stream.
  *   window      PS_WIN_RECT, PS_WIN_HANN (periodic) or PS_WIN_TAPS (n_taps control points, linear
  *               interpolation at u = n (n_taps - 1)/(N - 1); all ones until ps_set_window_taps).
  *   precision   PS_PREC_FP32 (the only value accepted by this build's plain path).
@@ -161,6 +161,23 @@ ps_status ps_destroy(ps_plan_t plan);
 
 const char* ps_status_string(ps_status status);
 const char* ps_last_error(void);
+
+/* Per-kernel timing for measurement.  While enabled, every kernel a plan launches is bracketed by two
+ * hipEvents recorded on the bound stream (up to 16384 launches are kept; later ones are not timed).
+ * ps_profile_read waits for the recorded events, returns the summed milliseconds and launch counts per
+ * kernel kind (arrays of PS_KERNEL_COUNT entries) and clears the record.  Keep profiling disabled while a
+ * hipGraph is being captured. */
+enum {
+  PS_KERNEL_COLPASS = 0,   /* unpack + window + column transforms + four-step twiddle */
+  PS_KERNEL_ROWPASS = 1,   /* row transforms + cross power + accumulation */
+  PS_KERNEL_STOKES = 2,    /* calibration + Eq. 2 */
+  PS_KERNEL_SPECTRA = 3,   /* raw spectra in channel order */
+  PS_KERNEL_BACKWARD = 4,  /* adjoint kernels */
+  PS_KERNEL_OTHER = 5,
+  PS_KERNEL_COUNT = 8
+};
+ps_status ps_profile_enable(ps_plan_t plan, int32_t enable);
+ps_status ps_profile_read(ps_plan_t plan, double* ms_total, int64_t* launches);
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int32_t ps_version(void);

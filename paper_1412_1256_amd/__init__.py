@@ -75,6 +75,8 @@ def lib():
             "ps_status_string": [C.c_int],
             "ps_last_error": [],
             "ps_version": [],
+            "ps_profile_enable": [vp, i32],
+            "ps_profile_read": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -271,6 +273,19 @@ class Plan:
 
     def state_import(self, buf, n_frames: int, inst: int = 0):
         _check(lib().ps_state_import(self._h, inst, _ptr(buf), int(n_frames)))
+
+    KERNELS = ("colpass", "rowpass", "stokes", "spectra", "backward", "other")
+
+    def profile_enable(self, on: bool = True):
+        """Bracket every kernel this plan launches with hipEvents on its stream (measurement only)."""
+        _check(lib().ps_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel: (total_ms, launches)} since the last read; waits for the recorded events."""
+        ms = (C.c_double * 8)()
+        n = (C.c_int64 * 8)()
+        _check(lib().ps_profile_read(self._h, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(self.KERNELS) if n[i]}
 
     def _as_f32(self, t):
         if t is None:

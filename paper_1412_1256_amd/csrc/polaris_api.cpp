@@ -80,6 +80,14 @@ struct ps_plan_s {
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
+  // per-kernel timing (measurement only)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;       // pairs (start, stop)
+  std::vector<int> ev_kind;         // kernel kind of each recorded pair
+  size_t ev_used = 0;
+  ~ps_plan_s() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -152,6 +160,23 @@ ps_status check_inst(ps_plan_t plan, int32_t i) {
 template <class T>
 T* ws_ptr(ps_plan_t plan, size_t off) {
   return reinterpret_cast<T*>(plan->ws + off);
+}
+
+constexpr size_t kMaxTimed = 16384;
+
+// Launch f() on the plan's stream; while profiling, bracket it with a pair of events.
+template <class F>
+hipError_t timed(ps_plan_t plan, int kind, F&& f) {
+  if (!plan->prof || plan->ev_used >= plan->ev_kind.size()) return f();
+  hipEvent_t a = plan->ev[2 * plan->ev_used], b = plan->ev[2 * plan->ev_used + 1];
+  hipError_t e = hipEventRecord(a, plan->stream);
+  if (e != hipSuccess) return e;
+  e = f();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, plan->stream);
+  if (e != hipSuccess) return e;
+  plan->ev_kind[plan->ev_used++] = kind;
+  return hipSuccess;
 }
 
 ps_status upload(ps_plan_t plan, size_t off, const void* src, size_t bytes) {
@@ -282,16 +307,25 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
         ca.px[p] = I.cfg.pair_x[p];
         ca.py[p] = I.cfg.pair_y[p];
       }
-      const int cols = I.N1 >= 2048 ? 8 : 16;
+      const int cols = ps::colpass_cols((int)I.N1);
       ca.n_colblk = (int32_t)(I.N2 / cols);
       ca.n_frames = nf;
+      {
+        // about two workgroups per CU: frames per workgroup so that groups x pairs x blocks ~ 512
+        const int64_t per_frame = (int64_t)ca.n_colblk * ca.P;
+        int64_t groups = (512 + per_frame / 2) / per_frame;
+        if (groups < 1) groups = 1;
+        if (groups > nf) groups = nf;
+        ca.frames_per_block = (int32_t)((nf + groups - 1) / groups);
+      }
       ca.win = I.win.empty() ? nullptr : ws_ptr<float>(plan, I.off_win);
       ca.tw_col = ws_ptr<float2>(plan, I.off_tw_col);
       ca.tw_hi = ca.tw_col;
       ca.tw_lo = ws_ptr<float2>(plan, I.off_tw_lo);
       ca.lo_bits = I.m2;
       ca.T = ws_ptr<float2>(plan, I.off_T);
-      hipError_t e = ps::launch_colpass((int)I.N1, I.cfg.bits, I.fast, ca, plan->stream);
+      hipError_t e = timed(plan, PS_KERNEL_COLPASS,
+                           [&] { return ps::launch_colpass((int)I.N1, I.cfg.bits, I.fast, ca, plan->stream); });
       if (e != hipSuccess) return hip_fail(e, "column pass launch");
       ps::RowArgs ra{};
       ra.T = ca.T;
@@ -301,7 +335,7 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
       ra.tw_row = ws_ptr<float2>(plan, I.off_tw_row);
       ra.acc = ws_ptr<double>(plan, I.off_acc);
       ra.first = I.first ? 1 : 0;
-      e = ps::launch_rowpass((int)I.N2, ra, plan->stream);
+      e = timed(plan, PS_KERNEL_ROWPASS, [&] { return ps::launch_rowpass((int)I.N2, ra, plan->stream); });
       if (e != hipSuccess) return hip_fail(e, "row pass launch");
       I.first = false;
       I.n_frames += nf;
@@ -329,7 +363,7 @@ ps_status ps_spectra(ps_plan_t plan, int32_t inst, double* out_dev, int64_t* n_f
   if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %d has no accumulated frames", inst);
   ps::OutArgs o = out_args(plan, I);
   o.spectra = out_dev;
-  hipError_t e = ps::launch_spectra(o, plan->stream);
+  hipError_t e = timed(plan, PS_KERNEL_SPECTRA, [&] { return ps::launch_spectra(o, plan->stream); });
   if (e != hipSuccess) return hip_fail(e, "spectra launch");
   if (n_frames) *n_frames = I.n_frames;
   return PS_OK;
@@ -355,7 +389,7 @@ ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv
     o.dterms = cal->dterms;
   }
   o.iquv = iquv_dev;
-  hipError_t e = ps::launch_stokes(o, plan->stream);
+  hipError_t e = timed(plan, PS_KERNEL_STOKES, [&] { return ps::launch_stokes(o, plan->stream); });
   if (e != hipSuccess) return hip_fail(e, "stokes launch");
   return PS_OK;
 }
@@ -414,6 +448,44 @@ ps_status ps_unpack(const void* packed_dev, int32_t bits, int32_t n_streams, int
   if (n_time == 0) return PS_OK;
   hipError_t e = ps::launch_unpack(packed_dev, bits, n_streams, n_time, out_dev, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "unpack launch");
+  return PS_OK;
+}
+
+ps_status ps_profile_enable(ps_plan_t plan, int32_t enable) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if (enable && plan->ev.empty()) {
+    plan->ev.resize(2 * kMaxTimed, nullptr);
+    for (size_t i = 0; i < plan->ev.size(); ++i) {
+      hipError_t e = hipEventCreate(&plan->ev[i]);
+      if (e != hipSuccess) return hip_fail(e, "profiling event create");
+    }
+    plan->ev_kind.assign(kMaxTimed, 0);
+  }
+  plan->prof = enable != 0;
+  return PS_OK;
+}
+
+ps_status ps_profile_read(ps_plan_t plan, double* ms_total, int64_t* launches) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if (!ms_total || !launches) return fail(PS_ERR_ARG, "null output");
+  for (int k = 0; k < PS_KERNEL_COUNT; ++k) {
+    ms_total[k] = 0.0;
+    launches[k] = 0;
+  }
+  if (plan->ev_used) {
+    hipError_t e = hipEventSynchronize(plan->ev[2 * plan->ev_used - 1]);
+    if (e != hipSuccess) return hip_fail(e, "profiling event wait");
+  }
+  for (size_t i = 0; i < plan->ev_used; ++i) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, plan->ev[2 * i], plan->ev[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "profiling elapsed time");
+    ms_total[plan->ev_kind[i]] += (double)ms;
+    launches[plan->ev_kind[i]] += 1;
+  }
+  plan->ev_used = 0;
   return PS_OK;
 }
 

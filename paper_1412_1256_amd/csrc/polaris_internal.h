@@ -21,6 +21,7 @@ struct ColArgs {
   int32_t px[4], py[4];     // pair -> stream
   int32_t n_colblk;         // column blocks per (frame, pair)
   int32_t n_frames;         // frames in this launch
+  int32_t frames_per_block; // frames looped over by one workgroup
   const float* win;         // window [N] or nullptr (rectangular)
   const float2* tw_col;     // W_N1^m, m < N1
   const float2* tw_hi;      // W_N^(m << lo_bits)
@@ -33,7 +34,7 @@ struct RowArgs {
   const float2* T;          // [n_frames][P][N1][N2]
   int32_t N1, P, n_frames;
   const float2* tw_row;     // W_N2^m, m < N2
-  double* acc;              // [P][N1/2][4][N2]: unit-major accumulators
+  double* acc;              // [P][N1/2][4][N2]: unit-major accumulators of 4 XX*, 4 YY*, 4 XY*
   int32_t first;            // 1: start from zero instead of the stored sums
 };
 
@@ -53,6 +54,7 @@ struct OutArgs {
   double* spectra;          // [P][4][C] (raw sums) when producing spectra
 };
 
+int colpass_cols(int N1);
 hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, hipStream_t s);
 hipError_t launch_rowpass(int N2, const RowArgs& a, hipStream_t s);
 hipError_t launch_stokes(const OutArgs& a, hipStream_t s);

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "polaris_internal.h"
 
 namespace ps {
@@ -112,20 +114,6 @@ __device__ __forceinline__ int pout(int ts, int i, int r) {
   return (j / NS) * NS * R + (j & (NS - 1)) + r * NS;
 }
 
-template <int L, int R, int NS>
-__device__ __forceinline__ void pass_compute(float2 (&v)[8], int ts, const float2* __restrict__ twl) {
-#pragma unroll
-  for (int i = 0; i < 8 / R; ++i) {
-    if constexpr (NS > 1) {
-      const int j = ts + i * (L / 8);
-      const int step = (L / (NS * R)) * (j & (NS - 1));
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], twl[r * step]);
-    }
-    Dft<R>::run(v + i * R);
-  }
-}
-
 // ------------------------------------------------------------------------------------------------
 // launch helpers
 // ------------------------------------------------------------------------------------------------
@@ -172,16 +160,98 @@ __device__ __forceinline__ void load_pair2(const uint8_t* __restrict__ in, int S
 }
 
 // ------------------------------------------------------------------------------------------------
-// column pass
+// per-thread pass twiddles.  A thread keeps the same slot ts for every frame it transforms, so the
+// twiddles of its passes are loaded once into registers: pass p >= 1 is radix 8 with one task per thread,
+// rotating point r by W_L^(r * step), step = (L / (NS * 8)) * (ts mod NS).
 // ------------------------------------------------------------------------------------------------
 
+template <int L>
+struct PassTw {
+  static constexpr int NP = Sched<L>::NPASS;
+  float2 w[NP > 1 ? NP - 1 : 1][7];
+  __device__ __forceinline__ void load(const float2* __restrict__ table, int ts) {
+#pragma unroll
+    for (int p = 1; p < NP; ++p) {
+      const int ns = Sched<L>::ns(p);
+      const int step = (L / (ns * 8)) * (ts & (ns - 1));
+#pragma unroll
+      for (int r = 1; r < 8; ++r) w[p - 1][r - 1] = table[r * step];
+    }
+  }
+};
+
+template <int L, int P>
+__device__ __forceinline__ void pass_compute_reg(float2 (&v)[8], const PassTw<L>& tw) {
+  constexpr int R = Sched<L>::radix(P);
+  if constexpr (P > 0) {
+#pragma unroll
+    for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], tw.w[P - 1][r - 1]);
+  }
+#pragma unroll
+  for (int i = 0; i < 8 / R; ++i) Dft<R>::run(v + i * R);
+}
+
+// LDS index of element l of a row sequence: one pad element after every 8 breaks the stride-8 and
+// stride-64 write patterns of the first passes across the LDS banks.
+__device__ __forceinline__ int pad8(int l) { return l + (l >> 3); }
+
+// ------------------------------------------------------------------------------------------------
+// column pass: a workgroup owns COLS adjacent columns of one pair and loops over a group of frames,
+// reusing its registers' pass and four-step twiddles; the next frame's input is fetched while the
+// current one is transformed.
+// ------------------------------------------------------------------------------------------------
+
+// Input of 8 rows x 2 adjacent columns of one thread.  The int8 two-stream path fetches the next frame's
+// raw words ahead of use; the other formats decode at use.
+template <int BITS, bool FAST>
+struct ColLoader {
+  int64_t fbase;
+  template <int L, int R0>
+  __device__ __forceinline__ void fetch(const ColArgs&, int64_t fb, int, int) { fbase = fb; }
+  template <int L, int R0>
+  __device__ __forceinline__ void convert(float2 (&v)[2][8], const ColArgs& a, int ts, int n2b, int sx,
+                                          int sy) const {
+#pragma unroll
+    for (int i = 0; i < 8 / R0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int64_t t = fbase + (int64_t)pin<L, R0>(ts, i, r) * a.N2 + n2b;
+        load_pair2<BITS, false>(a.in, a.S, sx, sy, t, v[0][i * R0 + r], v[1][i * R0 + r]);
+      }
+  }
+};
+
+template <>
+struct ColLoader<8, true> {
+  uint32_t raw[8];  // x0 y0 x1 y1 bytes of each row
+  template <int L, int R0>
+  __device__ __forceinline__ void fetch(const ColArgs& a, int64_t fb, int ts, int n2b) {
+#pragma unroll
+    for (int i = 0; i < 8 / R0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int64_t t = fb + (int64_t)pin<L, R0>(ts, i, r) * a.N2 + n2b;
+        raw[i * R0 + r] = *reinterpret_cast<const uint32_t*>(a.in + 2 * t);
+      }
+  }
+  template <int L, int R0>
+  __device__ __forceinline__ void convert(float2 (&v)[2][8], const ColArgs&, int, int, int, int) const {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t w = raw[e];
+      v[0][e] = make_float2((float)(int)(int8_t)(w & 0xffu), (float)(int)(int8_t)((w >> 8) & 0xffu));
+      v[1][e] = make_float2((float)(int)(int8_t)((w >> 16) & 0xffu), (float)(int)(int8_t)(w >> 24));
+    }
+  }
+};
+
 template <int L, int COLS, int P>
-__device__ __forceinline__ void col_passes(float2 (&v)[2][8], int ts, int cv, const float2* __restrict__ twl,
-                                           float2* __restrict__ tile, const ColArgs& a, int f, int p, int n2b) {
+__device__ __forceinline__ void col_chain(float2 (&v)[2][8], int ts, int cv, const PassTw<L>& tw,
+                                          float2* __restrict__ tile) {
   using SC = Sched<L>;
   constexpr int R = SC::radix(P), NS = SC::ns(P);
-  pass_compute<L, R, NS>(v[0], ts, twl);
-  pass_compute<L, R, NS>(v[1], ts, twl);
+  pass_compute_reg<L, P>(v[0], tw);
+  pass_compute_reg<L, P>(v[1], tw);
   if constexpr (P + 1 < SC::NPASS) {
 #pragma unroll
     for (int i = 0; i < 8 / R; ++i)
@@ -202,183 +272,214 @@ __device__ __forceinline__ void col_passes(float2 (&v)[2][8], int ts, int cv, co
         v[1][i * R2 + r] = make_float2(q.z, q.w);
       }
     __syncthreads();
-    col_passes<L, COLS, P + 1>(v, ts, cv, twl, tile, a, f, p, n2b);
-  } else {
-    // k1 = output index; apply W_N^(k1*n2) and write T[f][p][k1][n2 .. n2+1]
-    const int mask = (1 << a.lo_bits) - 1;
-    float2* dst = a.T + ((int64_t)f * a.P + p) * (int64_t)L * a.N2 + n2b;
-#pragma unroll
-    for (int i = 0; i < 8 / R; ++i)
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int k1 = pout<L, R, NS>(ts, i, r);
-        const int m0 = k1 * n2b, m1 = m0 + k1;
-        const float2 w0 = cmul(a.tw_hi[m0 >> a.lo_bits], a.tw_lo[m0 & mask]);
-        const float2 w1 = cmul(a.tw_hi[m1 >> a.lo_bits], a.tw_lo[m1 & mask]);
-        const float2 o0 = cmul(v[0][i * R + r], w0), o1 = cmul(v[1][i * R + r], w1);
-        *reinterpret_cast<float4*>(dst + (int64_t)k1 * a.N2) = make_float4(o0.x, o0.y, o1.x, o1.y);
-      }
+    col_chain<L, COLS, P + 1>(v, ts, cv, tw, tile);
   }
 }
 
 template <int L, int COLS, int BITS, bool FAST>
 __global__ void __launch_bounds__(L * COLS / 16) k_colpass(ColArgs a) {
-  constexpr int CPR = COLS / 2;          // two adjacent columns per thread
-  constexpr int NT = L * COLS / 16;
+  constexpr int CPR = COLS / 2;  // two adjacent columns per thread
   using SC = Sched<L>;
+  constexpr int R0 = SC::R0, RL = SC::radix(SC::NPASS - 1), NSL = SC::ns(SC::NPASS - 1);
   __shared__ __align__(16) float2 tile[L * COLS];
-  __shared__ float2 twl[L];
-  for (int i = threadIdx.x; i < L; i += NT) twl[i] = a.tw_col[i];
 
   const int blk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   const int cb = blk % a.n_colblk;
   const int rest = blk / a.n_colblk;
   const int p = rest % a.P;
-  const int f = rest / a.P;
+  const int g = rest / a.P;
+  const int f_begin = g * a.frames_per_block;
+  const int f_end = min(a.n_frames, f_begin + a.frames_per_block);
   const int cv = (int)threadIdx.x % CPR, ts = (int)threadIdx.x / CPR;
   const int n2b = cb * COLS + cv * 2;
-  const int64_t fbase = (int64_t)f * a.N;
   const int sx = a.px[p], sy = a.py[p];
 
-  float2 v[2][8];
-  constexpr int R0 = SC::R0;
+  PassTw<L> tw;
+  tw.load(a.tw_col, ts);
+  // four-step twiddles W_N^(k1 * n2) of this thread's outputs, k1 = output index of the last pass
+  float2 fst[2][8];
+  const int mask = (1 << a.lo_bits) - 1;
 #pragma unroll
-  for (int i = 0; i < 8 / R0; ++i)
+  for (int i = 0; i < 8 / RL; ++i)
 #pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int n1 = pin<L, R0>(ts, i, r);
-      const int64_t n = (int64_t)n1 * a.N2 + n2b;
-      float2 z0, z1;
-      load_pair2<BITS, FAST>(a.in, a.S, sx, sy, fbase + n, z0, z1);
-      if (a.win) {
-        const float w0 = a.win[n], w1 = a.win[n + 1];
-        z0 = make_float2(z0.x * w0, z0.y * w0);
-        z1 = make_float2(z1.x * w1, z1.y * w1);
+    for (int r = 0; r < RL; ++r) {
+      const int k1 = pout<L, RL, NSL>(ts, i, r);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int m = k1 * (n2b + c);
+        fst[c][i * RL + r] = cmul(a.tw_hi[m >> a.lo_bits], a.tw_lo[m & mask]);
       }
-      v[0][i * R0 + r] = z0;
-      v[1][i * R0 + r] = z1;
     }
-  __syncthreads();  // twiddle table
-  col_passes<L, COLS, 0>(v, ts, cv, twl, tile, a, f, p, n2b);
+  ColLoader<BITS, FAST> cur;
+  if (f_begin < f_end) cur.template fetch<L, R0>(a, (int64_t)f_begin * a.N, ts, n2b);
+  for (int f = f_begin; f < f_end; ++f) {
+    float2 v[2][8];
+    cur.template convert<L, R0>(v, a, ts, n2b, sx, sy);
+    if (f + 1 < f_end) cur.template fetch<L, R0>(a, (int64_t)(f + 1) * a.N, ts, n2b);
+    if (a.win) {  // the window is the same for every frame (and cached in L2)
+#pragma unroll
+      for (int i = 0; i < 8 / R0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          const int64_t n = (int64_t)pin<L, R0>(ts, i, r) * a.N2 + n2b;
+          const float w0 = a.win[n], w1 = a.win[n + 1];
+          const int e = i * R0 + r;
+          v[0][e] = make_float2(v[0][e].x * w0, v[0][e].y * w0);
+          v[1][e] = make_float2(v[1][e].x * w1, v[1][e].y * w1);
+        }
+    }
+    col_chain<L, COLS, 0>(v, ts, cv, tw, tile);
+    float2* dst = a.T + ((int64_t)f * a.P + p) * (int64_t)L * a.N2 + n2b;
+#pragma unroll
+    for (int i = 0; i < 8 / RL; ++i)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int k1 = pout<L, RL, NSL>(ts, i, r);
+        const float2 o0 = cmul(v[0][i * RL + r], fst[0][i * RL + r]);
+        const float2 o1 = cmul(v[1][i * RL + r], fst[1][i * RL + r]);
+        *reinterpret_cast<float4*>(dst + (int64_t)k1 * a.N2) = make_float4(o0.x, o0.y, o1.x, o1.y);
+      }
+  }
 }
 
 // ------------------------------------------------------------------------------------------------
 // row pass + two-for-one split + cross power + FP64 accumulation
+// UB units (row pairs) per workgroup, FB frames per batch; each thread transforms two row sequences
+// (frames fs and fs + FB/2 of a batch, same row and slot) and owns 8/FB channel slots for the
+// whole launch.  The next batch's input is fetched while the current one is transformed.
+// Accumulated per channel and frame, unscaled: |A + B*|^2, |A - B*|^2 and i (A + B*) conj(A - B*)
+// with A = Z[k], B = Z[N - k]; the factor 1/4 that turns them into XX*, YY*, XY* is applied on output.
 // ------------------------------------------------------------------------------------------------
 
 template <int L, int P>
-__device__ __forceinline__ void row_passes(float2 (&v)[8], int ts, const float2* __restrict__ twl,
-                                           float2* __restrict__ seq) {
+__device__ __forceinline__ void row_chain(float2 (&v0)[8], float2 (&v1)[8], int ts, const PassTw<L>& tw,
+                                          float2* __restrict__ s0, float2* __restrict__ s1) {
   using SC = Sched<L>;
   constexpr int R = SC::radix(P), NS = SC::ns(P);
-  pass_compute<L, R, NS>(v, ts, twl);
+  pass_compute_reg<L, P>(v0, tw);
+  pass_compute_reg<L, P>(v1, tw);
 #pragma unroll
   for (int i = 0; i < 8 / R; ++i)
 #pragma unroll
-    for (int r = 0; r < R; ++r) seq[pout<L, R, NS>(ts, i, r)] = v[i * R + r];
+    for (int r = 0; r < R; ++r) {
+      const int o = pad8(pout<L, R, NS>(ts, i, r));
+      s0[o] = v0[i * R + r];
+      s1[o] = v1[i * R + r];
+    }
   if constexpr (P + 1 < SC::NPASS) {
     __syncthreads();
     constexpr int R2 = SC::radix(P + 1);
 #pragma unroll
     for (int i = 0; i < 8 / R2; ++i)
 #pragma unroll
-      for (int r = 0; r < R2; ++r) v[i * R2 + r] = seq[pin<L, R2>(ts, i, r)];
+      for (int r = 0; r < R2; ++r) {
+        const int o = pad8(pin<L, R2>(ts, i, r));
+        v0[i * R2 + r] = s0[o];
+        v1[i * R2 + r] = s1[o];
+      }
     __syncthreads();
-    row_passes<L, P + 1>(v, ts, twl, seq);
+    row_chain<L, P + 1>(v0, v1, ts, tw, s0, s1);
   }
 }
 
-// UB units (row pairs) per workgroup, FB frames in flight; one thread per 8 points of a row.
 template <int L, int UB, int FB>
-__global__ void __launch_bounds__(UB * FB * L / 4) k_rowpass(RowArgs a) {
-  constexpr int NT = UB * FB * L / 4;
-  constexpr int TPS = L / 8;              // threads per row sequence
-  constexpr int SPT = (UB * L) / NT;      // channel slots per thread (= 4 / FB)
+__global__ void __launch_bounds__(UB * FB * L / 8) k_rowpass(RowArgs a) {
+  constexpr int NT = UB * FB * L / 8;
+  constexpr int TPS = L / 8;             // threads per row sequence
+  constexpr int SPT = (UB * L) / NT;     // channel slots per thread (= 8 / FB)
+  constexpr int HB = FB / 2;             // frame pairs per batch
+  constexpr int SEQ = L + L / 8;         // padded sequence length in LDS
   using SC = Sched<L>;
-  __shared__ __align__(16) float2 buf[UB * FB * 2 * L];
-  __shared__ float2 twl[L];
+  constexpr int R0 = SC::R0;
+  __shared__ __align__(16) float2 buf[UB * FB * 2 * SEQ];
   const int tid = (int)threadIdx.x;
-  for (int i = tid; i < L; i += NT) twl[i] = a.tw_row[i];
-
   const int p = (int)blockIdx.y;
   const int U = a.N1 / 2;
-  // transform role of this thread
-  const int ts = tid % TPS, sq = tid / TPS;
-  const int rr = sq & 1, fs = (sq >> 1) % FB, ub = (sq >> 1) / FB;
+  // transform role: slot ts of row rr of frames fs and fs + HB of unit ub
+  const int ts = tid % TPS, q = tid / TPS;
+  const int rr = q & 1, fs = (q >> 1) % HB, ub = (q >> 1) / HB;
   const int u = (int)blockIdx.x * UB + ub;
   const int row = (u == 0) ? (rr ? a.N1 / 2 : 0) : (rr ? a.N1 - u : u);
+  float2* s0 = buf + ((ub * FB + fs) * 2 + rr) * SEQ;
+  float2* s1 = buf + ((ub * FB + fs + HB) * 2 + rr) * SEQ;
 
-  // channel role: slot s of unit ubc; slots [0, L/2) are the first row's channels, [L/2, L) the second's
+  PassTw<L> tw;
+  tw.load(a.tw_row, ts);
+
   double sxx[SPT], syy[SPT], sxr[SPT], sxi[SPT];
   double* accp[SPT];
 #pragma unroll
-  for (int q = 0; q < SPT; ++q) {
-    const int id = tid + q * NT;
+  for (int k = 0; k < SPT; ++k) {
+    const int id = tid + k * NT;
     const int ubc = id / L, s = id % L;
     const int uc = (int)blockIdx.x * UB + ubc;
-    accp[q] = a.acc + ((int64_t)(p * U + uc) * 4) * L + s;
+    accp[k] = a.acc + ((int64_t)(p * U + uc) * 4) * L + s;
     if (a.first) {
-      sxx[q] = syy[q] = sxr[q] = sxi[q] = 0.0;
+      sxx[k] = syy[k] = sxr[k] = sxi[k] = 0.0;
     } else {
-      sxx[q] = accp[q][0];
-      syy[q] = accp[q][L];
-      sxr[q] = accp[q][2 * L];
-      sxi[q] = accp[q][3 * L];
+      sxx[k] = accp[k][0];
+      syy[k] = accp[k][L];
+      sxr[k] = accp[k][2 * L];
+      sxi[k] = accp[k][3 * L];
     }
   }
-  __syncthreads();  // twiddle table
 
-  constexpr int R0 = SC::R0;
+  const int64_t fstride = (int64_t)a.P * a.N1 * L;  // float2 per frame
+  const float2* src = a.T + ((int64_t)p * a.N1 + row) * (int64_t)L;
+  float2 n0[8], n1[8];
+  auto fetch = [&](int f0) {
+    const int fa = f0 + fs, fb = f0 + fs + HB;
+#pragma unroll
+    for (int i = 0; i < 8 / R0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int l = pin<L, R0>(ts, i, r);
+        n0[i * R0 + r] = fa < a.n_frames ? src[fa * fstride + l] : make_float2(0.f, 0.f);
+        n1[i * R0 + r] = fb < a.n_frames ? src[fb * fstride + l] : make_float2(0.f, 0.f);
+      }
+  };
+  fetch(0);
   for (int f0 = 0; f0 < a.n_frames; f0 += FB) {
-    const int f = f0 + fs;
-    float2 v[8];
-    if (f < a.n_frames) {
-      const float2* src = a.T + (((int64_t)f * a.P + p) * a.N1 + row) * (int64_t)L;
+    float2 v0[8], v1[8];
 #pragma unroll
-      for (int i = 0; i < 8 / R0; ++i)
-#pragma unroll
-        for (int r = 0; r < R0; ++r) v[i * R0 + r] = src[pin<L, R0>(ts, i, r)];
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = make_float2(0.f, 0.f);
+    for (int e = 0; e < 8; ++e) {
+      v0[e] = n0[e];
+      v1[e] = n1[e];
     }
-    row_passes<L, 0>(v, ts, twl, buf + sq * L);
+    if (f0 + FB < a.n_frames) fetch(f0 + FB);
+    row_chain<L, 0>(v0, v1, ts, tw, s0, s1);
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < SPT; ++q) {
-      const int id = tid + q * NT;
+    for (int k = 0; k < SPT; ++k) {
+      const int id = tid + k * NT;
       const int ubc = id / L, s = id % L;
       const int uc = (int)blockIdx.x * UB + ubc;
       const int half = s / (L / 2), k2 = s % (L / 2);
       // bin (row, k2) pairs with bin N - k: rows k1 and N1 - k1 swap, k2 -> N2 - 1 - k2; row 0 -> N2 - k2
       const int phalf = (uc == 0) ? half : 1 - half;
       const int pk2 = (uc == 0 && half == 0) ? ((L - k2) & (L - 1)) : (L - 1 - k2);
-      for (int g = 0; g < FB; ++g) {
-        if (f0 + g >= a.n_frames) break;
-        const float2* fr = buf + ((ubc * FB + g) * 2) * L;
-        const float2 A = fr[half * L + k2];
-        const float2 B = fr[phalf * L + pk2];
-        // X = (A + conj B)/2, Y = (A - conj B)/(2i)
-        const float2 sm = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
-        const float2 df = make_float2(0.5f * (A.x - B.x), 0.5f * (A.y + B.y));
-        const float xx = sm.x * sm.x + sm.y * sm.y;
-        const float yy = df.x * df.x + df.y * df.y;
-        const float qr = sm.x * df.x + sm.y * df.y;   // Re(sm conj df)
-        const float qi = sm.y * df.x - sm.x * df.y;   // Im(sm conj df)
-        sxx[q] += (double)xx;
-        syy[q] += (double)yy;
-        sxr[q] += (double)(-qi);  // XY* = i * sm * conj(df)
-        sxi[q] += (double)qr;
+      const int oa = half * SEQ + pad8(k2), ob = phalf * SEQ + pad8(pk2);
+      const int nf = min(FB, a.n_frames - f0);
+      for (int g = 0; g < nf; ++g) {
+        const float2* fr = buf + ((ubc * FB + g) * 2) * SEQ;
+        const float2 A = fr[oa];
+        const float2 B = fr[ob];
+        const float sx_ = A.x + B.x, sy_ = A.y - B.y;   // A + conj(B) = 2 X
+        const float dx_ = A.x - B.x, dy_ = A.y + B.y;   // A - conj(B) = 2i Y
+        sxx[k] += (double)(sx_ * sx_ + sy_ * sy_);
+        syy[k] += (double)(dx_ * dx_ + dy_ * dy_);
+        sxr[k] += (double)(sx_ * dy_ - sy_ * dx_);      // Re of i (s conj d)
+        sxi[k] += (double)(sx_ * dx_ + sy_ * dy_);      // Im of i (s conj d)
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < SPT; ++q) {
-    accp[q][0] = sxx[q];
-    accp[q][L] = syy[q];
-    accp[q][2 * L] = sxr[q];
-    accp[q][3 * L] = sxi[q];
+  for (int k = 0; k < SPT; ++k) {
+    accp[k][0] = sxx[k];
+    accp[k][L] = syy[k];
+    accp[k][2 * L] = sxr[k];
+    accp[k][3 * L] = sxi[k];
   }
 }
 
@@ -423,7 +524,9 @@ __global__ void __launch_bounds__(256) k_output(OutArgs a) {
   for (int e = (int)threadIdx.x; e < rt * kt; e += 256) {
     const int kk = e / rt, rl = e % rt;
     const int64_t k = (int64_t)(k20 + kk) * a.N1 + r0 + rl;
-    const double axx = t[0][rl][kk], ayy = t[1][rl][kk], axr = t[2][rl][kk], axi = t[3][rl][kk];
+    // stored sums are 4 XX*, 4 YY*, 4 XY* (exact power-of-two scale)
+    const double axx = 0.25 * t[0][rl][kk], ayy = 0.25 * t[1][rl][kk];
+    const double axr = 0.25 * t[2][rl][kk], axi = 0.25 * t[3][rl][kk];
     if constexpr (!STOKES) {
       double* o = a.spectra + (int64_t)p * 4 * a.C + k;
       o[0] = axx;
@@ -494,7 +597,8 @@ __global__ void __launch_bounds__(256) k_copy_words(const uint32_t* __restrict__
 
 template <int L, int COLS>
 static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)(a.n_frames * a.P * a.n_colblk)), block(L * COLS / 16);
+  const int groups = (a.n_frames + a.frames_per_block - 1) / a.frames_per_block;
+  const dim3 grid((unsigned)(groups * a.P * a.n_colblk)), block(L * COLS / 16);
   switch (bits) {
     case 2: hipLaunchKernelGGL((k_colpass<L, COLS, 2, false>), grid, block, 0, s, a); break;
     case 4: hipLaunchKernelGGL((k_colpass<L, COLS, 4, false>), grid, block, 0, s, a); break;
@@ -508,7 +612,7 @@ static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, hipStream_
   return hipGetLastError();
 }
 
-int colpass_cols(int N1) { return N1 >= 2048 ? 8 : 16; }
+int colpass_cols(int N1) { return N1 >= 2048 ? 4 : (N1 >= 1024 ? 8 : 16); }
 
 hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, hipStream_t s) {
   switch (N1) {
@@ -518,29 +622,27 @@ hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, hipStre
     case 128: return colpass_bits<128, 16>(bits, fast, a, s);
     case 256: return colpass_bits<256, 16>(bits, fast, a, s);
     case 512: return colpass_bits<512, 16>(bits, fast, a, s);
-    case 1024: return colpass_bits<1024, 16>(bits, fast, a, s);
-    case 2048: return colpass_bits<2048, 8>(bits, fast, a, s);
+    case 1024: return colpass_bits<1024, 8>(bits, fast, a, s);
+    case 2048: return colpass_bits<2048, 4>(bits, fast, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int L, int UB, int FB>
 static hipError_t rowpass_launch(const RowArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P), block(UB * FB * L / 4);
+  const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P), block(UB * FB * L / 8);
   hipLaunchKernelGGL((k_rowpass<L, UB, FB>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
-int rowpass_units_per_block(int N2) { return N2 >= 128 ? 1 : 128 / N2; }
-
 hipError_t launch_rowpass(int N2, const RowArgs& a, hipStream_t s) {
   switch (N2) {
-    case 16: return rowpass_launch<16, 8, 4>(a, s);
-    case 32: return rowpass_launch<32, 4, 4>(a, s);
-    case 64: return rowpass_launch<64, 2, 4>(a, s);
-    case 128: return rowpass_launch<128, 1, 4>(a, s);
-    case 256: return rowpass_launch<256, 1, 4>(a, s);
-    case 512: return rowpass_launch<512, 1, 4>(a, s);
+    case 16: return rowpass_launch<16, 8, 8>(a, s);
+    case 32: return rowpass_launch<32, 8, 8>(a, s);
+    case 64: return rowpass_launch<64, 4, 8>(a, s);
+    case 128: return rowpass_launch<128, 2, 8>(a, s);
+    case 256: return rowpass_launch<256, 1, 8>(a, s);
+    case 512: return rowpass_launch<512, 1, 8>(a, s);
     case 1024: return rowpass_launch<1024, 1, 4>(a, s);
     case 2048: return rowpass_launch<2048, 1, 2>(a, s);
     default: return hipErrorInvalidValue;
