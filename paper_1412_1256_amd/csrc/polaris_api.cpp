@@ -299,6 +299,10 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
       const int nf = (int)((F - f0) < I.chunk ? (F - f0) : I.chunk);
       ps::ColArgs ca{};
       ca.in = base + f0 * frame_bytes;
+      const int64_t in_bytes = (int64_t)nf * frame_bytes;
+      ca.in_bytes = in_bytes < (int64_t(1) << 31) ? (uint32_t)in_bytes : 0u;
+      // the int8 two-stream path addresses its input with 32-bit buffer offsets
+      const bool fast = I.fast && in_bytes < (int64_t(1) << 31) && I.N * 8 < (int64_t(1) << 31);
       ca.N = I.N;
       ca.N2 = (int32_t)I.N2;
       ca.S = I.cfg.n_streams;
@@ -325,7 +329,7 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
       ca.lo_bits = I.m2;
       ca.T = ws_ptr<float2>(plan, I.off_T);
       hipError_t e = timed(plan, PS_KERNEL_COLPASS,
-                           [&] { return ps::launch_colpass((int)I.N1, I.cfg.bits, I.fast, ca, plan->stream); });
+                           [&] { return ps::launch_colpass((int)I.N1, I.cfg.bits, fast, ca, plan->stream); });
       if (e != hipSuccess) return hip_fail(e, "column pass launch");
       ps::RowArgs ra{};
       ra.T = ca.T;

@@ -15,6 +15,7 @@ namespace ps {
 
 struct ColArgs {
   const uint8_t* in;        // packed input of the first frame of this launch
+  uint32_t in_bytes;        // bytes of input in this launch (< 2^31 on the int8 two-stream path)
   int64_t N;                // frame length
   int32_t N2;               // columns
   int32_t S, P;             // streams, pairs

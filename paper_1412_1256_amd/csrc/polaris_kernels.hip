@@ -127,6 +127,27 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
   return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Raw buffer resources: a wave-uniform base in SGPRs, 32-bit per-lane offsets and SGPR offsets for the
+// parts that are the same across the wave, so loads and stores need no 64-bit address arithmetic.
+// Accesses past num_records return zero / are dropped by the hardware.
+constexpr int kBufferFlags = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferFlags);
+}
+
+// A pointer that is the same in every lane of the wave, made visibly uniform so the compiler keeps it in
+// SGPRs and addresses with the scalar-base form of global loads.
+typedef const __attribute__((address_space(1))) uint8_t* gbytes;
+
+__device__ __forceinline__ gbytes uniform_gptr(const uint8_t* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (gbytes)(((uint64_t)hi << 32) | lo);
+}
+
 // ------------------------------------------------------------------------------------------------
 // data translation: level of one packed item (offset-binary 2/4-bit, int8, float32)
 // ------------------------------------------------------------------------------------------------
@@ -226,12 +247,15 @@ struct ColLoader<8, true> {
   uint32_t raw[8];  // x0 y0 x1 y1 bytes of each row
   template <int L, int R0>
   __device__ __forceinline__ void fetch(const ColArgs& a, int64_t fb, int ts, int n2b) {
+    // row n1 = ts + i L/8 + r L/R0, columns n2b, n2b + 1 of frame fb / N: a wave-uniform 64-bit base per
+    // (frame, i, r) plus a 32-bit per-lane offset (the global_load scalar-base form)
+    const uint32_t voff = 2u * (uint32_t)(ts * a.N2 + n2b);
 #pragma unroll
     for (int i = 0; i < 8 / R0; ++i)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
-        const int64_t t = fb + (int64_t)pin<L, R0>(ts, i, r) * a.N2 + n2b;
-        raw[i * R0 + r] = *reinterpret_cast<const uint32_t*>(a.in + 2 * t);
+        const gbytes base = uniform_gptr(a.in + 2 * (fb + (int64_t)a.N2 * (i * (L / 8) + r * (L / R0))));
+        raw[i * R0 + r] = *(const __attribute__((address_space(1))) uint32_t*)(base + voff);
       }
   }
   template <int L, int R0>
@@ -329,16 +353,21 @@ __global__ void __launch_bounds__(L * COLS / 16) k_colpass(ColArgs a) {
         }
     }
     col_chain<L, COLS, 0>(v, ts, cv, tw, tile);
-    float2* dst = a.T + ((int64_t)f * a.P + p) * (int64_t)L * a.N2 + n2b;
+    // the last pass is radix 8 with output k1 = ts + r L/8: write T[f][p][k1][n2b .. n2b + 1] (global stores:
+    // the next kernel reads them from every XCD)
+    static_assert(RL == 8 && NSL == L / 8, "last pass must be radix 8");
+    const uint32_t voff = 8u * (uint32_t)(ts * a.N2 + n2b);
 #pragma unroll
-    for (int i = 0; i < 8 / RL; ++i)
-#pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int k1 = pout<L, RL, NSL>(ts, i, r);
-        const float2 o0 = cmul(v[0][i * RL + r], fst[0][i * RL + r]);
-        const float2 o1 = cmul(v[1][i * RL + r], fst[1][i * RL + r]);
-        *reinterpret_cast<float4*>(dst + (int64_t)k1 * a.N2) = make_float4(o0.x, o0.y, o1.x, o1.y);
-      }
+    for (int r = 0; r < 8; ++r) {
+      const float2 o0 = cmul(v[0][r], fst[0][r]);
+      const float2 o1 = cmul(v[1][r], fst[1][r]);
+      typedef float f32x4 __attribute__((ext_vector_type(4)));
+      typedef __attribute__((address_space(1))) f32x4* gf4;
+      const gbytes base = uniform_gptr(reinterpret_cast<const uint8_t*>(
+          a.T + ((int64_t)f * a.P + p) * (int64_t)L * a.N2 + (int64_t)r * (L / 8) * a.N2));
+      const f32x4 q = {o0.x, o0.y, o1.x, o1.y};
+      *(gf4)(base + voff) = q;
+    }
   }
 }
 
@@ -350,6 +379,20 @@ __global__ void __launch_bounds__(L * COLS / 16) k_colpass(ColArgs a) {
 // Accumulated per channel and frame, unscaled: |A + B*|^2, |A - B*|^2 and i (A + B*) conj(A - B*)
 // with A = Z[k], B = Z[N - k]; the factor 1/4 that turns them into XX*, YY*, XY* is applied on output.
 // ------------------------------------------------------------------------------------------------
+
+// Exchange barrier between passes.  When a wave holds whole sequences (L/8 <= 64 threads per sequence)
+// every exchange stays inside the wave: LDS operations of one wave complete in order, so ordering the
+// wave's LDS writes before its reads is enough and no workgroup barrier is needed.
+template <int L>
+__device__ __forceinline__ void exchange_sync() {
+  if constexpr (L / 8 <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 
 template <int L, int P>
 __device__ __forceinline__ void row_chain(float2 (&v0)[8], float2 (&v1)[8], int ts, const PassTw<L>& tw,
@@ -367,7 +410,7 @@ __device__ __forceinline__ void row_chain(float2 (&v0)[8], float2 (&v1)[8], int 
       s1[o] = v1[i * R + r];
     }
   if constexpr (P + 1 < SC::NPASS) {
-    __syncthreads();
+    exchange_sync<L>();
     constexpr int R2 = SC::radix(P + 1);
 #pragma unroll
     for (int i = 0; i < 8 / R2; ++i)
@@ -377,7 +420,7 @@ __device__ __forceinline__ void row_chain(float2 (&v0)[8], float2 (&v1)[8], int 
         v0[i * R2 + r] = s0[o];
         v1[i * R2 + r] = s1[o];
       }
-    __syncthreads();
+    exchange_sync<L>();
     row_chain<L, P + 1>(v0, v1, ts, tw, s0, s1);
   }
 }
@@ -425,30 +468,23 @@ __global__ void __launch_bounds__(UB * FB * L / 8) k_rowpass(RowArgs a) {
   }
 
   const int64_t fstride = (int64_t)a.P * a.N1 * L;  // float2 per frame
-  const float2* src = a.T + ((int64_t)p * a.N1 + row) * (int64_t)L;
-  float2 n0[8], n1[8];
-  auto fetch = [&](int f0) {
-    const int fa = f0 + fs, fb = f0 + fs + HB;
+  const float2* src = a.T + ((int64_t)p * a.N1 + row) * (int64_t)L + ts;
+  // frames past the end of the launch repeat the last frame (their products are never accumulated)
+  auto fetch = [&](float2 (&d0)[8], float2 (&d1)[8], int f0) {
+    const float2* pa = src + (int64_t)min(f0 + fs, a.n_frames - 1) * fstride;
+    const float2* pb = src + (int64_t)min(f0 + fs + HB, a.n_frames - 1) * fstride;
 #pragma unroll
     for (int i = 0; i < 8 / R0; ++i)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
-        const int l = pin<L, R0>(ts, i, r);
-        n0[i * R0 + r] = fa < a.n_frames ? src[fa * fstride + l] : make_float2(0.f, 0.f);
-        n1[i * R0 + r] = fb < a.n_frames ? src[fb * fstride + l] : make_float2(0.f, 0.f);
+        d0[i * R0 + r] = pa[i * (L / 8) + r * (L / R0)];
+        d1[i * R0 + r] = pb[i * (L / 8) + r * (L / R0)];
       }
   };
-  fetch(0);
-  for (int f0 = 0; f0 < a.n_frames; f0 += FB) {
-    float2 v0[8], v1[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      v0[e] = n0[e];
-      v1[e] = n1[e];
-    }
-    if (f0 + FB < a.n_frames) fetch(f0 + FB);
+  auto batch = [&](float2 (&v0)[8], float2 (&v1)[8], int f0) {
     row_chain<L, 0>(v0, v1, ts, tw, s0, s1);
     __syncthreads();
+    const int nf = min(FB, a.n_frames - f0);
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
       const int id = tid + k * NT;
@@ -458,12 +494,11 @@ __global__ void __launch_bounds__(UB * FB * L / 8) k_rowpass(RowArgs a) {
       // bin (row, k2) pairs with bin N - k: rows k1 and N1 - k1 swap, k2 -> N2 - 1 - k2; row 0 -> N2 - k2
       const int phalf = (uc == 0) ? half : 1 - half;
       const int pk2 = (uc == 0 && half == 0) ? ((L - k2) & (L - 1)) : (L - 1 - k2);
-      const int oa = half * SEQ + pad8(k2), ob = phalf * SEQ + pad8(pk2);
-      const int nf = min(FB, a.n_frames - f0);
+      const float2* fa = buf + (ubc * FB * 2 + half) * SEQ + pad8(k2);
+      const float2* fb = buf + (ubc * FB * 2 + phalf) * SEQ + pad8(pk2);
       for (int g = 0; g < nf; ++g) {
-        const float2* fr = buf + ((ubc * FB + g) * 2) * SEQ;
-        const float2 A = fr[oa];
-        const float2 B = fr[ob];
+        const float2 A = fa[g * 2 * SEQ];
+        const float2 B = fb[g * 2 * SEQ];
         const float sx_ = A.x + B.x, sy_ = A.y - B.y;   // A + conj(B) = 2 X
         const float dx_ = A.x - B.x, dy_ = A.y + B.y;   // A - conj(B) = 2i Y
         sxx[k] += (double)(sx_ * sx_ + sy_ * sy_);
@@ -473,6 +508,16 @@ __global__ void __launch_bounds__(UB * FB * L / 8) k_rowpass(RowArgs a) {
       }
     }
     __syncthreads();
+  };
+  float2 a0[8], a1[8], b0[8], b1[8];
+  fetch(a0, a1, 0);
+  for (int f0 = 0; f0 < a.n_frames; f0 += 2 * FB) {
+    const bool second = f0 + FB < a.n_frames;
+    if (second) fetch(b0, b1, f0 + FB);
+    batch(a0, a1, f0);
+    if (!second) break;
+    if (f0 + 2 * FB < a.n_frames) fetch(a0, a1, f0 + 2 * FB);
+    batch(b0, b1, f0 + FB);
   }
 #pragma unroll
   for (int k = 0; k < SPT; ++k) {
@@ -493,10 +538,6 @@ struct cd {
 __device__ __forceinline__ cd cdm(cd a, cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ __forceinline__ cd cda(cd a, cd b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ cd cdc(cd a) { return {a.x, -a.y}; }
-__device__ __forceinline__ cd cdiv(cd a, cd b) {
-  const double d = b.x * b.x + b.y * b.y;
-  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
-}
 
 template <bool STOKES>
 __global__ void __launch_bounds__(256) k_output(OutArgs a) {
@@ -534,34 +575,40 @@ __global__ void __launch_bounds__(256) k_output(OutArgs a) {
       o[2 * a.C] = axr;
       o[3 * a.C] = axi;
     } else {
-      // normalised coherency M
-      const cd mxx = {axx * scale, 0.0}, myy = {ayy * scale, 0.0};
+      // normalised coherency M = A / (F sum w^2); C = Fi M Fi^H with Fi = (G J)^-1 (C_yx = conj C_xy)
+      const double mxx = axx * scale, myy = ayy * scale;
       const cd mxy = {axr * scale, axi * scale}, myx = cdc(mxy);
-      // E = G J = [[gx, gx dx], [gy dy, gy]];  Fi = E^-1
-      cd gx = {1.0, 0.0}, gy = {1.0, 0.0}, dx = {0.0, 0.0}, dy = {0.0, 0.0};
-      if (a.gain_x) gx = {(double)a.gain_x[2 * ((int64_t)p * a.C + k)], (double)a.gain_x[2 * ((int64_t)p * a.C + k) + 1]};
-      if (a.gain_y) gy = {(double)a.gain_y[2 * ((int64_t)p * a.C + k)], (double)a.gain_y[2 * ((int64_t)p * a.C + k) + 1]};
-      if (a.dterms) {
-        dx = {(double)a.dterms[4 * p + 0], (double)a.dterms[4 * p + 1]};
-        dy = {(double)a.dterms[4 * p + 2], (double)a.dterms[4 * p + 3]};
+      double cxx = mxx, cyy = myy;
+      cd cxy = mxy;
+      if (a.gain_x || a.gain_y || a.dterms) {
+        cd gx = {1.0, 0.0}, gy = {1.0, 0.0}, dx = {0.0, 0.0}, dy = {0.0, 0.0};
+        const int64_t gi = 2 * ((int64_t)p * a.C + k);
+        if (a.gain_x) gx = {(double)a.gain_x[gi], (double)a.gain_x[gi + 1]};
+        if (a.gain_y) gy = {(double)a.gain_y[gi], (double)a.gain_y[gi + 1]};
+        if (a.dterms) {
+          dx = {(double)a.dterms[4 * p + 0], (double)a.dterms[4 * p + 1]};
+          dy = {(double)a.dterms[4 * p + 2], (double)a.dterms[4 * p + 3]};
+        }
+        // E = [[gx, gx dx], [gy dy, gy]], det E = gx gy (1 - dx dy), Fi = adj(E) / det E
+        const cd e01 = cdm(gx, dx), e10 = cdm(gy, dy);
+        const cd dxy = cdm(dx, dy);
+        const cd det = cdm(cdm(gx, gy), {1.0 - dxy.x, -dxy.y});
+        const double inv = 1.0 / (det.x * det.x + det.y * det.y);
+        const cd id = {det.x * inv, -det.y * inv};  // 1 / det
+        const cd f00 = cdm(gy, id), f01 = cdm({-e01.x, -e01.y}, id);
+        const cd f10 = cdm({-e10.x, -e10.y}, id), f11 = cdm(gx, id);
+        const cd t00 = cda(cdm(f00, {mxx, 0.0}), cdm(f01, myx)), t01 = cda(cdm(f00, mxy), cdm(f01, {myy, 0.0}));
+        const cd t10 = cda(cdm(f10, {mxx, 0.0}), cdm(f11, myx)), t11 = cda(cdm(f10, mxy), cdm(f11, {myy, 0.0}));
+        cxx = cda(cdm(t00, cdc(f00)), cdm(t01, cdc(f01))).x;
+        cxy = cda(cdm(t00, cdc(f10)), cdm(t01, cdc(f11)));
+        cyy = cda(cdm(t10, cdc(f10)), cdm(t11, cdc(f11))).x;
       }
-      const cd e00 = gx, e01 = cdm(gx, dx), e10 = cdm(gy, dy), e11 = gy;
-      const cd det = cda(cdm(e00, e11), {-cdm(e01, e10).x, -cdm(e01, e10).y});
-      const cd f00 = cdiv(e11, det), f01 = cdiv({-e01.x, -e01.y}, det);
-      const cd f10 = cdiv({-e10.x, -e10.y}, det), f11 = cdiv(e00, det);
-      // T = Fi M ; C = T Fi^H
-      const cd t00 = cda(cdm(f00, mxx), cdm(f01, myx)), t01 = cda(cdm(f00, mxy), cdm(f01, myy));
-      const cd t10 = cda(cdm(f10, mxx), cdm(f11, myx)), t11 = cda(cdm(f10, mxy), cdm(f11, myy));
-      const cd c00 = cda(cdm(t00, cdc(f00)), cdm(t01, cdc(f01)));
-      const cd c01 = cda(cdm(t00, cdc(f10)), cdm(t01, cdc(f11)));
-      const cd c10 = cda(cdm(t10, cdc(f00)), cdm(t11, cdc(f01)));
-      const cd c11 = cda(cdm(t10, cdc(f10)), cdm(t11, cdc(f11)));
-      // Eq. 2 rows acting on [C_xx, C_xy, C_yx, C_yy]
+      // Eq. 2 rows acting on [C_xx, C_xy, C_yx, C_yy] with C_yx = conj C_xy
       const double c2 = a.cos2psi, s2 = a.sin2psi;
-      const double I = 0.5 * (c00.x + c11.x);
-      const double Q = 0.5 * (c2 * c00.x - s2 * c01.x - s2 * c10.x - c2 * c11.x);
-      const double Uq = 0.5 * (s2 * c00.x + c2 * c01.x + c2 * c10.x - s2 * c11.x);
-      const double V = 0.5 * (c01.y - c10.y);  // Re(-i C_xy + i C_yx)
+      const double I = 0.5 * (cxx + cyy);
+      const double Q = 0.5 * (c2 * (cxx - cyy) - s2 * 2.0 * cxy.x);
+      const double Uq = 0.5 * (s2 * (cxx - cyy) + c2 * 2.0 * cxy.x);
+      const double V = cxy.y;  // Re(-i C_xy + i C_yx) / 2
       float* o = a.iquv + (int64_t)p * 4 * a.C + k;
       o[0] = (float)I;
       o[a.C] = (float)Q;

@@ -297,3 +297,26 @@ def test_error_paths(pk, torch_dev):
     plan.accumulate(packed)
     s, nf = plan.spectra()
     assert nf == 2
+
+
+def test_reused_input_buffer_between_calls(pk, torch_dev):
+    """Streaming: one device buffer is overwritten with new sampler data before each call."""
+    torch, dev = torch_dev
+    say("reused input buffer")
+    N, F = 1 << 18, 6
+    inst = synth.make_correlated_noise(8, 0.2, N, 2 * F, seed_extra=11)
+    bpc = N * 2 * F  # bytes per call
+    host = torch.from_numpy(inst["packed"])
+    buf = torch.empty(bpc, dtype=torch.uint8, device=dev)
+    plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev)
+    plan.reset()
+    for c in range(2):
+        buf.copy_(host[c * bpc:(c + 1) * bpc].to(dev))
+        plan.accumulate(buf)
+    got, nf = plan.spectra()
+    torch.cuda.synchronize(dev)
+    acc, nfo, s2, _ = oracle.run_instance(inst)
+    assert nf == nfo == 2 * F
+    e = spectra_err(got.cpu().numpy(), acc)
+    say(f"  spectra err {e.ravel().tolist()}")
+    assert np.all(e < TOL), e
