@@ -80,6 +80,7 @@ struct ps_plan_s {
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
+  int n_cu = 256;  // compute units of the bound device
   // per-kernel timing (measurement only)
   bool prof = false;
   std::vector<hipEvent_t> ev;       // pairs (start, stop)
@@ -244,6 +245,13 @@ ps_status ps_bind(ps_plan_t plan, void* workspace_dev, size_t bytes, void* hip_s
   plan->ws = static_cast<char*>(workspace_dev);
   plan->stream = static_cast<hipStream_t>(hip_stream);
   plan->bound = false;
+  {
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    plan->n_cu = ncu > 0 ? ncu : 256;
+  }
   for (Inst& I : plan->inst) {
     if ((st = upload(plan, I.off_tw_col, I.tw_col.data(), I.tw_col.size() * 4)) != PS_OK) return st;
     if ((st = upload(plan, I.off_tw_row, I.tw_row.data(), I.tw_row.size() * 4)) != PS_OK) return st;
@@ -315,9 +323,9 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
       ca.n_colblk = (int32_t)(I.N2 / cols);
       ca.n_frames = nf;
       {
-        // about two workgroups per CU: frames per workgroup so that groups x pairs x blocks ~ 512
+        // one workgroup per CU: each loops over a group of frames, so that groups x pairs x blocks ~ CUs
         const int64_t per_frame = (int64_t)ca.n_colblk * ca.P;
-        int64_t groups = (512 + per_frame / 2) / per_frame;
+        int64_t groups = (plan->n_cu + per_frame / 2) / per_frame;
         if (groups < 1) groups = 1;
         if (groups > nf) groups = nf;
         ca.frames_per_block = (int32_t)((nf + groups - 1) / groups);

@@ -212,78 +212,118 @@ __device__ __forceinline__ void pass_compute_reg(float2 (&v)[8], const PassTw<L>
   for (int i = 0; i < 8 / R; ++i) Dft<R>::run(v + i * R);
 }
 
-// LDS index of element l of a row sequence: one pad element after every 8 breaks the stride-8 and
-// stride-64 write patterns of the first passes across the LDS banks.
-__device__ __forceinline__ int pad8(int l) { return l + (l >> 3); }
+// LDS index of element e of a row sequence.  The low five bits of e are XORed with bits 4..7 so that the
+// stride-8 and stride-64 write patterns of the radix-8 passes, their unit-stride reads and the channel
+// stage's forward and reversed reads all fall on distinct banks; the map stays inside each aligned block
+// of 32 elements, so a sequence needs no padding.
+__device__ __forceinline__ int swz(int e) {
+  return e ^ (((e >> 4) & 7) | (((e >> 6) & 1) << 3) | (((e >> 7) & 1) << 4));
+}
 
 // ------------------------------------------------------------------------------------------------
 // column pass: a workgroup owns COLS adjacent columns of one pair and loops over a group of frames,
 // reusing its registers' pass and four-step twiddles; the next frame's input is fetched while the
-// current one is transformed.
+// current one is transformed.  Each thread owns V adjacent columns (8 points of each).
 // ------------------------------------------------------------------------------------------------
 
-// Input of 8 rows x 2 adjacent columns of one thread.  The int8 two-stream path fetches the next frame's
+// Input of 8 rows x V adjacent columns of one thread.  The int8 two-stream path fetches the next frame's
 // raw words ahead of use; the other formats decode at use.
-template <int BITS, bool FAST>
+template <int BITS, bool FAST, int V>
 struct ColLoader {
   int64_t fbase;
   template <int L, int R0>
   __device__ __forceinline__ void fetch(const ColArgs&, int64_t fb, int, int) { fbase = fb; }
   template <int L, int R0>
-  __device__ __forceinline__ void convert(float2 (&v)[2][8], const ColArgs& a, int ts, int n2b, int sx,
+  __device__ __forceinline__ void convert(float2 (&v)[V][8], const ColArgs& a, int ts, int n2b, int sx,
                                           int sy) const {
 #pragma unroll
     for (int i = 0; i < 8 / R0; ++i)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
         const int64_t t = fbase + (int64_t)pin<L, R0>(ts, i, r) * a.N2 + n2b;
-        load_pair2<BITS, false>(a.in, a.S, sx, sy, t, v[0][i * R0 + r], v[1][i * R0 + r]);
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          const int64_t it = (t + c) * a.S;
+          v[c][i * R0 + r] = make_float2(level_of<BITS>(a.in, it + sx), level_of<BITS>(a.in, it + sy));
+        }
       }
   }
 };
 
-template <>
-struct ColLoader<8, true> {
-  uint32_t raw[8];  // x0 y0 x1 y1 bytes of each row
+// int8, two streams, pair (0, 1): sample t of the pair is the 16-bit word x_t y_t
+template <int V>
+struct ColLoader<8, true, V> {
+  uint32_t raw[8];  // V x (x, y) bytes of each row
   template <int L, int R0>
   __device__ __forceinline__ void fetch(const ColArgs& a, int64_t fb, int ts, int n2b) {
-    // row n1 = ts + i L/8 + r L/R0, columns n2b, n2b + 1 of frame fb / N: a wave-uniform 64-bit base per
-    // (frame, i, r) plus a 32-bit per-lane offset (the global_load scalar-base form)
+    // row n1 = ts + i L/8 + r L/R0 of frame fb / N: a wave-uniform 64-bit base per (frame, i, r) plus a
+    // 32-bit per-lane offset (the global_load scalar-base form)
     const uint32_t voff = 2u * (uint32_t)(ts * a.N2 + n2b);
 #pragma unroll
     for (int i = 0; i < 8 / R0; ++i)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
         const gbytes base = uniform_gptr(a.in + 2 * (fb + (int64_t)a.N2 * (i * (L / 8) + r * (L / R0))));
-        raw[i * R0 + r] = *(const __attribute__((address_space(1))) uint32_t*)(base + voff);
+        if constexpr (V == 2)
+          raw[i * R0 + r] = *(const __attribute__((address_space(1))) uint32_t*)(base + voff);
+        else
+          raw[i * R0 + r] = *(const __attribute__((address_space(1))) uint16_t*)(base + voff);
       }
   }
   template <int L, int R0>
-  __device__ __forceinline__ void convert(float2 (&v)[2][8], const ColArgs&, int, int, int, int) const {
+  __device__ __forceinline__ void convert(float2 (&v)[V][8], const ColArgs&, int, int, int, int) const {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const uint32_t w = raw[e];
       v[0][e] = make_float2((float)(int)(int8_t)(w & 0xffu), (float)(int)(int8_t)((w >> 8) & 0xffu));
-      v[1][e] = make_float2((float)(int)(int8_t)((w >> 16) & 0xffu), (float)(int)(int8_t)(w >> 24));
+      if constexpr (V == 2)
+        v[1][e] = make_float2((float)(int)(int8_t)((w >> 16) & 0xffu), (float)(int)(int8_t)(w >> 24));
     }
   }
 };
 
-template <int L, int COLS, int P>
-__device__ __forceinline__ void col_chain(float2 (&v)[2][8], int ts, int cv, const PassTw<L>& tw,
-                                          float2* __restrict__ tile) {
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// LDS tile [L][COLS]: element l of column cv*V + c at l*COLS + cv*V + c
+template <int V>
+__device__ __forceinline__ void tile_store(float2* __restrict__ tile, int idx, const float2 (&w)[V]) {
+  if constexpr (V == 2)
+    *reinterpret_cast<float4*>(tile + idx) = make_float4(w[0].x, w[0].y, w[1].x, w[1].y);
+  else
+    tile[idx] = w[0];
+}
+
+template <int V>
+__device__ __forceinline__ void tile_load(const float2* __restrict__ tile, int idx, float2 (&w)[V]) {
+  if constexpr (V == 2) {
+    const float4 q = *reinterpret_cast<const float4*>(tile + idx);
+    w[0] = make_float2(q.x, q.y);
+    w[1] = make_float2(q.z, q.w);
+  } else {
+    w[0] = tile[idx];
+  }
+}
+
+// Exchanges alternate between NB tiles: with two tiles a pass writes the tile the previous exchange did not
+// read, so one barrier per exchange suffices (every reader of that tile has passed the previous barrier).
+template <int L, int COLS, int V, int NB, int P>
+__device__ __forceinline__ void col_chain(float2 (&v)[V][8], int ts, int cv, const PassTw<L>& tw,
+                                          float2* __restrict__ tiles) {
   using SC = Sched<L>;
   constexpr int R = SC::radix(P), NS = SC::ns(P);
-  pass_compute_reg<L, P>(v[0], tw);
-  pass_compute_reg<L, P>(v[1], tw);
+  float2* __restrict__ tile = tiles + (P % NB) * (L * COLS);
+#pragma unroll
+  for (int c = 0; c < V; ++c) pass_compute_reg<L, P>(v[c], tw);
   if constexpr (P + 1 < SC::NPASS) {
 #pragma unroll
     for (int i = 0; i < 8 / R; ++i)
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int l = pout<L, R, NS>(ts, i, r);
-        const float2 a0 = v[0][i * R + r], a1 = v[1][i * R + r];
-        *reinterpret_cast<float4*>(tile + l * COLS + cv * 2) = make_float4(a0.x, a0.y, a1.x, a1.y);
+        float2 w[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) w[c] = v[c][i * R + r];
+        tile_store<V>(tile, pout<L, R, NS>(ts, i, r) * COLS + cv * V, w);
       }
     __syncthreads();
     constexpr int R2 = SC::radix(P + 1);
@@ -291,21 +331,25 @@ __device__ __forceinline__ void col_chain(float2 (&v)[2][8], int ts, int cv, con
     for (int i = 0; i < 8 / R2; ++i)
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
-        const float4 q = *reinterpret_cast<const float4*>(tile + pin<L, R2>(ts, i, r) * COLS + cv * 2);
-        v[0][i * R2 + r] = make_float2(q.x, q.y);
-        v[1][i * R2 + r] = make_float2(q.z, q.w);
+        float2 w[V];
+        tile_load<V>(tile, pin<L, R2>(ts, i, r) * COLS + cv * V, w);
+#pragma unroll
+        for (int c = 0; c < V; ++c) v[c][i * R2 + r] = w[c];
       }
-    __syncthreads();
-    col_chain<L, COLS, P + 1>(v, ts, cv, tw, tile);
+    if constexpr (NB == 1) __syncthreads();
+    col_chain<L, COLS, V, NB, P + 1>(v, ts, cv, tw, tiles);
   }
 }
 
-template <int L, int COLS, int BITS, bool FAST>
-__global__ void __launch_bounds__(L * COLS / 16) k_colpass(ColArgs a) {
-  constexpr int CPR = COLS / 2;  // two adjacent columns per thread
+template <int L, int COLS, int V, int BITS, bool FAST>
+__global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass(ColArgs a) {
+  constexpr int CPR = COLS / V;  // column groups per row
   using SC = Sched<L>;
   constexpr int R0 = SC::R0, RL = SC::radix(SC::NPASS - 1), NSL = SC::ns(SC::NPASS - 1);
-  __shared__ __align__(16) float2 tile[L * COLS];
+  static_assert(RL == 8 && NSL == L / 8, "last pass must be radix 8");
+  // two tiles when they fit beside the workgroup's other needs (one workgroup per CU)
+  constexpr int NB = (2 * L * COLS * 8 <= 128 * 1024) ? 2 : 1;
+  __shared__ __align__(16) float2 tile[NB * L * COLS];
 
   const int blk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   const int cb = blk % a.n_colblk;
@@ -315,67 +359,69 @@ __global__ void __launch_bounds__(L * COLS / 16) k_colpass(ColArgs a) {
   const int f_begin = g * a.frames_per_block;
   const int f_end = min(a.n_frames, f_begin + a.frames_per_block);
   const int cv = (int)threadIdx.x % CPR, ts = (int)threadIdx.x / CPR;
-  const int n2b = cb * COLS + cv * 2;
+  const int n2b = cb * COLS + cv * V;
   const int sx = a.px[p], sy = a.py[p];
 
   PassTw<L> tw;
   tw.load(a.tw_col, ts);
-  // four-step twiddles W_N^(k1 * n2) of this thread's outputs, k1 = output index of the last pass
-  float2 fst[2][8];
+  // four-step twiddles W_N^(k1 * n2) of this thread's outputs, k1 = ts + r L/8 (the last pass's outputs)
+  float2 fst[V][8];
   const int mask = (1 << a.lo_bits) - 1;
 #pragma unroll
-  for (int i = 0; i < 8 / RL; ++i)
+  for (int r = 0; r < 8; ++r)
 #pragma unroll
-    for (int r = 0; r < RL; ++r) {
-      const int k1 = pout<L, RL, NSL>(ts, i, r);
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int m = k1 * (n2b + c);
-        fst[c][i * RL + r] = cmul(a.tw_hi[m >> a.lo_bits], a.tw_lo[m & mask]);
-      }
+    for (int c = 0; c < V; ++c) {
+      const int m = (ts + r * (L / 8)) * (n2b + c);
+      fst[c][r] = cmul(a.tw_hi[m >> a.lo_bits], a.tw_lo[m & mask]);
     }
-  ColLoader<BITS, FAST> cur;
+  ColLoader<BITS, FAST, V> cur;
   if (f_begin < f_end) cur.template fetch<L, R0>(a, (int64_t)f_begin * a.N, ts, n2b);
   for (int f = f_begin; f < f_end; ++f) {
-    float2 v[2][8];
+    float2 v[V][8];
     cur.template convert<L, R0>(v, a, ts, n2b, sx, sy);
-    if (f + 1 < f_end) cur.template fetch<L, R0>(a, (int64_t)(f + 1) * a.N, ts, n2b);
-    if (a.win) {  // the window is the same for every frame (and cached in L2)
+    if (a.win) {  // the window is the same for every frame (and cached in L2); read before the prefetch
 #pragma unroll
       for (int i = 0; i < 8 / R0; ++i)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
           const int64_t n = (int64_t)pin<L, R0>(ts, i, r) * a.N2 + n2b;
-          const float w0 = a.win[n], w1 = a.win[n + 1];
-          const int e = i * R0 + r;
-          v[0][e] = make_float2(v[0][e].x * w0, v[0][e].y * w0);
-          v[1][e] = make_float2(v[1][e].x * w1, v[1][e].y * w1);
+#pragma unroll
+          for (int c = 0; c < V; ++c) {
+            const float w = a.win[n + c];
+            v[c][i * R0 + r] = make_float2(v[c][i * R0 + r].x * w, v[c][i * R0 + r].y * w);
+          }
         }
     }
-    col_chain<L, COLS, 0>(v, ts, cv, tw, tile);
-    // the last pass is radix 8 with output k1 = ts + r L/8: write T[f][p][k1][n2b .. n2b + 1] (global stores:
-    // the next kernel reads them from every XCD)
-    static_assert(RL == 8 && NSL == L / 8, "last pass must be radix 8");
+    if (f + 1 < f_end) cur.template fetch<L, R0>(a, (int64_t)(f + 1) * a.N, ts, n2b);
+    col_chain<L, COLS, V, NB, 0>(v, ts, cv, tw, tile);
+    // with an odd number of exchanges per frame the next frame's first exchange reuses the tile the last
+    // one read: wait for every reader first
+    if constexpr (NB == 2 && (SC::NPASS - 1) % 2 == 1) __syncthreads();
+    // write T[f][p][k1][n2b ..] for k1 = ts + r L/8 (global stores: the next kernel reads them from every XCD)
     const uint32_t voff = 8u * (uint32_t)(ts * a.N2 + n2b);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const float2 o0 = cmul(v[0][r], fst[0][r]);
-      const float2 o1 = cmul(v[1][r], fst[1][r]);
-      typedef float f32x4 __attribute__((ext_vector_type(4)));
-      typedef __attribute__((address_space(1))) f32x4* gf4;
       const gbytes base = uniform_gptr(reinterpret_cast<const uint8_t*>(
           a.T + ((int64_t)f * a.P + p) * (int64_t)L * a.N2 + (int64_t)r * (L / 8) * a.N2));
-      const f32x4 q = {o0.x, o0.y, o1.x, o1.y};
-      *(gf4)(base + voff) = q;
+      const float2 o0 = cmul(v[0][r], fst[0][r]);
+      if constexpr (V == 2) {
+        const float2 o1 = cmul(v[1][r], fst[1][r]);
+        const f32x4 q = {o0.x, o0.y, o1.x, o1.y};
+        *(__attribute__((address_space(1))) f32x4*)(base + voff) = q;
+      } else {
+        const f32x2 q = {o0.x, o0.y};
+        *(__attribute__((address_space(1))) f32x2*)(base + voff) = q;
+      }
     }
   }
 }
 
 // ------------------------------------------------------------------------------------------------
 // row pass + two-for-one split + cross power + FP64 accumulation
-// UB units (row pairs) per workgroup, FB frames per batch; each thread transforms two row sequences
-// (frames fs and fs + FB/2 of a batch, same row and slot) and owns 8/FB channel slots for the
-// whole launch.  The next batch's input is fetched while the current one is transformed.
+// UB units (row pairs) per workgroup, FB frames per batch; each thread transforms SQ row sequences (frames
+// fs + j FB/SQ of a batch, same row and slot) and the first UB*L threads own one channel slot each for
+// the whole launch (SPT slots each when there are fewer threads than slots).  The next batch's input is
+// fetched while the current one is transformed.
 // Accumulated per channel and frame, unscaled: |A + B*|^2, |A - B*|^2 and i (A + B*) conj(A - B*)
 // with A = Z[k], B = Z[N - k]; the factor 1/4 that turns them into XX*, YY*, XY* is applied on output.
 // ------------------------------------------------------------------------------------------------
@@ -394,20 +440,20 @@ __device__ __forceinline__ void exchange_sync() {
   }
 }
 
-template <int L, int P>
-__device__ __forceinline__ void row_chain(float2 (&v0)[8], float2 (&v1)[8], int ts, const PassTw<L>& tw,
-                                          float2* __restrict__ s0, float2* __restrict__ s1) {
+template <int L, int SQ, int P>
+__device__ __forceinline__ void row_chain(float2 (&v)[SQ][8], int ts, const PassTw<L>& tw,
+                                          float2* const (&seq)[SQ]) {
   using SC = Sched<L>;
   constexpr int R = SC::radix(P), NS = SC::ns(P);
-  pass_compute_reg<L, P>(v0, tw);
-  pass_compute_reg<L, P>(v1, tw);
+#pragma unroll
+  for (int j = 0; j < SQ; ++j) pass_compute_reg<L, P>(v[j], tw);
 #pragma unroll
   for (int i = 0; i < 8 / R; ++i)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int o = pad8(pout<L, R, NS>(ts, i, r));
-      s0[o] = v0[i * R + r];
-      s1[o] = v1[i * R + r];
+      const int o = swz(pout<L, R, NS>(ts, i, r));
+#pragma unroll
+      for (int j = 0; j < SQ; ++j) seq[j][o] = v[j][i * R + r];
     }
   if constexpr (P + 1 < SC::NPASS) {
     exchange_sync<L>();
@@ -416,50 +462,52 @@ __device__ __forceinline__ void row_chain(float2 (&v0)[8], float2 (&v1)[8], int 
     for (int i = 0; i < 8 / R2; ++i)
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
-        const int o = pad8(pin<L, R2>(ts, i, r));
-        v0[i * R2 + r] = s0[o];
-        v1[i * R2 + r] = s1[o];
+        const int o = swz(pin<L, R2>(ts, i, r));
+#pragma unroll
+        for (int j = 0; j < SQ; ++j) v[j][i * R2 + r] = seq[j][o];
       }
     exchange_sync<L>();
-    row_chain<L, P + 1>(v0, v1, ts, tw, s0, s1);
+    row_chain<L, SQ, P + 1>(v, ts, tw, seq);
   }
 }
 
-template <int L, int UB, int FB>
-__global__ void __launch_bounds__(UB * FB * L / 8) k_rowpass(RowArgs a) {
-  constexpr int NT = UB * FB * L / 8;
-  constexpr int TPS = L / 8;             // threads per row sequence
-  constexpr int SPT = (UB * L) / NT;     // channel slots per thread (= 8 / FB)
-  constexpr int HB = FB / 2;             // frame pairs per batch
-  constexpr int SEQ = L + L / 8;         // padded sequence length in LDS
+template <int L, int UB, int FB, int SQ>
+__global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
+  constexpr int NT = UB * FB * L / (4 * SQ);
+  constexpr int TPS = L / 8;                       // threads per row sequence
+  constexpr int NCH = UB * L < NT ? UB * L : NT;   // threads that own channel slots
+  constexpr int SPT = (UB * L) / NCH;              // channel slots per owning thread
+  constexpr int FS = FB / SQ;                      // frame stride between a thread's sequences
+  constexpr int SEQ = L;                           // sequence length in LDS
   using SC = Sched<L>;
   constexpr int R0 = SC::R0;
   __shared__ __align__(16) float2 buf[UB * FB * 2 * SEQ];
   const int tid = (int)threadIdx.x;
   const int p = (int)blockIdx.y;
   const int U = a.N1 / 2;
-  // transform role: slot ts of row rr of frames fs and fs + HB of unit ub
+  // transform role: slot ts of row rr of frames fs + j FS (j < SQ) of unit ub
   const int ts = tid % TPS, q = tid / TPS;
-  const int rr = q & 1, fs = (q >> 1) % HB, ub = (q >> 1) / HB;
+  const int rr = q & 1, fs = (q >> 1) % FS, ub = (q >> 1) / FS;
   const int u = (int)blockIdx.x * UB + ub;
   const int row = (u == 0) ? (rr ? a.N1 / 2 : 0) : (rr ? a.N1 - u : u);
-  float2* s0 = buf + ((ub * FB + fs) * 2 + rr) * SEQ;
-  float2* s1 = buf + ((ub * FB + fs + HB) * 2 + rr) * SEQ;
+  float2* seq[SQ];
+#pragma unroll
+  for (int j = 0; j < SQ; ++j) seq[j] = buf + ((ub * FB + fs + j * FS) * 2 + rr) * SEQ;
 
   PassTw<L> tw;
   tw.load(a.tw_row, ts);
 
+  const bool owner = tid < NCH;
   double sxx[SPT], syy[SPT], sxr[SPT], sxi[SPT];
   double* accp[SPT];
 #pragma unroll
   for (int k = 0; k < SPT; ++k) {
-    const int id = tid + k * NT;
+    const int id = tid + k * NCH;
     const int ubc = id / L, s = id % L;
     const int uc = (int)blockIdx.x * UB + ubc;
     accp[k] = a.acc + ((int64_t)(p * U + uc) * 4) * L + s;
-    if (a.first) {
-      sxx[k] = syy[k] = sxr[k] = sxi[k] = 0.0;
-    } else {
+    sxx[k] = syy[k] = sxr[k] = sxi[k] = 0.0;
+    if (owner && !a.first) {
       sxx[k] = accp[k][0];
       syy[k] = accp[k][L];
       sxr[k] = accp[k][2 * L];
@@ -470,61 +518,64 @@ __global__ void __launch_bounds__(UB * FB * L / 8) k_rowpass(RowArgs a) {
   const int64_t fstride = (int64_t)a.P * a.N1 * L;  // float2 per frame
   const float2* src = a.T + ((int64_t)p * a.N1 + row) * (int64_t)L + ts;
   // frames past the end of the launch repeat the last frame (their products are never accumulated)
-  auto fetch = [&](float2 (&d0)[8], float2 (&d1)[8], int f0) {
-    const float2* pa = src + (int64_t)min(f0 + fs, a.n_frames - 1) * fstride;
-    const float2* pb = src + (int64_t)min(f0 + fs + HB, a.n_frames - 1) * fstride;
+  auto fetch = [&](float2 (&d)[SQ][8], int f0) {
 #pragma unroll
-    for (int i = 0; i < 8 / R0; ++i)
+    for (int j = 0; j < SQ; ++j) {
+      const float2* pj = src + (int64_t)min(f0 + fs + j * FS, a.n_frames - 1) * fstride;
 #pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        d0[i * R0 + r] = pa[i * (L / 8) + r * (L / R0)];
-        d1[i * R0 + r] = pb[i * (L / 8) + r * (L / R0)];
-      }
+      for (int i = 0; i < 8 / R0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) d[j][i * R0 + r] = pj[i * (L / 8) + r * (L / R0)];
+    }
   };
-  auto batch = [&](float2 (&v0)[8], float2 (&v1)[8], int f0) {
-    row_chain<L, 0>(v0, v1, ts, tw, s0, s1);
+  auto batch = [&](float2 (&v)[SQ][8], int f0) {
+    row_chain<L, SQ, 0>(v, ts, tw, seq);
     __syncthreads();
-    const int nf = min(FB, a.n_frames - f0);
+    if (owner) {
+      const int nf = min(FB, a.n_frames - f0);
 #pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-      const int id = tid + k * NT;
-      const int ubc = id / L, s = id % L;
-      const int uc = (int)blockIdx.x * UB + ubc;
-      const int half = s / (L / 2), k2 = s % (L / 2);
-      // bin (row, k2) pairs with bin N - k: rows k1 and N1 - k1 swap, k2 -> N2 - 1 - k2; row 0 -> N2 - k2
-      const int phalf = (uc == 0) ? half : 1 - half;
-      const int pk2 = (uc == 0 && half == 0) ? ((L - k2) & (L - 1)) : (L - 1 - k2);
-      const float2* fa = buf + (ubc * FB * 2 + half) * SEQ + pad8(k2);
-      const float2* fb = buf + (ubc * FB * 2 + phalf) * SEQ + pad8(pk2);
-      for (int g = 0; g < nf; ++g) {
-        const float2 A = fa[g * 2 * SEQ];
-        const float2 B = fb[g * 2 * SEQ];
-        const float sx_ = A.x + B.x, sy_ = A.y - B.y;   // A + conj(B) = 2 X
-        const float dx_ = A.x - B.x, dy_ = A.y + B.y;   // A - conj(B) = 2i Y
-        sxx[k] += (double)(sx_ * sx_ + sy_ * sy_);
-        syy[k] += (double)(dx_ * dx_ + dy_ * dy_);
-        sxr[k] += (double)(sx_ * dy_ - sy_ * dx_);      // Re of i (s conj d)
-        sxi[k] += (double)(sx_ * dx_ + sy_ * dy_);      // Im of i (s conj d)
+      for (int k = 0; k < SPT; ++k) {
+        const int id = tid + k * NCH;
+        const int ubc = id / L, s = id % L;
+        const int uc = (int)blockIdx.x * UB + ubc;
+        const int half = s / (L / 2), k2 = s % (L / 2);
+        // bin (row, k2) pairs with bin N - k: rows k1 and N1 - k1 swap, k2 -> N2 - 1 - k2; row 0 -> N2 - k2
+        const int phalf = (uc == 0) ? half : 1 - half;
+        const int pk2 = (uc == 0 && half == 0) ? ((L - k2) & (L - 1)) : (L - 1 - k2);
+        const float2* fa = buf + (ubc * FB * 2 + half) * SEQ + swz(k2);
+        const float2* fb = buf + (ubc * FB * 2 + phalf) * SEQ + swz(pk2);
+        for (int g = 0; g < nf; ++g) {
+          const float2 A = fa[g * 2 * SEQ];
+          const float2 B = fb[g * 2 * SEQ];
+          const float sx_ = A.x + B.x, sy_ = A.y - B.y;   // A + conj(B) = 2 X
+          const float dx_ = A.x - B.x, dy_ = A.y + B.y;   // A - conj(B) = 2i Y
+          sxx[k] += (double)(sx_ * sx_ + sy_ * sy_);
+          syy[k] += (double)(dx_ * dx_ + dy_ * dy_);
+          sxr[k] += (double)(sx_ * dy_ - sy_ * dx_);      // Re of i (s conj d)
+          sxi[k] += (double)(sx_ * dx_ + sy_ * dy_);      // Im of i (s conj d)
+        }
       }
     }
     __syncthreads();
   };
-  float2 a0[8], a1[8], b0[8], b1[8];
-  fetch(a0, a1, 0);
+  float2 va[SQ][8], vb[SQ][8];
+  fetch(va, 0);
   for (int f0 = 0; f0 < a.n_frames; f0 += 2 * FB) {
     const bool second = f0 + FB < a.n_frames;
-    if (second) fetch(b0, b1, f0 + FB);
-    batch(a0, a1, f0);
+    if (second) fetch(vb, f0 + FB);
+    batch(va, f0);
     if (!second) break;
-    if (f0 + 2 * FB < a.n_frames) fetch(a0, a1, f0 + 2 * FB);
-    batch(b0, b1, f0 + FB);
+    if (f0 + 2 * FB < a.n_frames) fetch(va, f0 + 2 * FB);
+    batch(vb, f0 + FB);
   }
+  if (owner) {
 #pragma unroll
-  for (int k = 0; k < SPT; ++k) {
-    accp[k][0] = sxx[k];
-    accp[k][L] = syy[k];
-    accp[k][2 * L] = sxr[k];
-    accp[k][3 * L] = sxi[k];
+    for (int k = 0; k < SPT; ++k) {
+      accp[k][0] = sxx[k];
+      accp[k][L] = syy[k];
+      accp[k][2 * L] = sxr[k];
+      accp[k][3 * L] = sxi[k];
+    }
   }
 }
 
@@ -539,15 +590,17 @@ __device__ __forceinline__ cd cdm(cd a, cd b) { return {a.x * b.x - a.y * b.y, a
 __device__ __forceinline__ cd cda(cd a, cd b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ cd cdc(cd a) { return {a.x, -a.y}; }
 
+constexpr int kOutThreads = 512;  // one channel of the 32 x 16 tile per thread
+
 template <bool STOKES>
-__global__ void __launch_bounds__(256) k_output(OutArgs a) {
+__global__ void __launch_bounds__(kOutThreads) k_output(OutArgs a) {
   constexpr int RT = 32, KT = 16;
   __shared__ double t[4][RT][KT + 1];
   const int L = a.N2, U = a.N1 / 2;
   const int rt = RT < a.N1 ? RT : a.N1;
   const int kt = KT < L / 2 ? KT : L / 2;
   const int r0 = (int)blockIdx.x * rt, k20 = (int)blockIdx.y * kt, p = (int)blockIdx.z;
-  for (int e = (int)threadIdx.x; e < rt * kt; e += 256) {
+  for (int e = (int)threadIdx.x; e < rt * kt; e += kOutThreads) {
     const int rl = e / kt, kk = e % kt;
     const int r = r0 + rl, k2 = k20 + kk;
     int u, half;
@@ -562,7 +615,7 @@ __global__ void __launch_bounds__(256) k_output(OutArgs a) {
   __syncthreads();
   double scale = a.scale;
   if (STOKES && a.sumw2_dev) scale = 1.0 / (a.n_frames * a.sumw2_dev[0]);
-  for (int e = (int)threadIdx.x; e < rt * kt; e += 256) {
+  for (int e = (int)threadIdx.x; e < rt * kt; e += kOutThreads) {
     const int kk = e / rt, rl = e % rt;
     const int64_t k = (int64_t)(k20 + kk) * a.N1 + r0 + rl;
     // stored sums are 4 XX*, 4 YY*, 4 XY* (exact power-of-two scale)
@@ -642,56 +695,70 @@ __global__ void __launch_bounds__(256) k_copy_words(const uint32_t* __restrict__
 // launchers
 // ------------------------------------------------------------------------------------------------
 
-template <int L, int COLS>
+// Column-pass shape per N1: columns per workgroup and columns per thread (tunable at build time).
+#ifndef PS_COLPASS_V
+#define PS_COLPASS_V 2
+#endif
+#ifndef PS_ROWPASS_SQ
+#define PS_ROWPASS_SQ 1
+#endif
+
+template <int L, int COLS, int V>
 static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, hipStream_t s) {
   const int groups = (a.n_frames + a.frames_per_block - 1) / a.frames_per_block;
-  const dim3 grid((unsigned)(groups * a.P * a.n_colblk)), block(L * COLS / 16);
+  const dim3 grid((unsigned)(groups * a.P * a.n_colblk)), block(L * COLS / (8 * V));
   switch (bits) {
-    case 2: hipLaunchKernelGGL((k_colpass<L, COLS, 2, false>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_colpass<L, COLS, 4, false>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_colpass<L, COLS, V, 2, false>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_colpass<L, COLS, V, 4, false>), grid, block, 0, s, a); break;
     case 8:
-      if (fast) hipLaunchKernelGGL((k_colpass<L, COLS, 8, true>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((k_colpass<L, COLS, 8, false>), grid, block, 0, s, a);
+      if (fast) hipLaunchKernelGGL((k_colpass<L, COLS, V, 8, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_colpass<L, COLS, V, 8, false>), grid, block, 0, s, a);
       break;
-    case 32: hipLaunchKernelGGL((k_colpass<L, COLS, 32, false>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_colpass<L, COLS, V, 32, false>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-int colpass_cols(int N1) { return N1 >= 2048 ? 4 : (N1 >= 1024 ? 8 : 16); }
+#ifndef PS_COLPASS_COLS
+#define PS_COLPASS_COLS 16
+#endif
+
+int colpass_cols(int N1) { return N1 >= 2048 ? 4 : (N1 >= 1024 ? 8 : PS_COLPASS_COLS); }
 
 hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, hipStream_t s) {
+  constexpr int V = PS_COLPASS_V;
   switch (N1) {
-    case 16: return colpass_bits<16, 16>(bits, fast, a, s);
-    case 32: return colpass_bits<32, 16>(bits, fast, a, s);
-    case 64: return colpass_bits<64, 16>(bits, fast, a, s);
-    case 128: return colpass_bits<128, 16>(bits, fast, a, s);
-    case 256: return colpass_bits<256, 16>(bits, fast, a, s);
-    case 512: return colpass_bits<512, 16>(bits, fast, a, s);
-    case 1024: return colpass_bits<1024, 8>(bits, fast, a, s);
-    case 2048: return colpass_bits<2048, 4>(bits, fast, a, s);
+    case 16: return colpass_bits<16, 16, 2>(bits, fast, a, s);
+    case 32: return colpass_bits<32, 16, 2>(bits, fast, a, s);
+    case 64: return colpass_bits<64, 16, 2>(bits, fast, a, s);
+    case 128: return colpass_bits<128, 16, 2>(bits, fast, a, s);
+    case 256: return colpass_bits<256, PS_COLPASS_COLS, V>(bits, fast, a, s);
+    case 512: return colpass_bits<512, PS_COLPASS_COLS, V>(bits, fast, a, s);
+    case 1024: return colpass_bits<1024, 8, 2>(bits, fast, a, s);
+    case 2048: return colpass_bits<2048, 4, 2>(bits, fast, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int L, int UB, int FB>
+template <int L, int UB, int FB, int SQ>
 static hipError_t rowpass_launch(const RowArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P), block(UB * FB * L / 8);
-  hipLaunchKernelGGL((k_rowpass<L, UB, FB>), grid, block, 0, s, a);
+  const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P), block(UB * FB * L / (4 * SQ));
+  hipLaunchKernelGGL((k_rowpass<L, UB, FB, SQ>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_rowpass(int N2, const RowArgs& a, hipStream_t s) {
+  constexpr int SQ = PS_ROWPASS_SQ;
   switch (N2) {
-    case 16: return rowpass_launch<16, 8, 8>(a, s);
-    case 32: return rowpass_launch<32, 8, 8>(a, s);
-    case 64: return rowpass_launch<64, 4, 8>(a, s);
-    case 128: return rowpass_launch<128, 2, 8>(a, s);
-    case 256: return rowpass_launch<256, 1, 8>(a, s);
-    case 512: return rowpass_launch<512, 1, 8>(a, s);
-    case 1024: return rowpass_launch<1024, 1, 4>(a, s);
-    case 2048: return rowpass_launch<2048, 1, 2>(a, s);
+    case 16: return rowpass_launch<16, 8, 8, 2>(a, s);
+    case 32: return rowpass_launch<32, 8, 8, 2>(a, s);
+    case 64: return rowpass_launch<64, 4, 8, 2>(a, s);
+    case 128: return rowpass_launch<128, 2, 8, 2>(a, s);
+    case 256: return rowpass_launch<256, 1, 8, SQ>(a, s);
+    case 512: return rowpass_launch<512, 1, 8, SQ>(a, s);
+    case 1024: return rowpass_launch<1024, 1, 4, 2>(a, s);
+    case 2048: return rowpass_launch<2048, 1, 2, 2>(a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -703,12 +770,12 @@ static dim3 output_grid(const OutArgs& a) {
 }
 
 hipError_t launch_stokes(const OutArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_output<true>), output_grid(a), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_output<true>), output_grid(a), dim3(kOutThreads), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_spectra(const OutArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_output<false>), output_grid(a), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_output<false>), output_grid(a), dim3(kOutThreads), 0, s, a);
   return hipGetLastError();
 }
 
