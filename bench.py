@@ -73,6 +73,31 @@ def kernel_bytes(kind: str, inst: dict, frames: int) -> float:
     return float("nan")
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1412_1256_amd", "csrc", "polaris_kernels.hip")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_paper_2e18.txt")
+KIND_OF = {"k_colpass": "colpass", "k_rowpass": "rowpass", "k_output": "stokes"}
+
+
+def counter_traffic() -> dict:
+    """HBM bytes per launch from the committed counter record, if it was taken on the current kernel source."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_RECORD):
+        return {}
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    out, rec_sha = {}, None
+    for line in open(TRAFFIC_RECORD):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "source_sha256":
+            rec_sha = f[1]
+        elif f[0] == "kernel":
+            name = line.split("kernel ", 1)[1].split(" fetch_kib")[0]
+            vals = dict(zip(f[-12::2], f[-11::2]))
+            out[KIND_OF.get(name.split("<")[0], name)] = float(vals["traffic_bytes"])
+    return out if rec_sha == sha else {}
+
+
 def cpu_baseline(inst: dict, reps: int):
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -146,8 +171,10 @@ def main():
                       "alg_bytes": nbytes, "GBps": nbytes / avg_s / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches_per_step"])
     kd = kernels[dom]
+    traffic = counter_traffic()
     roofline = {"kernel": dom, "bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": None}
+                "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": traffic.get(dom), "traffic_unit": "bytes per launch",
+                "alg_bytes": kd["alg_bytes"]}
 
     value = samples / dt / 1e9
     nominal_flop = S * F * 5 * N * math.log2(N)      # 5 N log2 N per N-point real frame per stream

@@ -165,16 +165,13 @@ T* ws_ptr(ps_plan_t plan, size_t off) {
 
 constexpr size_t kMaxTimed = 16384;
 
-// Launch f() on the plan's stream; while profiling, bracket it with a pair of events.
+// Launch f(launch) on the plan's stream; while profiling, the dispatch stamps a pair of events with the
+// kernel's own start and end.
 template <class F>
 hipError_t timed(ps_plan_t plan, int kind, F&& f) {
-  if (!plan->prof || plan->ev_used >= plan->ev_kind.size()) return f();
-  hipEvent_t a = plan->ev[2 * plan->ev_used], b = plan->ev[2 * plan->ev_used + 1];
-  hipError_t e = hipEventRecord(a, plan->stream);
-  if (e != hipSuccess) return e;
-  e = f();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(b, plan->stream);
+  if (!plan->prof || plan->ev_used >= plan->ev_kind.size()) return f(ps::Launch{plan->stream, nullptr, nullptr});
+  const ps::Launch l{plan->stream, plan->ev[2 * plan->ev_used], plan->ev[2 * plan->ev_used + 1]};
+  hipError_t e = f(l);
   if (e != hipSuccess) return e;
   plan->ev_kind[plan->ev_used++] = kind;
   return hipSuccess;
@@ -337,7 +334,7 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
       ca.lo_bits = I.m2;
       ca.T = ws_ptr<float2>(plan, I.off_T);
       hipError_t e = timed(plan, PS_KERNEL_COLPASS,
-                           [&] { return ps::launch_colpass((int)I.N1, I.cfg.bits, fast, ca, plan->stream); });
+                           [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cfg.bits, fast, ca, l); });
       if (e != hipSuccess) return hip_fail(e, "column pass launch");
       ps::RowArgs ra{};
       ra.T = ca.T;
@@ -347,7 +344,7 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
       ra.tw_row = ws_ptr<float2>(plan, I.off_tw_row);
       ra.acc = ws_ptr<double>(plan, I.off_acc);
       ra.first = I.first ? 1 : 0;
-      e = timed(plan, PS_KERNEL_ROWPASS, [&] { return ps::launch_rowpass((int)I.N2, ra, plan->stream); });
+      e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& l) { return ps::launch_rowpass((int)I.N2, ra, l); });
       if (e != hipSuccess) return hip_fail(e, "row pass launch");
       I.first = false;
       I.n_frames += nf;
@@ -375,7 +372,7 @@ ps_status ps_spectra(ps_plan_t plan, int32_t inst, double* out_dev, int64_t* n_f
   if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %d has no accumulated frames", inst);
   ps::OutArgs o = out_args(plan, I);
   o.spectra = out_dev;
-  hipError_t e = timed(plan, PS_KERNEL_SPECTRA, [&] { return ps::launch_spectra(o, plan->stream); });
+  hipError_t e = timed(plan, PS_KERNEL_SPECTRA, [&](const ps::Launch& l) { return ps::launch_spectra(o, l); });
   if (e != hipSuccess) return hip_fail(e, "spectra launch");
   if (n_frames) *n_frames = I.n_frames;
   return PS_OK;
@@ -401,7 +398,7 @@ ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv
     o.dterms = cal->dterms;
   }
   o.iquv = iquv_dev;
-  hipError_t e = timed(plan, PS_KERNEL_STOKES, [&] { return ps::launch_stokes(o, plan->stream); });
+  hipError_t e = timed(plan, PS_KERNEL_STOKES, [&](const ps::Launch& l) { return ps::launch_stokes(o, l); });
   if (e != hipSuccess) return hip_fail(e, "stokes launch");
   return PS_OK;
 }

@@ -55,11 +55,18 @@ struct OutArgs {
   double* spectra;          // [P][4][C] (raw sums) when producing spectra
 };
 
+// Stream of a launch, and optionally two events the dispatch itself stamps with the kernel's start and end.
+struct Launch {
+  hipStream_t stream;
+  hipEvent_t start;
+  hipEvent_t stop;
+};
+
 int colpass_cols(int N1);
-hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, hipStream_t s);
-hipError_t launch_rowpass(int N2, const RowArgs& a, hipStream_t s);
-hipError_t launch_stokes(const OutArgs& a, hipStream_t s);
-hipError_t launch_spectra(const OutArgs& a, hipStream_t s);
+hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, const Launch& l);
+hipError_t launch_rowpass(int N2, const RowArgs& a, const Launch& l);
+hipError_t launch_stokes(const OutArgs& a, const Launch& l);
+hipError_t launch_spectra(const OutArgs& a, const Launch& l);
 hipError_t launch_unpack(const void* packed, int bits, int S, int64_t n_time, float* out, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 

@@ -16,6 +16,7 @@
 //   * the output kernels gather the unit-major accumulators through LDS into natural channel order and
 //     apply the FP64 calibration and Eq. 2.
 // Twiddles come from tables generated on the host in FP64 and rounded once to FP32.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -703,18 +704,21 @@ __global__ void __launch_bounds__(256) k_copy_words(const uint32_t* __restrict__
 #define PS_ROWPASS_SQ 1
 #endif
 
+#define PS_LAUNCH(kernel, grid, block, l, ...) \
+  hipExtLaunchKernelGGL(kernel, grid, block, 0, (l).stream, (l).start, (l).stop, 0, __VA_ARGS__)
+
 template <int L, int COLS, int V>
-static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, hipStream_t s) {
+static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, const Launch& s) {
   const int groups = (a.n_frames + a.frames_per_block - 1) / a.frames_per_block;
   const dim3 grid((unsigned)(groups * a.P * a.n_colblk)), block(L * COLS / (8 * V));
   switch (bits) {
-    case 2: hipLaunchKernelGGL((k_colpass<L, COLS, V, 2, false>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_colpass<L, COLS, V, 4, false>), grid, block, 0, s, a); break;
+    case 2: PS_LAUNCH((k_colpass<L, COLS, V, 2, false>), grid, block, s, a); break;
+    case 4: PS_LAUNCH((k_colpass<L, COLS, V, 4, false>), grid, block, s, a); break;
     case 8:
-      if (fast) hipLaunchKernelGGL((k_colpass<L, COLS, V, 8, true>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((k_colpass<L, COLS, V, 8, false>), grid, block, 0, s, a);
+      if (fast) PS_LAUNCH((k_colpass<L, COLS, V, 8, true>), grid, block, s, a);
+      else PS_LAUNCH((k_colpass<L, COLS, V, 8, false>), grid, block, s, a);
       break;
-    case 32: hipLaunchKernelGGL((k_colpass<L, COLS, V, 32, false>), grid, block, 0, s, a); break;
+    case 32: PS_LAUNCH((k_colpass<L, COLS, V, 32, false>), grid, block, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -726,7 +730,7 @@ static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, hipStream_
 
 int colpass_cols(int N1) { return N1 >= 2048 ? 4 : (N1 >= 1024 ? 8 : PS_COLPASS_COLS); }
 
-hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, hipStream_t s) {
+hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, const Launch& s) {
   constexpr int V = PS_COLPASS_V;
   switch (N1) {
     case 16: return colpass_bits<16, 16, 2>(bits, fast, a, s);
@@ -742,13 +746,13 @@ hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, hipStre
 }
 
 template <int L, int UB, int FB, int SQ>
-static hipError_t rowpass_launch(const RowArgs& a, hipStream_t s) {
+static hipError_t rowpass_launch(const RowArgs& a, const Launch& s) {
   const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P), block(UB * FB * L / (4 * SQ));
-  hipLaunchKernelGGL((k_rowpass<L, UB, FB, SQ>), grid, block, 0, s, a);
+  PS_LAUNCH((k_rowpass<L, UB, FB, SQ>), grid, block, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_rowpass(int N2, const RowArgs& a, hipStream_t s) {
+hipError_t launch_rowpass(int N2, const RowArgs& a, const Launch& s) {
   constexpr int SQ = PS_ROWPASS_SQ;
   switch (N2) {
     case 16: return rowpass_launch<16, 8, 8, 2>(a, s);
@@ -769,13 +773,13 @@ static dim3 output_grid(const OutArgs& a) {
   return dim3((unsigned)(a.N1 / rt), (unsigned)(a.N2 / 2 / kt), (unsigned)a.P);
 }
 
-hipError_t launch_stokes(const OutArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_output<true>), output_grid(a), dim3(kOutThreads), 0, s, a);
+hipError_t launch_stokes(const OutArgs& a, const Launch& s) {
+  PS_LAUNCH((k_output<true>), output_grid(a), dim3(kOutThreads), s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_spectra(const OutArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_output<false>), output_grid(a), dim3(kOutThreads), 0, s, a);
+hipError_t launch_spectra(const OutArgs& a, const Launch& s) {
+  PS_LAUNCH((k_output<false>), output_grid(a), dim3(kOutThreads), s, a);
   return hipGetLastError();
 }
 
