@@ -65,7 +65,10 @@ struct Inst {
   bool fast = false;
   size_t off_tw_col = 0, off_tw_row = 0, off_tw_lo = 0, off_win = 0, off_taps = 0, off_sumw2 = 0;
   size_t off_T = 0, off_acc = 0, end = 0;
-  std::vector<float> tw_col, tw_row, tw_lo, win;
+  // differentiation form: window partial sums, Gb(A), per-unit partials, normaliser terms, partial dL/dw
+  size_t off_wpart = 0, off_ga = 0, off_red = 0, off_norm = 0, off_dw = 0;
+  bool taps() const { return cfg.window == PS_WIN_TAPS; }
+  std::vector<float> tw_col, tw_row, tw_lo, win, ones;
   double sumw2 = 0.0;
   bool first = true;
   int64_t n_frames = 0;
@@ -222,6 +225,14 @@ ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_
     I.off_sumw2 = off; off = align_up(off + 8);
     I.off_T = off; off = align_up(off + (size_t)I.chunk * (size_t)I.cfg.n_pairs * (size_t)I.N * 8);
     I.off_acc = off; off = align_up(off + I.acc_bytes());
+    const size_t U = (size_t)(I.N1 / 2), P = (size_t)I.cfg.n_pairs;
+    I.off_red = off; off = align_up(off + P * U * 5 * sizeof(double));
+    I.off_norm = off; off = align_up(off + P * sizeof(double));
+    if (I.taps()) {
+      I.off_wpart = off; off = align_up(off + (size_t)ps::window_taps_blocks(I.N) * sizeof(double));
+      I.off_ga = off; off = align_up(off + P * (size_t)I.C * 4 * sizeof(float));
+      I.off_dw = off; off = align_up(off + (size_t)ps::kMaxBwGroups * (size_t)I.N * sizeof(double));
+    }
     I.end = off;
   }
   plan->ws_bytes = off;
@@ -255,6 +266,10 @@ ps_status ps_bind(ps_plan_t plan, void* workspace_dev, size_t bytes, void* hip_s
     if ((st = upload(plan, I.off_tw_lo, I.tw_lo.data(), I.tw_lo.size() * 4)) != PS_OK) return st;
     if ((st = upload(plan, I.off_win, I.win.data(), I.win.size() * 4)) != PS_OK) return st;
     if ((st = upload(plan, I.off_sumw2, &I.sumw2, 8)) != PS_OK) return st;
+    if (I.taps()) {
+      I.ones.assign((size_t)I.cfg.n_taps, 1.0f);
+      if ((st = upload(plan, I.off_taps, I.ones.data(), I.ones.size() * 4)) != PS_OK) return st;
+    }
     I.first = true;
     I.n_frames = 0;
   }
@@ -268,8 +283,22 @@ ps_status ps_set_window_taps(ps_plan_t plan, int32_t inst, const float* taps_dev
   ps_status st = check_plan(plan, true);
   if (st != PS_OK) return st;
   if ((st = check_inst(plan, inst)) != PS_OK) return st;
-  (void)taps_dev;
-  return fail(PS_ERR_UNSUPPORTED, "learnable window taps are not built in this library");
+  Inst& I = plan->inst[(size_t)inst];
+  if (!I.taps()) return fail(PS_ERR_ARG, "instance %d does not use a PS_WIN_TAPS window", inst);
+  if (!taps_dev) return fail(PS_ERR_ARG, "null taps");
+  hipError_t e = ps::launch_copy(taps_dev, plan->ws + I.off_taps, (size_t)I.cfg.n_taps * 4, plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "taps copy");
+  ps::WinArgs w{};
+  w.taps = ws_ptr<float>(plan, I.off_taps);
+  w.n_taps = I.cfg.n_taps;
+  w.N = I.N;
+  w.win = ws_ptr<float>(plan, I.off_win);
+  w.partial = ws_ptr<double>(plan, I.off_wpart);
+  e = timed(plan, PS_KERNEL_OTHER, [&](const ps::Launch& l) {
+    return ps::launch_window_taps(w, ps::window_taps_blocks(I.N), ws_ptr<double>(plan, I.off_sumw2), l);
+  });
+  if (e != hipSuccess) return hip_fail(e, "window launch");
+  return PS_OK;
 }
 
 ps_status ps_reset(ps_plan_t plan) {
@@ -408,8 +437,127 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
   ps_status st = check_plan(plan, true);
   if (st != PS_OK) return st;
   if ((st = check_inst(plan, inst)) != PS_OK) return st;
-  (void)packed_dev; (void)n_samples; (void)cal; (void)dL_diquv_dev; (void)grad;
-  return fail(PS_ERR_UNSUPPORTED, "the adjoint is not built in this library");
+  Inst& I = plan->inst[(size_t)inst];
+  if (!dL_diquv_dev || !grad) return fail(PS_ERR_ARG, "null upstream gradient or gradient outputs");
+  if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %d has no accumulated frames", inst);
+  const bool want_taps = grad->d_taps != nullptr;
+  if (want_taps) {
+    if (!I.taps()) return fail(PS_ERR_ARG, "d_taps requested for an instance without a PS_WIN_TAPS window");
+    if (I.N2 > 512) return fail(PS_ERR_UNSUPPORTED, "the window adjoint is built for fft_len <= 2^18");
+    if (!packed_dev) return fail(PS_ERR_ARG, "null packed input");
+    if (n_samples < 0 || n_samples % I.N) return fail(PS_ERR_SIZE, "n_samples is not a multiple of fft_len");
+    if (n_samples / I.N != I.n_frames)
+      return fail(PS_ERR_STATE, "the input has %lld frames but the integration has %lld",
+                  (long long)(n_samples / I.N), (long long)I.n_frames);
+  }
+  if (I.N2 > 512) return fail(PS_ERR_UNSUPPORTED, "the adjoint is built for fft_len <= 2^18");
+  ps::BwChanArgs ca{};
+  ca.acc = ws_ptr<double>(plan, I.off_acc);
+  ca.N1 = (int32_t)I.N1;
+  ca.P = I.cfg.n_pairs;
+  ca.C = I.C;
+  ca.n_frames = (double)I.n_frames;
+  ca.sumw2 = ws_ptr<double>(plan, I.off_sumw2);
+  const double psi = cal ? cal->psi : 0.0;
+  ca.cos2psi = std::cos(2.0 * psi);
+  ca.sin2psi = std::sin(2.0 * psi);
+  if (cal) {
+    ca.gain_x = cal->gain_x;
+    ca.gain_y = cal->gain_y;
+    ca.dterms = cal->dterms;
+  }
+  ca.g_iquv = dL_diquv_dev;
+  ca.d_gain_x = grad->d_gain_x;
+  ca.d_gain_y = grad->d_gain_y;
+  ca.d_dterms = grad->d_dterms;
+  ca.g_a = want_taps ? ws_ptr<float>(plan, I.off_ga) : nullptr;
+  ca.red = ws_ptr<double>(plan, I.off_red);
+  ca.norm = ws_ptr<double>(plan, I.off_norm);
+  hipError_t e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_bw_channel((int)I.N2, ca, l); });
+  if (e != hipSuccess) return hip_fail(e, "backward channel launch");
+  if (!want_taps) return PS_OK;
+
+  const int64_t F = I.n_frames;
+  const int64_t frame_bytes = I.N * I.cfg.n_streams * I.cfg.bits / 8;
+  const uint8_t* base = static_cast<const uint8_t*>(packed_dev);
+  int groups_used = 0;
+  for (int64_t f0 = 0; f0 < F; f0 += I.chunk) {
+    const int nf = (int)((F - f0) < I.chunk ? (F - f0) : I.chunk);
+    ps::ColArgs col{};
+    col.in = base + f0 * frame_bytes;
+    const int64_t in_bytes = (int64_t)nf * frame_bytes;
+    col.in_bytes = in_bytes < (int64_t(1) << 31) ? (uint32_t)in_bytes : 0u;
+    const bool fast = I.fast && in_bytes < (int64_t(1) << 31);
+    col.N = I.N;
+    col.N2 = (int32_t)I.N2;
+    col.S = I.cfg.n_streams;
+    col.P = I.cfg.n_pairs;
+    for (int p = 0; p < 4; ++p) {
+      col.px[p] = I.cfg.pair_x[p];
+      col.py[p] = I.cfg.pair_y[p];
+    }
+    col.n_colblk = (int32_t)(I.N2 / ps::colpass_cols((int)I.N1));
+    col.n_frames = nf;
+    {
+      const int64_t per_frame = (int64_t)col.n_colblk * col.P;
+      int64_t groups = (plan->n_cu + per_frame / 2) / per_frame;
+      if (groups < 1) groups = 1;
+      if (groups > nf) groups = nf;
+      col.frames_per_block = (int32_t)((nf + groups - 1) / groups);
+    }
+    col.win = ws_ptr<float>(plan, I.off_win);
+    col.tw_col = ws_ptr<float2>(plan, I.off_tw_col);
+    col.tw_hi = col.tw_col;
+    col.tw_lo = ws_ptr<float2>(plan, I.off_tw_lo);
+    col.lo_bits = I.m2;
+    col.T = ws_ptr<float2>(plan, I.off_T);
+    e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cfg.bits, fast, col, l); });
+    if (e != hipSuccess) return hip_fail(e, "backward forward-recompute launch");
+    ps::BwRowArgs ra{};
+    ra.T = col.T;
+    ra.N1 = (int32_t)I.N1;
+    ra.P = I.cfg.n_pairs;
+    ra.n_frames = nf;
+    ra.tw_row = ws_ptr<float2>(plan, I.off_tw_row);
+    ra.tw_hi = col.tw_hi;
+    ra.tw_lo = col.tw_lo;
+    ra.lo_bits = I.m2;
+    ra.g_a = ca.g_a;
+    e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_bw_rowpass((int)I.N2, ra, l); });
+    if (e != hipSuccess) return hip_fail(e, "backward row pass launch");
+    ps::BwColArgs ba{};
+    ba.col = col;
+    ba.col.win = nullptr;
+    {
+      // at most kMaxBwGroups groups of frames, each with its own partial dL/dw
+      const int64_t per_frame = (int64_t)col.n_colblk * col.P;
+      int64_t groups = (plan->n_cu + per_frame / 2) / per_frame;
+      if (groups < 1) groups = 1;
+      const int64_t cap = ps::kMaxBwGroups / col.P > 0 ? ps::kMaxBwGroups / col.P : 1;
+      if (groups > cap) groups = cap;
+      if (groups > nf) groups = nf;
+      ba.col.frames_per_block = (int32_t)((nf + groups - 1) / groups);
+      const int used = (int)((nf + ba.col.frames_per_block - 1) / ba.col.frames_per_block);
+      if (f0 == 0) groups_used = used;
+    }
+    ba.dw = ws_ptr<double>(plan, I.off_dw);
+    ba.first = f0 == 0 ? 1 : 0;
+    e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_bw_colpass((int)I.N1, I.cfg.bits, fast, ba, l); });
+    if (e != hipSuccess) return hip_fail(e, "backward column pass launch");
+  }
+  ps::BwTapArgs ta{};
+  ta.dw = ws_ptr<double>(plan, I.off_dw);
+  ta.groups = groups_used * I.cfg.n_pairs;
+  ta.N = I.N;
+  ta.n_taps = I.cfg.n_taps;
+  ta.taps = ws_ptr<float>(plan, I.off_taps);
+  ta.sumw2 = ws_ptr<double>(plan, I.off_sumw2);
+  ta.norm = ca.norm;
+  ta.P = I.cfg.n_pairs;
+  ta.d_taps = grad->d_taps;
+  e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_bw_taps(ta, l); });
+  if (e != hipSuccess) return hip_fail(e, "tap gradient launch");
+  return PS_OK;
 }
 
 ps_status ps_state_bytes(ps_plan_t plan, int32_t inst, size_t* bytes) {

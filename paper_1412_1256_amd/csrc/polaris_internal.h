@@ -55,6 +55,63 @@ struct OutArgs {
   double* spectra;          // [P][4][C] (raw sums) when producing spectra
 };
 
+// ---- differentiation form ----------------------------------------------------------------------
+
+struct WinArgs {            // learnable window from its control points
+  const float* taps;
+  int32_t n_taps;
+  int64_t N;
+  float* win;               // [N]
+  double* partial;          // per-block sums of w^2
+};
+
+struct BwChanArgs {         // per-channel adjoint of Eq. 2 and the calibration
+  const double* acc;        // [P][N1/2][4][N2]
+  int32_t N1, P;
+  int64_t C;
+  double n_frames;
+  const double* sumw2;
+  const float* gain_x;
+  const float* gain_y;
+  const float* dterms;
+  double cos2psi, sin2psi;
+  const float* g_iquv;      // [P][4][C] upstream gradient
+  float* d_gain_x;          // [P][C] complex, or nullptr
+  float* d_gain_y;
+  float* d_dterms;          // [P][4], or nullptr
+  float* g_a;               // [P][N1/2][4][N2] Gb(A) (00, 11, Re 01, Im 01), or nullptr
+  double* red;              // [P][N1/2][5] unit partials
+  double* norm;             // [P] Re tr(Gb(M)^H M)
+};
+
+struct BwRowArgs {          // backward row pass (in place on the inter-pass buffer)
+  float2* T;
+  int32_t N1, P, n_frames;
+  const float2* tw_row;
+  const float2* tw_hi;
+  const float2* tw_lo;
+  int32_t lo_bits;
+  const float* g_a;
+};
+
+struct BwColArgs {          // backward column pass
+  ColArgs col;              // col.T is the row pass's output; col.in the packed samples
+  double* dw;               // [groups][P][N] partial dL/dw
+  int32_t first;            // 1: write the partials instead of adding to them
+};
+
+struct BwTapArgs {          // tap gradient
+  const double* dw;         // [groups][N] partials to sum in order
+  int32_t groups;
+  int64_t N;
+  int32_t n_taps;
+  const float* taps;
+  const double* sumw2;
+  const double* norm;       // [P]
+  int32_t P;
+  float* d_taps;
+};
+
 // Stream of a launch, and optionally two events the dispatch itself stamps with the kernel's start and end.
 struct Launch {
   hipStream_t stream;
@@ -68,6 +125,14 @@ hipError_t launch_rowpass(int N2, const RowArgs& a, const Launch& l);
 hipError_t launch_stokes(const OutArgs& a, const Launch& l);
 hipError_t launch_spectra(const OutArgs& a, const Launch& l);
 hipError_t launch_unpack(const void* packed, int bits, int S, int64_t n_time, float* out, hipStream_t s);
+
+constexpr int kMaxBwGroups = 32;  // partial dL/dw buffers of the backward column pass (groups x pairs)
+int window_taps_blocks(int64_t N);
+hipError_t launch_window_taps(const WinArgs& a, int n_blocks, double* sumw2, const Launch& l);
+hipError_t launch_bw_channel(int N2, const BwChanArgs& a, const Launch& l);
+hipError_t launch_bw_rowpass(int N2, const BwRowArgs& a, const Launch& l);
+hipError_t launch_bw_colpass(int N1, int bits, bool fast, const BwColArgs& a, const Launch& l);
+hipError_t launch_bw_taps(const BwTapArgs& a, const Launch& l);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace ps
