@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-reps", type=int, default=5, help="oracle repetitions of the whole integration")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time (whole integrations)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
     return ap.parse_args()
 
@@ -98,21 +98,79 @@ def counter_traffic() -> dict:
     return out if rec_sha == sha else {}
 
 
-def cpu_baseline(inst: dict, reps: int):
+def cpu_baseline(inst: dict, min_seconds: float):
+    """Whole integrations by the oracle, repeated until at least min_seconds of CPU work have run."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
     # one untimed run builds/loads the oracle
     acc, nf, s2, _ = oracle.run_instance(inst, nthreads=threads)
+    reps = 0
     t0 = time.perf_counter()
-    for _ in range(reps):
+    while True:
         acc, nf, s2, _ = oracle.run_instance(inst, nthreads=threads)
         oracle.stokes(acc, nf, s2, psi=0.25)
-    dt = time.perf_counter() - t0
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
     samples = inst["n_samples"] * inst["n_streams"] * reps
     return {"value": samples / dt / 1e9, "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
             "sample": f"{reps} full integrations of the paper-shaped workload ({inst['n_frames']} frames of "
                       f"2x2^18 int8 samples each), FP64 radix-2 oracle incl. Stokes",
             "seconds": dt, "x_realtime": reps * inst["n_samples"] / SAMPLE_RATE / dt}
+
+
+def time_steps(torch, dev, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize(dev)
+    return (time.perf_counter() - t0) / steps
+
+
+def differentiation_form(pk, torch, dev, steps, warmup):
+    """fwd+bwd vs plain on the differentiation workload: 2 int8 pols, 2^16-point frames, 128 frames, learnable
+    per-channel gains, leakage terms and a 64-tap window; the backward recomputes every frame."""
+    import numpy as np
+    import synth
+    inst = synth.make_differentiation()
+    N, F, S = inst["fft_len"], inst["n_frames"], inst["n_streams"]
+    samples = F * N * S
+    packed = torch.from_numpy(inst["packed"]).to(dev)
+    gx = torch.from_numpy(inst["init_gain_x"].astype(np.complex64)[None]).to(dev)
+    gy = torch.from_numpy(inst["init_gain_y"].astype(np.complex64)[None]).to(dev)
+    dt = torch.zeros((1, 2), dtype=torch.complex64, device=dev)
+    taps = torch.ones(64, dtype=torch.float32, device=dev)
+    g = torch.randn((1, 4, N // 2), dtype=torch.float32, device=dev, generator=torch.Generator(dev).manual_seed(5))
+    plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev)
+    plain = pk.Plan([pk.Instance(fft_len=N, bits=8)], device=dev)
+    out = torch.empty((1, 4, N // 2), dtype=torch.float32, device=dev)
+
+    def plain_step():
+        plain.reset()
+        plain.accumulate(packed)
+        plain.stokes(out=out)
+
+    def fwd():
+        plan.set_window_taps(taps)
+        plan.reset()
+        plan.accumulate(packed)
+        plan.stokes(gain_x=gx, gain_y=gy, dterms=dt, out=out)
+
+    def fwd_bwd():
+        fwd()
+        plan.calibrate_backward(packed, g, gain_x=gx, gain_y=gy, dterms=dt)
+
+    t_plain = time_steps(torch, dev, plain_step, steps, warmup)
+    t_fwd = time_steps(torch, dev, fwd, steps, warmup)
+    t_fb = time_steps(torch, dev, fwd_bwd, steps, warmup)
+    return {"workload": "2 int8 pols, 2^16-pt frames, 128 frames (0.524 s), learnable gains, leakage and 64 taps",
+            "plain_us": t_plain * 1e6, "fwd_us": t_fwd * 1e6, "fwd_bwd_us": t_fb * 1e6,
+            "fwd_bwd_vs_plain": t_fb / t_plain, "fwd_bwd_vs_fwd": t_fb / t_fwd,
+            "fwd_bwd_Gsamples_per_s": samples / t_fb / 1e9, "fwd_bwd_x_realtime": F * N / SAMPLE_RATE / t_fb}
 
 
 def main():
@@ -195,8 +253,9 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    out["fwd_bwd"] = differentiation_form(pk, torch, dev, max(5, args.steps // 2), 2)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_reps)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
