@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true", help="skip the 16-bit precision-form section")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time (whole integrations)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
     return ap.parse_args()
@@ -173,6 +174,70 @@ def differentiation_form(pk, torch, dev, steps, warmup):
             "fwd_bwd_Gsamples_per_s": samples / t_fb / 1e9, "fwd_bwd_x_realtime": F * N / SAMPLE_RATE / t_fb}
 
 
+def kernel_bytes_mx(kind: str, inst: dict, frames: int) -> float:
+    """Algorithmic HBM bytes of one launch of a precision-form kernel (16-bit complex intermediate)."""
+    N, S, P, b = inst["fft_len"], inst["n_streams"], len(inst["pairs"]), inst["bits"]
+    C = N // 2
+    if kind == "colpass":   # packed input once + 16-bit complex intermediate written once
+        return frames * N * S * b / 8 + frames * P * N * 4
+    if kind == "rowpass":   # intermediate read once + FP64 accumulators read and written
+        return frames * P * N * 4 + 2 * P * C * 32
+    return kernel_bytes(kind, inst, frames)
+
+
+def precision_form(pk, torch, dev, steps, warmup, with_oracle=True):
+    """Plain FP32 path vs the 16-bit matrix-core passes (compensated FP32 integration) on the precision
+    workload: 4 int8 streams (X0, X1, Y0, Y1; pairs (0,2), (1,3)), 2^18-point frames, 610 frames (9.99 s).
+    Error of each Stokes product against the FP64 oracle: max_k |P - P_ref| / I_ref,k."""
+    import numpy as np
+    import oracle
+    import synth
+    inst = synth.make_precision(n_frames=610)
+    N, S, F, P = inst["fft_len"], inst["n_streams"], inst["n_frames"], len(inst["pairs"])
+    samples = F * N * S
+    packed = torch.from_numpy(inst["packed"]).to(dev)
+    ref = None
+    if with_oracle:
+        acc, nf, s2, _ = oracle.run_instance(inst, nthreads=min(16, os.cpu_count() or 1))
+        ref = oracle.stokes(acc, nf, s2)
+    res = {"workload": "4 int8 streams (2 bands x 2 pols), 2^18-pt rect frames, 610 frames (9.99 s), Stokes of "
+                       "pairs (0,2), (1,3)", "samples_per_step": samples}
+    out = torch.empty((P, 4, N // 2), dtype=torch.float32, device=dev)
+    for prec, accum in (("fp32", "fp64"), ("fp16", "kahan32"), ("bf16", "kahan32")):
+        plan = pk.Plan([pk.Instance.from_synth(inst, precision=prec, accum=accum, chunk_frames=128)], device=dev)
+
+        def step():
+            plan.reset()
+            plan.accumulate(packed)
+            plan.stokes(out=out)
+
+        t = time_steps(torch, dev, step, steps, warmup)
+        plan.profile_enable(True)
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize(dev)
+        prof = plan.profile_read()
+        plan.profile_enable(False)
+        kb = kernel_bytes if prec == "fp32" else kernel_bytes_mx
+        kern = {}
+        for k, (ms, n) in prof.items():
+            # algorithmic bytes of the whole step; the passes run once per chunk of 128 frames
+            nbytes = kb(k, inst, F)
+            if k == "rowpass":
+                nbytes = F * P * N * (8 if prec == "fp32" else 4) + (n / 2) * 2 * P * (N // 2) * 32
+            kern[k] = {"us_per_step": ms / 2 * 1e3, "launches_per_step": n / 2,
+                       "GBps": nbytes / (ms / 2 / 1e3) / 1e9}
+        r = {"us_per_step": t * 1e6, "Gsamples_per_s": samples / t / 1e9, "x_realtime": F * N / SAMPLE_RATE / t,
+             "kernels": kern}
+        if ref is not None:
+            got = out.cpu().numpy().astype(np.float64)
+            e = np.max(np.abs(got - ref) / ref[:, 0:1, :], axis=2)
+            r["err_vs_oracle_IQUV"] = [float(v) for v in e.max(axis=0)]
+        res[f"{prec}_{accum}"] = r
+        del plan
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -254,6 +319,9 @@ def main():
         "roofline": roofline,
     }
     out["fwd_bwd"] = differentiation_form(pk, torch, dev, max(5, args.steps // 2), 2)
+    if not args.no_precision:
+        out["precision_form"] = precision_form(pk, torch, dev, max(3, args.steps // 10), 1,
+                                               with_oracle=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out), flush=True)

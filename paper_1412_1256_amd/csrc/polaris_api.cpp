@@ -69,6 +69,11 @@ struct Inst {
   size_t off_wpart = 0, off_ga = 0, off_red = 0, off_norm = 0, off_dw = 0;
   bool taps() const { return cfg.window == PS_WIN_TAPS; }
   std::vector<float> tw_col, tw_row, tw_lo, win, ones;
+  // precision form: 16-bit DFT matrices of radix 16 and 32 (hi, lo), stage twiddles of the two passes
+  bool mx() const { return cfg.precision != PS_PREC_FP32; }
+  size_t off_mx16 = 0, off_mx32 = 0, off_tws_col = 0, off_tws_row = 0;
+  std::vector<uint32_t> mx16, mx32;
+  std::vector<float> tws_col, tws_row;
   double sumw2 = 0.0;
   bool first = true;
   int64_t n_frames = 0;
@@ -116,18 +121,98 @@ ps_status validate_instance(const ps_instance& c, int idx) {
     return fail(PS_ERR_ARG, "instance %d: n_taps %d not in 2..4096", idx, c.n_taps);
   if (c.precision != PS_PREC_FP32 && c.precision != PS_PREC_FP16 && c.precision != PS_PREC_BF16)
     return fail(PS_ERR_ARG, "instance %d: unknown precision %d", idx, c.precision);
-  if (c.precision != PS_PREC_FP32)
-    return fail(PS_ERR_UNSUPPORTED, "instance %d: reduced-precision passes are not built in this library", idx);
   if (c.accum != PS_ACC_FP64 && c.accum != PS_ACC_KAHAN32)
     return fail(PS_ERR_ARG, "instance %d: unknown accumulator %d", idx, c.accum);
-  if (c.accum != PS_ACC_FP64)
-    return fail(PS_ERR_UNSUPPORTED, "instance %d: only FP64 accumulation is built with FP32 passes", idx);
+  if (c.precision == PS_PREC_FP32 && c.accum != PS_ACC_FP64)
+    return fail(PS_ERR_UNSUPPORTED, "instance %d: FP32 passes accumulate in FP64 only", idx);
+  if (c.precision != PS_PREC_FP32) {
+    if (m < 16 || m > 18)
+      return fail(PS_ERR_UNSUPPORTED, "instance %d: 16-bit passes are built for fft_len 2^16 .. 2^18, not 2^%d", idx, m);
+    if (c.window == PS_WIN_TAPS)
+      return fail(PS_ERR_UNSUPPORTED, "instance %d: the learnable window runs with FP32 passes only", idx);
+  }
   if (c.chunk_frames < 0 || c.chunk_frames > 65536)
     return fail(PS_ERR_ARG, "instance %d: chunk_frames %d not in 0..65536", idx, c.chunk_frames);
   return PS_OK;
 }
 
+// x rounded to nearest even in a binary format with p significand bits and minimum normal exponent emin
+// (subnormals below it), evaluated exactly in FP64.
+double round_to_format(double x, int p, int emin) {
+  if (x == 0.0 || !std::isfinite(x)) return x;
+  int e = 0;
+  (void)std::frexp(x, &e);  // |x| = f 2^e, f in [0.5, 1): unit in the last place 2^(e - p)
+  int q = e - p;
+  if (e - 1 < emin) q = emin - p + 1;
+  return std::ldexp(std::nearbyint(std::ldexp(x, -q)), q);
+}
+
+// bit pattern of a value already representable in the format
+uint16_t format_bits(double v, int prec) {
+  if (prec == PS_PREC_BF16) {
+    const float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (uint16_t)(u >> 16);
+  }
+  if (v == 0.0) return std::signbit(v) ? 0x8000 : 0;
+  const uint16_t sign = v < 0 ? 0x8000 : 0;
+  const double a = std::fabs(v);
+  int e = 0;
+  const double f = std::frexp(a, &e);  // a = f 2^e
+  if (e - 1 >= -14) {
+    const uint32_t mant = (uint32_t)std::ldexp(2.0 * f - 1.0, 10);
+    return (uint16_t)(sign | (uint32_t)(e - 1 + 15) << 10 | mant);
+  }
+  return (uint16_t)(sign | (uint32_t)std::ldexp(a, 24));  // subnormal: multiples of 2^-24
+}
+
+// DFT matrix of radix r (outputs q, inputs c: W_r^(q c)) as a 2r x 2r real block in the A-operand lane
+// layout of the 16x16x32 matrix instructions, split as hi + lo in the 16-bit format:
+//   [hl][tile t = 2*qb + part][K-step s][lane l][word jj], lane l = 16 g + i:
+//   output q = 16 qb + i (real part for part 0, imaginary for 1);
+//   word jj holds the coefficients of input c = 16 s + 4 g + jj: real input in the low half, imaginary high.
+// Re Y = cos * xr + sin * xi, Im Y = -sin * xr + cos * xi with the angle 2 pi q c / r.
+void dft_matrix(std::vector<uint32_t>& out, int r, int prec) {
+  const int NT = 2 * r / 16, NS = r / 16;
+  const int p = prec == PS_PREC_BF16 ? 8 : 11, emin = prec == PS_PREC_BF16 ? -126 : -14;
+  out.assign((size_t)2 * NT * NS * 64 * 4, 0u);
+  for (int hl = 0; hl < 2; ++hl)
+    for (int t = 0; t < NT; ++t)
+      for (int s = 0; s < NS; ++s)
+        for (int l = 0; l < 64; ++l)
+          for (int jj = 0; jj < 4; ++jj) {
+            const int q = 16 * (t / 2) + l % 16, part = t % 2, c = 16 * s + 4 * (l / 16) + jj;
+            const double a = kTwoPi * (double)((q * c) % r) / (double)r;
+            const double cs = std::cos(a), sn = std::sin(a);
+            const double v[2] = {part == 0 ? cs : -sn, part == 0 ? sn : cs};  // coefficient of xr, xi
+            uint32_t word = 0;
+            for (int k = 0; k < 2; ++k) {
+              const double hi = round_to_format(v[k], p, emin);
+              const double val = hl == 0 ? hi : round_to_format(v[k] - hi, p, emin);
+              word |= (uint32_t)format_bits(val, prec) << (16 * k);
+            }
+            out[((((size_t)hl * NT + t) * NS + s) * 64 + l) * 4 + jj] = word;
+          }
+}
+
+// W_len^m / 16 for m < len (stage twiddle of a 16 x R split, with the scale of the radix-16 stage)
+void stage_twiddles(std::vector<float>& out, int64_t len) {
+  out.resize(2 * (size_t)len);
+  for (int64_t m = 0; m < len; ++m) {
+    const double a = kTwoPi * (double)m / (double)len;
+    out[2 * m] = (float)(std::cos(a) / 16.0);
+    out[2 * m + 1] = (float)(-std::sin(a) / 16.0);
+  }
+}
+
 void build_tables(Inst& I) {
+  if (I.mx()) {
+    dft_matrix(I.mx16, 16, I.cfg.precision);
+    if (I.N1 == 512 || I.N2 == 512) dft_matrix(I.mx32, 32, I.cfg.precision);
+    stage_twiddles(I.tws_col, I.N1);
+    stage_twiddles(I.tws_row, I.N2);
+  }
   twiddle_table(I.tw_col, I.N1, I.N1);
   twiddle_table(I.tw_row, I.N2, I.N2);
   twiddle_table(I.tw_lo, I.N, I.N2);  // W_N^m, m < N2; W_N^(q*N2) = W_N1^q reuses tw_col
@@ -187,6 +272,50 @@ ps_status upload(ps_plan_t plan, size_t off, const void* src, size_t bytes) {
   return PS_OK;
 }
 
+// Precision form of one chunk: 16-bit column pass (16 columns per workgroup, one workgroup per CU) and
+// 16-bit row pass with FP64 or compensated FP32 sums (one workgroup per unit and pair).
+ps_status accumulate_mx(ps_plan_t plan, Inst& I, const ps::ColArgs& ca) {
+  ps::MxColArgs m{};
+  m.col = ca;
+  m.col.n_colblk = (int32_t)(I.N2 / 16);
+  const int64_t per_frame = (int64_t)m.col.n_colblk * ca.P;
+  int64_t groups = (plan->n_cu + per_frame / 2) / per_frame;
+  if (groups < 1) groups = 1;
+  if (groups > ca.n_frames) groups = ca.n_frames;
+  m.col.frames_per_block = (int32_t)((ca.n_frames + groups - 1) / groups);
+  groups = (ca.n_frames + m.col.frames_per_block - 1) / m.col.frames_per_block;
+  m.m.a16 = ws_ptr<uint32_t>(plan, I.off_mx16);
+  m.m.aR = ws_ptr<uint32_t>(plan, I.N1 == 512 ? I.off_mx32 : I.off_mx16);
+  m.m.tws = ws_ptr<float2>(plan, I.off_tws_col);
+  m.T = ws_ptr<uint32_t>(plan, I.off_T);
+  const ps_instance& c = I.cfg;
+  m.mode = 0;
+  if (c.bits == 8 && c.n_streams == 2 && c.n_pairs == 1 && c.pair_x[0] == 0 && c.pair_y[0] == 1) m.mode = 1;
+  if (c.bits == 8 && c.n_streams == 4) m.mode = 2;
+  const int n_blocks = (int)(groups * per_frame);
+  hipError_t e = timed(plan, PS_KERNEL_COLPASS, [&](const ps::Launch& l) {
+    return ps::launch_colpass_mx((int)I.N1, c.precision, c.bits, m, n_blocks, l);
+  });
+  if (e != hipSuccess) return hip_fail(e, "16-bit column pass launch");
+  ps::MxRowArgs r{};
+  r.T = m.T;
+  r.N1 = (int32_t)I.N1;
+  r.P = c.n_pairs;
+  r.n_frames = ca.n_frames;
+  r.m.a16 = m.m.a16;
+  r.m.aR = ws_ptr<uint32_t>(plan, I.N2 == 512 ? I.off_mx32 : I.off_mx16);
+  r.m.tws = ws_ptr<float2>(plan, I.off_tws_row);
+  r.acc = ws_ptr<double>(plan, I.off_acc);
+  r.first = I.first ? 1 : 0;
+  // the stages scale Z by 1 / (16 * (N1 / 16) * 16) = 1 / (16 N1); products by its square
+  r.unscale = std::ldexp(1.0, 2 * (4 + I.m1));
+  e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& l) {
+    return ps::launch_rowpass_mx((int)I.N2, c.precision, c.accum, r, l);
+  });
+  if (e != hipSuccess) return hip_fail(e, "16-bit row pass launch");
+  return PS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -223,6 +352,12 @@ ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_
     I.off_win = off; off = align_up(off + (I.win.empty() ? 0 : (size_t)I.N * 4));
     I.off_taps = off; off = align_up(off + (I.cfg.window == PS_WIN_TAPS ? (size_t)I.cfg.n_taps * 4 : 0));
     I.off_sumw2 = off; off = align_up(off + 8);
+    if (I.mx()) {
+      I.off_mx16 = off; off = align_up(off + I.mx16.size() * 4);
+      I.off_mx32 = off; off = align_up(off + I.mx32.size() * 4);
+      I.off_tws_col = off; off = align_up(off + I.tws_col.size() * 4);
+      I.off_tws_row = off; off = align_up(off + I.tws_row.size() * 4);
+    }
     I.off_T = off; off = align_up(off + (size_t)I.chunk * (size_t)I.cfg.n_pairs * (size_t)I.N * 8);
     I.off_acc = off; off = align_up(off + I.acc_bytes());
     const size_t U = (size_t)(I.N1 / 2), P = (size_t)I.cfg.n_pairs;
@@ -266,6 +401,12 @@ ps_status ps_bind(ps_plan_t plan, void* workspace_dev, size_t bytes, void* hip_s
     if ((st = upload(plan, I.off_tw_lo, I.tw_lo.data(), I.tw_lo.size() * 4)) != PS_OK) return st;
     if ((st = upload(plan, I.off_win, I.win.data(), I.win.size() * 4)) != PS_OK) return st;
     if ((st = upload(plan, I.off_sumw2, &I.sumw2, 8)) != PS_OK) return st;
+    if (I.mx()) {
+      if ((st = upload(plan, I.off_mx16, I.mx16.data(), I.mx16.size() * 4)) != PS_OK) return st;
+      if ((st = upload(plan, I.off_mx32, I.mx32.data(), I.mx32.size() * 4)) != PS_OK) return st;
+      if ((st = upload(plan, I.off_tws_col, I.tws_col.data(), I.tws_col.size() * 4)) != PS_OK) return st;
+      if ((st = upload(plan, I.off_tws_row, I.tws_row.data(), I.tws_row.size() * 4)) != PS_OK) return st;
+    }
     if (I.taps()) {
       I.ones.assign((size_t)I.cfg.n_taps, 1.0f);
       if ((st = upload(plan, I.off_taps, I.ones.data(), I.ones.size() * 4)) != PS_OK) return st;
@@ -362,6 +503,13 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
       ca.tw_lo = ws_ptr<float2>(plan, I.off_tw_lo);
       ca.lo_bits = I.m2;
       ca.T = ws_ptr<float2>(plan, I.off_T);
+      if (I.mx()) {
+        ps_status ms = accumulate_mx(plan, I, ca);
+        if (ms != PS_OK) return ms;
+        I.first = false;
+        I.n_frames += nf;
+        continue;
+      }
       hipError_t e = timed(plan, PS_KERNEL_COLPASS,
                            [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cfg.bits, fast, ca, l); });
       if (e != hipSuccess) return hip_fail(e, "column pass launch");

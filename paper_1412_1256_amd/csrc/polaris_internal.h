@@ -55,6 +55,38 @@ struct OutArgs {
   double* spectra;          // [P][4][C] (raw sums) when producing spectra
 };
 
+// ---- precision form (FP16 / BF16 blocked-DFT passes on the matrix cores) -----------------------
+//
+// Each N1- and N2-point DFT is split as 16 x R (R = 16 or 32): n = R*a + b, k = kappa + 16*kb.  Stage A is
+// a 16-point DFT over a for every b, stage B an R-point DFT over b for every kappa; both are products of
+// the DFT matrix (as a 2r x 2r real block, FP16/BF16 hi + lo parts) with 16 vectors at a time, FP32
+// accumulate.  Between the stages the twiddle W^(b*kappa) is applied in FP32 and the result rounded to
+// the 16-bit format; every stage is scaled by 1/r (exact), so stored values never exceed the input range.
+// The inter-pass buffer holds packed 16-bit complex values [n_frames][P][N1][N2].
+
+struct MxMats {
+  const uint32_t* a16;      // radix-16 matrix, A-operand lane layout [hi, lo][2 tiles][64 lanes][4 words]
+  const uint32_t* aR;       // radix-R matrix [hi, lo][2R/16 tiles][R/16 K-steps][64 lanes][4 words]
+  const float2* tws;        // W_L^m / 16, m < L (stage twiddle with the 1/16 of stage A)
+};
+
+struct MxColArgs {
+  ColArgs col;              // geometry and input; col.T is unused
+  MxMats m;
+  uint32_t* T;              // packed 16-bit complex [n_frames][P][N1][N2]
+  int32_t mode;             // input access: 0 generic, 1 int8 two streams pair (0,1), 2 int8 four streams
+};
+
+struct MxRowArgs {
+  const uint32_t* T;
+  int32_t N1, P, n_frames;
+  MxMats m;
+  double* acc;              // [P][N1/2][4][N2] FP64, unscaled
+  int32_t first;
+  double unscale;           // 1 / (product scale)^2 of the stages: multiplies the sums before they are stored
+};
+
+
 // ---- differentiation form ----------------------------------------------------------------------
 
 struct WinArgs {            // learnable window from its control points
@@ -120,6 +152,9 @@ struct Launch {
 };
 
 int colpass_cols(int N1);
+hipError_t launch_colpass_mx(int N1, int prec, int bits, const MxColArgs& a, int n_blocks, const Launch& l);
+hipError_t launch_rowpass_mx(int N2, int prec, int accum, const MxRowArgs& a, const Launch& l);
+
 hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, const Launch& l);
 hipError_t launch_rowpass(int N2, const RowArgs& a, const Launch& l);
 hipError_t launch_stokes(const OutArgs& a, const Launch& l);

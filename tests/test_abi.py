@@ -61,12 +61,27 @@ def test_valid_plan_reports_aligned_workspace():
     (dict(window="taps", n_taps=1), "PS_ERR_ARG"),
     (dict(window=7), "PS_ERR_ARG"),
     (dict(chunk_frames=-1), "PS_ERR_ARG"),
+    (dict(precision=5), "PS_ERR_ARG"),
+    (dict(accum=3), "PS_ERR_ARG"),
+    (dict(accum="kahan32"), "PS_ERR_UNSUPPORTED"),
+    (dict(fft_len=1 << 20, precision="fp16"), "PS_ERR_UNSUPPORTED"),
+    (dict(fft_len=1 << 12, precision="bf16"), "PS_ERR_UNSUPPORTED"),
+    (dict(fft_len=1 << 16, precision="fp16", window="taps", n_taps=64), "PS_ERR_UNSUPPORTED"),
 ])
 def test_plan_rejects_bad_instances(kw, code):
     st, h, n = _plan(**kw)
     assert pk.STATUS[st] == code, pk.lib().ps_last_error()
     assert not h.value
     assert len(pk.lib().ps_last_error()) > 0
+
+
+@pytest.mark.parametrize("log2n", [16, 17, 18])
+@pytest.mark.parametrize("precision,accum", [("fp16", "kahan32"), ("bf16", "fp64")])
+def test_reduced_precision_plans(log2n, precision, accum):
+    st, h, n = _plan(fft_len=1 << log2n, precision=precision, accum=accum)
+    assert st == 0, pk.lib().ps_last_error()
+    assert n % 256 == 0
+    assert pk.lib().ps_destroy(h) == 0
 
 
 def test_calls_before_bind_are_state_errors():
