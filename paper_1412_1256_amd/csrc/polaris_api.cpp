@@ -272,14 +272,15 @@ ps_status upload(ps_plan_t plan, size_t off, const void* src, size_t bytes) {
   return PS_OK;
 }
 
-// Precision form of one chunk: 16-bit column pass (16 columns per workgroup, one workgroup per CU) and
+// Precision form of one chunk: 16-bit column pass (16 columns per workgroup, about two workgroups per CU) and
 // 16-bit row pass with FP64 or compensated FP32 sums (one workgroup per unit and pair).
 ps_status accumulate_mx(ps_plan_t plan, Inst& I, const ps::ColArgs& ca) {
   ps::MxColArgs m{};
   m.col = ca;
   m.col.n_colblk = (int32_t)(I.N2 / 16);
   const int64_t per_frame = (int64_t)m.col.n_colblk * ca.P;
-  int64_t groups = (plan->n_cu + per_frame / 2) / per_frame;
+  // two or three workgroups fit on a CU: aim at two per CU, each looping over a group of frames
+  int64_t groups = (2 * plan->n_cu + per_frame / 2) / per_frame;
   if (groups < 1) groups = 1;
   if (groups > ca.n_frames) groups = ca.n_frames;
   m.col.frames_per_block = (int32_t)((ca.n_frames + groups - 1) / groups);

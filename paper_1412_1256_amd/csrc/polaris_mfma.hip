@@ -7,7 +7,8 @@
 // 16 x R: n = R*a + b, k = kappa + 16*kb,
 //   stage A: Y[kappa][b] = sum_a W16^(a*kappa) z[R*a + b]          (16 vectors b per matrix product)
 //   twiddle: Y *= W_L^(b*kappa) / 16                                 (FP32, then rounded to 16 bits)
-//   stage B: Z[kappa + 16*kb] = sum_b WR^(b*kb) Y[kappa][b] / R      (16 vectors of 16 columns or kappas)
+//   stage B: Z[kappa + 16*kb] = sum_b WR^(b*kb) Y[kappa][b] / R      (16 vectors of 16 columns or kappas;
+//            for R = 32 a radix-2 butterfly in FP32 and two radix-16 products)
 //
 // A DFT of radix r applied to 16 vectors is one r x r complex matrix product.  With the complex values as
 // (re, im) pairs it is a 2r x 2r real product, which maps onto 16x16x32 matrix instructions: the vectors
@@ -118,20 +119,28 @@ struct MxIn {
 };
 
 // ------------------------------------------------------------------------------------------------
-// column pass: a workgroup of 4 waves transforms 16 adjacent columns (all N1 rows) of a frame, for a
-// group of frames.  Stage A: wave w handles b = 4q + j for the quads q = w + 4t; the results go to LDS as
-// [kappa][column][b].  Stage B: wave w handles kappa = w + 4t, then the four-step twiddle W_N^(k1*n2) / R,
-// and the packed 16-bit result is written to T[f][p][k1][n2].
+// Radix-32 stage B as a radix-2 butterfly and two radix-16 products.  With b = b_lo + 16 b_hi and the stage A
+// outputs Y (twiddle not yet applied),
+//   Z[2m]   = sum_blo W16^(blo m) W_L^(blo kappa) (Y[blo] + W32^kappa Y[blo + 16]) / 16
+//   Z[2m+1] = sum_blo W16^(blo m) W_L^(blo (kappa + 16)) (Y[blo] - W32^kappa Y[blo + 16]) / 16
+// (W_L^(16 kappa) = W32^kappa for L = 512), so one radix-16 matrix serves every stage and the butterfly runs
+// in FP32 before the rounding to 16 bits.  H = R / 16 is the number of such halves (1 for R = 16).
 // ------------------------------------------------------------------------------------------------
-template <int R, int PREC, int BITS, int MODE>
-__global__ void __launch_bounds__(256) k_colpass_mx(MxColArgs a) {
+
+// column pass: a workgroup of 4 waves transforms 16 adjacent columns (all N1 rows) of a frame, for a group
+// of frames.  Stage A: wave w handles b_lo = 4w + j (and b_lo + 16); the results go to LDS as
+// [half][kappa][column][b_lo].  Stage B: wave w handles kappa = w + 4t, then the four-step twiddle
+// W_N^(k1*n2) / R, and the packed 16-bit result is written to T[f][p][k1][n2].
+template <int R, int N2, int PREC, int BITS, int MODE, bool WIN>
+__global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
   constexpr int N1 = 16 * R;
-  constexpr int NQ = R / 16;  // b-quads per wave
-  constexpr int XS = R + 4;   // words per (kappa, column) row of the exchange, 16-byte aligned rows
-  __shared__ __align__(16) uint32_t X[16 * 16 * XS];
+  constexpr int H = R / 16;
+  constexpr int XS = 20;  // words per (half, kappa, column) row: 16 points + 4 of padding (16-byte aligned)
+  __shared__ __align__(16) uint32_t X[H * 16 * 16 * XS];
   __shared__ float2 tws[N1];
   const ColArgs& c = a.col;
-  const int tid = (int)threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, n = lane & 15;
+  const int tid = (int)threadIdx.x, lane = tid & 63, g = lane >> 4, n = lane & 15;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
   const int blk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   const int cb = blk % c.n_colblk;
   const int rest = blk / c.n_colblk;
@@ -141,106 +150,129 @@ __global__ void __launch_bounds__(256) k_colpass_mx(MxColArgs a) {
   const int f_end = min(c.n_frames, f_begin + c.frames_per_block);
   const int n2 = cb * 16 + n;
   const int sx = c.px[p], sy = c.py[p];
+  // Addresses: a wave-uniform base (SGPRs) per element, which changes with the frame, plus one per-lane
+  // offset shared by every element, so no per-element offsets stay live across the frame loop.
+  const uint32_t lane_t = (uint32_t)(4 * R * g * N2 + n2);                // time index, lane part
+  const uint32_t lane_o = (uint32_t)(16 * H * 4 * g * N2 + n2) * 4u;     // output byte offset, lane part
 
   for (int i = tid; i < N1; i += 256) tws[i] = a.m.tws[i];
-  const gbytes win = c.win ? uniform_gptr(reinterpret_cast<const uint8_t*>(c.win)) : nullptr;
   Mat<16> A16;
-  Mat<R> AR;
   A16.load(a.m.a16, lane);
-  AR.load(a.m.aR, lane);
-  // four-step twiddles W_N^(k1 * n2), k1 = kappa + 16 kb: t1 for this wave's kappas, t2 for this lane's kb
+  // four-step twiddles W_N^(k1 * n2) / R of this lane's outputs k1 = kappa + 16 kb, kappa = w + 4t,
+  // kb = H (4g + i) + half, as the product t1[t] * t2[half][i] = W_N^(kappa n2) * W_N^(16 kb n2) / R
   const int mask = (1 << c.lo_bits) - 1;
-  float2 t1[4], t2[NQ][4];
+  float2 t1[4], t2[H][4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int m = (w + 4 * t) * n2;
     t1[t] = cmul(c.tw_hi[m >> c.lo_bits], c.tw_lo[m & mask]);
   }
 #pragma unroll
-  for (int qb = 0; qb < NQ; ++qb)
+  for (int h = 0; h < H; ++h)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int m = 16 * (16 * qb + 4 * g + i) * n2;
+      const int m = 16 * (H * (4 * g + i) + h) * n2;
       const float2 v = cmul(c.tw_hi[m >> c.lo_bits], c.tw_lo[m & mask]);
-      t2[qb][i] = make_float2(v.x * (1.0f / R), v.y * (1.0f / R));
+      t2[h][i] = make_float2(v.x * (1.0f / R), v.y * (1.0f / R));
     }
   __syncthreads();
+  // W32^kappa for kappa = 4g + i (the stage twiddle table holds W_N1^m / 16)
+  float2 w32[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float2 v = tws[(16 * (4 * g + i)) & (N1 - 1)];
+    w32[i] = make_float2(16.0f * v.x, 16.0f * v.y);
+  }
 
-  MxIn<BITS, MODE> in[NQ][4][4];  // [quad][j][point a = 4g + jj]
+  MxIn<BITS, MODE> in[4][H][4];  // [j][b_hi][point a = 4g + jj]
   constexpr int BPT = MODE == 1 ? 2 : 4;  // bytes per time step on the word paths
+  // time index of element (j, h, jj) within the frame: lane_t + (R jj + 4w + j + 16h) N2
   auto fetch = [&](int f) {
     if constexpr (MODE != 0) {
-      const gbytes fb = uniform_gptr(c.in + (int64_t)f * c.N * BPT);
 #pragma unroll
-      for (int t = 0; t < NQ; ++t)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int h = 0; h < H; ++h)
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj) {
-            const int b = 4 * (w + 4 * t) + j;
-            const int n1 = R * (4 * g + jj) + b;
-            in[t][j][jj].fetch(fb, (uint32_t)(n1 * c.N2 + n2));
+            const gbytes fb = uniform_gptr(
+                c.in + ((int64_t)f * c.N + (int64_t)(R * jj + 4 * w + j + 16 * h) * N2) * BPT);
+            in[j][h][jj].fetch(fb, lane_t);
           }
     }
   };
   if (f_begin < f_end) fetch(f_begin);
   for (int f = f_begin; f < f_end; ++f) {
-    // ---- stage A
+    // the stage twiddles are read from LDS in every frame: an opaque zero keeps the compiler from holding
+    // all of them in registers across the frame loop
+    int z0;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z0));
+    // ---- stage A (and the radix-2 butterfly of a radix-32 stage B)
+    uint32_t Y[H][4][4];  // [half][i][j]
 #pragma unroll
-    for (int t = 0; t < NQ; ++t) {
-      const int q = w + 4 * t;
-      uint32_t Y[4][4];  // [i][j]
+    for (int j = 0; j < 4; ++j) {
+      const int b = 4 * w + j;
+      f4v o[H][2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int b = 4 * q + j;
+      for (int h = 0; h < H; ++h) {
         w4v xb[1];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-          const int n1 = R * (4 * g + jj) + b;
-          const int64_t tt = (int64_t)f * c.N + (int64_t)n1 * c.N2 + n2;
-          float2 v = in[t][j][jj].level(c, tt, sx, sy);
-          if (win) {
-            const float wv = *(const __attribute__((address_space(1))) float*)(win + 4u * (uint32_t)(n1 * c.N2 + n2));
+          const int64_t tt = (int64_t)f * c.N + (int64_t)(R * jj + b + 16 * h) * N2 + lane_t;
+          float2 v = in[j][h][jj].level(c, tt, sx, sy);
+          if constexpr (WIN) {
+            const gbytes wb = uniform_gptr(reinterpret_cast<const uint8_t*>(c.win + (R * jj + b + 16 * h) * N2));
+            const float wv = *(const __attribute__((address_space(1))) float*)(wb + 4u * lane_t);
             v = make_float2(v.x * wv, v.y * wv);
           }
           xb[0][jj] = pk<PREC>(v.x, v.y);
         }
-        f4v o[2];
-        A16.template apply<PREC>(xb, o);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float2 tw = tws[(b * (4 * g + i)) & (N1 - 1)];
-          Y[i][j] = pk<PREC>(o[0][i] * tw.x - o[1][i] * tw.y, o[0][i] * tw.y + o[1][i] * tw.x);
-        }
+        A16.template apply<PREC>(xb, o[h]);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const w4v v = {Y[i][0], Y[i][1], Y[i][2], Y[i][3]};
-        *reinterpret_cast<w4v*>(&X[((4 * g + i) * 16 + n) * XS + 4 * q]) = v;
+        const int kap = 4 * g + i;
+        const float2 y0 = make_float2(o[0][0][i], o[0][1][i]);
+        if constexpr (H == 1) {
+          const float2 t = tws[((b * kap) & (N1 - 1)) + z0];
+          Y[0][i][j] = pk<PREC>(y0.x * t.x - y0.y * t.y, y0.x * t.y + y0.y * t.x);
+        } else {
+          const float2 v = cmul(w32[i], make_float2(o[1][0][i], o[1][1][i]));
+          const float2 s0 = cadd(y0, v), d0 = csub(y0, v);
+          const float2 ta = tws[((b * kap) & (N1 - 1)) + z0];
+          const float2 tb = tws[((b * (kap + 16)) & (N1 - 1)) + z0];
+          Y[0][i][j] = pk<PREC>(s0.x * ta.x - s0.y * ta.y, s0.x * ta.y + s0.y * ta.x);
+          Y[1][i][j] = pk<PREC>(d0.x * tb.x - d0.y * tb.y, d0.x * tb.y + d0.y * tb.x);
+        }
       }
     }
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const w4v v = {Y[h][i][0], Y[h][i][1], Y[h][i][2], Y[h][i][3]};
+        *reinterpret_cast<w4v*>(&X[((h * 16 + 4 * g + i) * 16 + n) * XS + 4 * w]) = v;
+      }
     if (f + 1 < f_end) fetch(f + 1);
     __syncthreads();
     // ---- stage B and the four-step twiddle
-    const gbytes Tf = uniform_gptr(reinterpret_cast<const uint8_t*>(a.T + ((int64_t)f * c.P + p) * (int64_t)N1 * c.N2));
+    const uint32_t* Tf = a.T + ((int64_t)f * c.P + p) * (int64_t)N1 * N2;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int kap = w + 4 * t;
-      w4v xs[NQ];
 #pragma unroll
-      for (int s = 0; s < NQ; ++s) xs[s] = *reinterpret_cast<const w4v*>(&X[(kap * 16 + n) * XS + 16 * s + 4 * g]);
-      f4v o[2 * NQ];
-      AR.template apply<PREC>(xs, o);
-#pragma unroll
-      for (int qb = 0; qb < NQ; ++qb)
+      for (int h = 0; h < H; ++h) {
+        const w4v xs[1] = {*reinterpret_cast<const w4v*>(&X[((h * 16 + kap) * 16 + n) * XS + 4 * g])};
+        f4v o[2];
+        A16.template apply<PREC>(xs, o);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int k1 = kap + 16 * (16 * qb + 4 * g + i);
-          const float2 tw = cmul(t1[t], t2[qb][i]);
-          const float2 z = make_float2(o[2 * qb][i], o[2 * qb + 1][i]);
-          const float2 v = cmul(z, tw);
-          *(__attribute__((address_space(1))) uint32_t*)(Tf + 4u * (uint32_t)(k1 * c.N2 + n2)) = pk<PREC>(v.x, v.y);
+          // k1 = kap + 16 (H (4g + i) + h): lane part 16 H 4g, uniform part kap + 16 (H i + h)
+          const gbytes ob = uniform_gptr(reinterpret_cast<const uint8_t*>(Tf + (kap + 16 * (H * i + h)) * N2));
+          const float2 v = cmul(make_float2(o[0][i], o[1][i]), cmul(t1[t], t2[h][i]));
+          *(__attribute__((address_space(1))) uint32_t*)(ob + lane_o) = pk<PREC>(v.x, v.y);
         }
+      }
     }
     __syncthreads();
   }
@@ -256,31 +288,35 @@ __global__ void __launch_bounds__(256) k_colpass_mx(MxColArgs a) {
 template <int R, int PREC, bool KAHAN>
 __global__ void __launch_bounds__(256, 2) k_rowpass_mx(MxRowArgs a) {
   constexpr int N2 = 16 * R;
-  constexpr int NQ = R / 16;
+  constexpr int H = R / 16;
   constexpr int NW = 4;
-  constexpr int XS = R + 4;
+  constexpr int XS = 20;
   constexpr int SPL = N2 / 64;          // channel slots per lane
   constexpr int SP = N2 + N2 / 16;      // padded spectrum row
-  constexpr int WAVE_BYTES = 16 * XS * 4 + 2 * SP * 8;
+  constexpr int WAVE_BYTES = H * 16 * XS * 4 + 2 * SP * 8;
   constexpr int LOOP_BYTES = NW * WAVE_BYTES;
   constexpr int SUM_BYTES = (NW - 1) * 64 * SPL * 4 * 8;
   __shared__ __align__(16) unsigned char lds[LOOP_BYTES > SUM_BYTES ? LOOP_BYTES : SUM_BYTES];
-  const int tid = (int)threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, n = lane & 15;
+  const int tid = (int)threadIdx.x, lane = tid & 63, g = lane >> 4, n = lane & 15;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
   const int u = (int)blockIdx.x, p = (int)blockIdx.y;
   const int N1 = a.N1, U = N1 / 2;
   const int rows[2] = {u == 0 ? 0 : u, u == 0 ? N1 / 2 : N1 - u};
   uint32_t* X = reinterpret_cast<uint32_t*>(lds + w * WAVE_BYTES);
-  float2* spec = reinterpret_cast<float2*>(lds + w * WAVE_BYTES + 16 * XS * 4);
+  float2* spec = reinterpret_cast<float2*>(lds + w * WAVE_BYTES + H * 16 * XS * 4);
 
   Mat<16> A16;
-  Mat<R> AR;
   A16.load(a.m.a16, lane);
-  AR.load(a.m.aR, lane);
-  float2 tw[NQ][4];  // W_N2^(b * kappa) / 16 for b = 16h + n, kappa = 4g + i
+  // stage twiddles (W_N2^m / 16 in the table) for b_lo = n, kappa = 4g + i; W32^kappa unscaled
+  float2 ta[4], tb[4], w32[4];
 #pragma unroll
-  for (int h = 0; h < NQ; ++h)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) tw[h][i] = a.m.tws[((16 * h + n) * (4 * g + i)) & (N2 - 1)];
+  for (int i = 0; i < 4; ++i) {
+    const int kap = 4 * g + i;
+    ta[i] = a.m.tws[(n * kap) & (N2 - 1)];
+    tb[i] = a.m.tws[(n * (kap + 16)) & (N2 - 1)];
+    const float2 v = a.m.tws[(16 * kap) & (N2 - 1)];
+    w32[i] = make_float2(16.0f * v.x, 16.0f * v.y);
+  }
 
   using acc_t = typename std::conditional<KAHAN, float, double>::type;
   acc_t sum[SPL][4], cmp[SPL][4];
@@ -289,13 +325,13 @@ __global__ void __launch_bounds__(256, 2) k_rowpass_mx(MxRowArgs a) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) sum[m][k] = cmp[m][k] = 0;
 
-  uint32_t raw[2][NQ][4];
+  uint32_t raw[2][H][4];
   auto fetch = [&](int f) {
     const gbytes fb = uniform_gptr(reinterpret_cast<const uint8_t*>(a.T + ((int64_t)f * a.P + p) * N1 * N2));
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int h = 0; h < NQ; ++h)
+      for (int h = 0; h < H; ++h)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
           raw[r][h][jj] = *(const __attribute__((address_space(1))) uint32_t*)(
@@ -303,40 +339,47 @@ __global__ void __launch_bounds__(256, 2) k_rowpass_mx(MxRowArgs a) {
   };
   if (w < a.n_frames) fetch(w);
   for (int f = w; f < a.n_frames; f += NW) {
-    uint32_t cur[2][NQ][4];
+    uint32_t cur[2][H][4];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int h = 0; h < NQ; ++h)
+      for (int h = 0; h < H; ++h)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) cur[r][h][jj] = raw[r][h][jj];
     if (f + NW < a.n_frames) fetch(f + NW);
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
+      f4v o[H][2];
 #pragma unroll
-      for (int h = 0; h < NQ; ++h) {
-        w4v xb[1] = {{cur[r][h][0], cur[r][h][1], cur[r][h][2], cur[r][h][3]}};
-        f4v o[2];
-        A16.template apply<PREC>(xb, o);
+      for (int h = 0; h < H; ++h) {
+        const w4v xb[1] = {{cur[r][h][0], cur[r][h][1], cur[r][h][2], cur[r][h][3]}};
+        A16.template apply<PREC>(xb, o[h]);
+      }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float2 t = tw[h][i];
-          X[(4 * g + i) * XS + 16 * h + n] = pk<PREC>(o[0][i] * t.x - o[1][i] * t.y, o[0][i] * t.y + o[1][i] * t.x);
+      for (int i = 0; i < 4; ++i) {
+        const float2 y0 = make_float2(o[0][0][i], o[0][1][i]);
+        if constexpr (H == 1) {
+          X[(4 * g + i) * XS + n] = pk<PREC>(y0.x * ta[i].x - y0.y * ta[i].y, y0.x * ta[i].y + y0.y * ta[i].x);
+        } else {
+          const float2 v = cmul(w32[i], make_float2(o[1][0][i], o[1][1][i]));
+          const float2 s0 = cadd(y0, v), d0 = csub(y0, v);
+          X[(4 * g + i) * XS + n] = pk<PREC>(s0.x * ta[i].x - s0.y * ta[i].y, s0.x * ta[i].y + s0.y * ta[i].x);
+          X[(16 + 4 * g + i) * XS + n] =
+              pk<PREC>(d0.x * tb[i].x - d0.y * tb[i].y, d0.x * tb[i].y + d0.y * tb[i].x);
         }
       }
       wave_sync();
-      w4v xs[NQ];
 #pragma unroll
-      for (int s = 0; s < NQ; ++s) xs[s] = *reinterpret_cast<const w4v*>(&X[n * XS + 16 * s + 4 * g]);
-      f4v o[2 * NQ];
-      AR.template apply<PREC>(xs, o);
-#pragma unroll
-      for (int qb = 0; qb < NQ; ++qb)
+      for (int h = 0; h < H; ++h) {
+        const w4v xs[1] = {*reinterpret_cast<const w4v*>(&X[(h * 16 + n) * XS + 4 * g])};
+        f4v z[2];
+        A16.template apply<PREC>(xs, z);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int k2 = n + 16 * (16 * qb + 4 * g + i);
-          spec[r * SP + k2 + (k2 >> 4)] = make_float2(o[2 * qb][i], o[2 * qb + 1][i]);
+          const int k2 = n + 16 * (H * (4 * g + i) + h);
+          spec[r * SP + k2 + (k2 >> 4)] = make_float2(z[0][i], z[1][i]);
         }
+      }
       wave_sync();
     }
 #pragma unroll
@@ -397,22 +440,38 @@ __global__ void __launch_bounds__(256, 2) k_rowpass_mx(MxRowArgs a) {
 #define PS_LAUNCH(kernel, grid, block, l, ...) \
   hipExtLaunchKernelGGL(kernel, grid, block, 0, (l).stream, (l).start, (l).stop, 0, __VA_ARGS__)
 
-template <int R, int PREC>
-hipError_t colpass_mx_bits(int bits, const MxColArgs& a, int n_blocks, const Launch& l) {
-  const dim3 grid((unsigned)n_blocks), block(256);
-  switch (a.mode) {
-    case 1: PS_LAUNCH((k_colpass_mx<R, PREC, 8, 1>), grid, block, l, a); break;
-    case 2: PS_LAUNCH((k_colpass_mx<R, PREC, 8, 2>), grid, block, l, a); break;
-    default:
-      switch (bits) {
-        case 2: PS_LAUNCH((k_colpass_mx<R, PREC, 2, 0>), grid, block, l, a); break;
-        case 4: PS_LAUNCH((k_colpass_mx<R, PREC, 4, 0>), grid, block, l, a); break;
-        case 8: PS_LAUNCH((k_colpass_mx<R, PREC, 8, 0>), grid, block, l, a); break;
-        case 32: PS_LAUNCH((k_colpass_mx<R, PREC, 32, 0>), grid, block, l, a); break;
-        default: return hipErrorInvalidValue;
-      }
+// int8 word paths (no window), or item-by-item decoding of any format with or without a window
+template <int R, int N2, int PREC, bool WIN>
+hipError_t colpass_mx_generic(int bits, const MxColArgs& a, const dim3& grid, const Launch& l) {
+  const dim3 block(256);
+  switch (bits) {
+    case 2: PS_LAUNCH((k_colpass_mx<R, N2, PREC, 2, 0, WIN>), grid, block, l, a); break;
+    case 4: PS_LAUNCH((k_colpass_mx<R, N2, PREC, 4, 0, WIN>), grid, block, l, a); break;
+    case 8: PS_LAUNCH((k_colpass_mx<R, N2, PREC, 8, 0, WIN>), grid, block, l, a); break;
+    case 32: PS_LAUNCH((k_colpass_mx<R, N2, PREC, 32, 0, WIN>), grid, block, l, a); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int R, int N2, int PREC>
+hipError_t colpass_mx_bits(int bits, const MxColArgs& a, int n_blocks, const Launch& l) {
+  const dim3 grid((unsigned)n_blocks), block(256);
+  if (a.col.win) return colpass_mx_generic<R, N2, PREC, true>(bits, a, grid, l);
+  switch (a.mode) {
+    case 1: PS_LAUNCH((k_colpass_mx<R, N2, PREC, 8, 1, false>), grid, block, l, a); break;
+    case 2: PS_LAUNCH((k_colpass_mx<R, N2, PREC, 8, 2, false>), grid, block, l, a); break;
+    default: return colpass_mx_generic<R, N2, PREC, false>(bits, a, grid, l);
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t colpass_mx_prec(int N1, int N2, int bits, const MxColArgs& a, int n_blocks, const Launch& l) {
+  if (N1 == 256 && N2 == 256) return colpass_mx_bits<16, 256, PREC>(bits, a, n_blocks, l);
+  if (N1 == 256 && N2 == 512) return colpass_mx_bits<16, 512, PREC>(bits, a, n_blocks, l);
+  if (N1 == 512 && N2 == 512) return colpass_mx_bits<32, 512, PREC>(bits, a, n_blocks, l);
+  return hipErrorInvalidValue;
 }
 
 template <int R>
@@ -434,13 +493,8 @@ hipError_t rowpass_mx_r(int prec, int accum, const MxRowArgs& a, const Launch& l
 }  // namespace
 
 hipError_t launch_colpass_mx(int N1, int prec, int bits, const MxColArgs& a, int n_blocks, const Launch& l) {
-  if (prec == PS_PREC_FP16) {
-    if (N1 == 256) return colpass_mx_bits<16, PS_PREC_FP16>(bits, a, n_blocks, l);
-    if (N1 == 512) return colpass_mx_bits<32, PS_PREC_FP16>(bits, a, n_blocks, l);
-  } else if (prec == PS_PREC_BF16) {
-    if (N1 == 256) return colpass_mx_bits<16, PS_PREC_BF16>(bits, a, n_blocks, l);
-    if (N1 == 512) return colpass_mx_bits<32, PS_PREC_BF16>(bits, a, n_blocks, l);
-  }
+  if (prec == PS_PREC_FP16) return colpass_mx_prec<PS_PREC_FP16>(N1, a.col.N2, bits, a, n_blocks, l);
+  if (prec == PS_PREC_BF16) return colpass_mx_prec<PS_PREC_BF16>(N1, a.col.N2, bits, a, n_blocks, l);
   return hipErrorInvalidValue;
 }
 
