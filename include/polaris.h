@@ -16,9 +16,13 @@
  *   - The caller owns every device buffer, including the workspace whose size ps_plan reports.  The
  *     library never allocates or frees device memory; a plan owns host metadata only.
  *   - All device work is enqueued asynchronously on the stream given to ps_bind; no call synchronises
- *     except ps_bind itself.  ps_reset, ps_accumulate, ps_spectra, ps_stokes, ps_set_window_taps and
- *     ps_calibrate_backward enqueue kernels only (no allocation, copy or memset), so they can be
- *     captured into a hipGraph.
+ *     except ps_bind itself and the descriptor upload described next.  ps_reset, ps_accumulate,
+ *     ps_spectra, ps_stokes, ps_stokes_all, ps_set_window_taps and ps_calibrate_backward enqueue kernels
+ *     only (no allocation or memset), so they can be captured into a hipGraph (ps_graph_begin).
+ *   - Plans of several instances run each pass as grouped persistent launches (the batching form), whose
+ *     per-instance launch descriptors live in the workspace.  ps_accumulate and ps_stokes_all upload them
+ *     (waiting for the stream, then one copy from pinned host memory) only when they differ from the
+ *     previous call's, e.g. new buffers or frame counts; during a capture they must be unchanged.
  *   - Argument and size errors are returned before anything is enqueued (no partial work).  Kernel
  *     launch failures return PS_ERR_HIP.  Faults inside kernels surface at the caller's next
  *     synchronisation.
@@ -64,8 +68,14 @@ typedef struct ps_plan_s* ps_plan_t;
  *   fft_len     N, a power of two, 2^8 .. 2^22; channels C = N/2; one segment = N samples per stream.
  *   window      PS_WIN_RECT, PS_WIN_HANN (periodic) or PS_WIN_TAPS (n_taps control points, linear
  *               interpolation at u = n (n_taps - 1)/(N - 1); all ones until ps_set_window_taps).
- *   precision   PS_PREC_FP32 (the only value accepted by this build's plain path).
- *   accum       PS_ACC_FP64.
+ *   precision   PS_PREC_FP32: FP32 transforms.  PS_PREC_FP16 / PS_PREC_BF16 (the precision form,
+ *               fft_len 2^16 .. 2^18, rect or Hann window): each pass as 16 x R blocked DFT matrix
+ *               products on the matrix cores with 16-bit inputs and FP32 accumulation, a 16-bit
+ *               inter-pass buffer; every stage is scaled by 1/radix (exact), so FP16 values stay within
+ *               the input range (|level| < 65504).
+ *   accum       PS_ACC_FP64 (any precision), or PS_ACC_KAHAN32 (16-bit passes only): the products of
+ *               the frames of one pass launch are summed per channel in registers, in FP64 or in
+ *               compensated FP32, then added to FP64 accumulators.
  *   chunk_frames  frames processed per internal pass pair (0 = 64); bounds the workspace.
  *   sample_rate_hz  metadata only (channel width = sample_rate_hz / N).
  */
@@ -126,7 +136,11 @@ ps_status ps_reset(ps_plan_t plan);
  *   packed_dev[i]   device pointer to instance i's packed buffer (layout above); may be NULL when
  *                   n_samples[i] == 0.
  *   n_samples[i]    samples per stream, a multiple of fft_len (PS_ERR_SIZE otherwise).
- * Frames are added in order; splitting one input over several calls gives bitwise the same sums. */
+ * Frames are added in order; with FP32 passes, splitting one input over several calls gives bitwise the
+ * same sums (with 16-bit passes the same up to the rounding of the per-launch sums).
+ * In a plan of several instances, the FP32 instances of a call run together: per chunk round, one
+ * persistent column-pass launch per (segment shape, sample format) and one row-pass launch per row length
+ * walk the tiles of all of them (up to 8 chunk rounds per call; beyond that instance by instance). */
 ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples);
 
 /* Raw accumulated products of instance inst into out_dev [n_pairs][4][C] doubles:
@@ -138,6 +152,24 @@ ps_status ps_spectra(ps_plan_t plan, int32_t inst, double* out_dev, int64_t* n_f
  * (I, Q, U, V), computed in FP64 from M = A / (F sum w^2) and C = (G J)^-1 M (G J)^-H.  cal may be NULL
  * (unit gains, no leakage, psi = 0).  The integration is read, not consumed. */
 ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv_dev);
+
+/* Stokes spectra of every instance whose iquv_dev[i] is not NULL, in one persistent launch (the batching
+ * form).  cal: NULL or an array of n_inst calibrations; iquv_dev: n_inst device pointers, each
+ * [n_pairs][4][C] floats.  PS_ERR_STATE if a selected instance has no accumulated frame. */
+ps_status ps_stokes_all(ps_plan_t plan, const ps_cal* cal, float* const* iquv_dev);
+
+/* hipGraph capture of a sequence of calls on the plan's stream (the batching form's streaming loop):
+ *   ps_graph_begin   starts capturing the bound stream (not the null stream; profiling must be off);
+ *   ps_graph_end     ends the capture; keep != 0 instantiates the graph (replacing an earlier one),
+ *                    keep == 0 discards what was captured (e.g. after a call failed during the capture);
+ *   ps_graph_launch  replays it on the bound stream and restores the plan's host state (frame counts) to
+ *                    what it was at the end of the capture.
+ * A captured sequence is meant to be a whole integration: ps_reset, ps_accumulate on fixed input buffers,
+ * then ps_stokes / ps_stokes_all into fixed outputs.  Make the same calls once before capturing, so the
+ * launch descriptors are already in place.  PS_ERR_STATE for calls out of order. */
+ps_status ps_graph_begin(ps_plan_t plan);
+ps_status ps_graph_end(ps_plan_t plan, int32_t keep);
+ps_status ps_graph_launch(ps_plan_t plan);
 
 /* Gradient of a real loss L(iquv) with respect to the gains, leakage terms and window taps, given
  * dL_diquv_dev [n_pairs][4][C] floats.  Needs the current integration (the forward's accumulators,

@@ -77,6 +77,10 @@ def lib():
             "ps_version": [],
             "ps_profile_enable": [vp, i32],
             "ps_profile_read": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
+            "ps_stokes_all": [vp, C.POINTER(_Cal), C.POINTER(vp)],
+            "ps_graph_begin": [vp],
+            "ps_graph_end": [vp, i32],
+            "ps_graph_launch": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -227,6 +231,48 @@ class Plan:
         cal = self._cal(gain_x, gain_y, dterms, psi)
         _check(lib().ps_stokes(self._h, inst, C.byref(cal), _ptr(out)))
         return out
+
+    def stokes_all(self, outs=None, cals=None):
+        """Stokes of every instance in one grouped launch.  outs: list of float32 [P][4][C] tensors (None
+        entries skip an instance; default: new tensors); cals: None or a list of (gain_x, gain_y, dterms, psi)
+        tuples (entries may be None)."""
+        n = len(self.instances)
+        if outs is None:
+            outs = [self.torch.empty((I.n_pairs, 4, I.channels), dtype=self.torch.float32, device=self.device)
+                    for I in self.instances]
+        ptrs = (C.c_void_p * n)(*[None if o is None else o.data_ptr() for o in outs])
+        calp = None
+        if cals is not None:
+            arr = (_Cal * n)()
+            keep = []
+            for i, c in enumerate(cals):
+                gx, gy, dt, psi = c if c is not None else (None, None, None, 0.0)
+                gx, gy, dt = self._as_f32(gx), self._as_f32(gy), self._as_f32(dt)
+                keep += [gx, gy, dt]
+                arr[i] = self._cal(gx, gy, dt, psi)
+            self._cal_keepalive = keep
+            calp = arr
+        _check(lib().ps_stokes_all(self._h, calp, ptrs))
+        return outs
+
+    # --------------------------------------------------------------------------------------------
+    # hipGraph capture of a whole integration (the plan must be bound to a non-default stream)
+    def graph_capture(self, fn):
+        """Run fn() once eagerly (puts the launch descriptors in place), then capture fn() into a graph."""
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            fn()
+        _check(lib().ps_graph_begin(self._h))
+        try:
+            with torch.cuda.stream(self.stream):
+                fn()
+        except BaseException:
+            lib().ps_graph_end(self._h, 0)  # discard the partial capture
+            raise
+        _check(lib().ps_graph_end(self._h, 1))
+
+    def graph_replay(self):
+        _check(lib().ps_graph_launch(self._h))
 
     def calibrate_backward(self, packed, dL_diquv, inst: int = 0, gain_x=None, gain_y=None, dterms=None,
                            psi: float = 0.0, want=("gain_x", "gain_y", "dterms", "taps")):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -94,8 +95,23 @@ struct ps_plan_s {
   std::vector<hipEvent_t> ev;       // pairs (start, stop)
   std::vector<int> ev_kind;         // kernel kind of each recorded pair
   size_t ev_used = 0;
+  // batching form: launch descriptors of the grouped passes (device copy in the workspace, host copy
+  // in pinned memory), uploaded only when they change
+  struct Desc {
+    size_t off = 0, cap = 0;                 // device region
+    unsigned char* host = nullptr;           // pinned staging
+    std::vector<unsigned char> current;      // what the device region holds
+  };
+  Desc acc_desc, out_desc;
+  // graph of a captured integration and the host state it leaves behind
+  hipGraphExec_t gexec = nullptr;
+  bool capturing = false;
+  std::vector<std::pair<bool, int64_t>> graph_state;
   ~ps_plan_s() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (acc_desc.host) (void)hipHostFree(acc_desc.host);
+    if (out_desc.host) (void)hipHostFree(out_desc.host);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
   }
 };
 
@@ -252,6 +268,7 @@ T* ws_ptr(ps_plan_t plan, size_t off) {
 }
 
 constexpr size_t kMaxTimed = 16384;
+constexpr size_t kMaxRounds = 8;  // chunks per call handled by the grouped launches
 
 // Launch f(launch) on the plan's stream; while profiling, the dispatch stamps a pair of events with the
 // kernel's own start and end.
@@ -269,6 +286,203 @@ ps_status upload(ps_plan_t plan, size_t off, const void* src, size_t bytes) {
   if (!bytes) return PS_OK;
   hipError_t e = hipMemcpyAsync(plan->ws + off, src, bytes, hipMemcpyHostToDevice, plan->stream);
   if (e != hipSuccess) return hip_fail(e, "table upload");
+  return PS_OK;
+}
+
+// Column-pass arguments of frames f0 .. f0+nf-1 of instance I.  groups: frame groups of the tile grid (0:
+// as many as make the tiles about one per CU).  *fast: the int8 two-stream path (32-bit input offsets).
+ps::ColArgs col_args(ps_plan_t plan, const Inst& I, const uint8_t* base, int64_t f0, int nf, int64_t groups,
+                     bool* fast) {
+  const int64_t frame_bytes = I.N * I.cfg.n_streams * I.cfg.bits / 8;
+  ps::ColArgs ca{};
+  ca.in = base + f0 * frame_bytes;
+  const int64_t in_bytes = (int64_t)nf * frame_bytes;
+  ca.in_bytes = in_bytes < (int64_t(1) << 31) ? (uint32_t)in_bytes : 0u;
+  *fast = I.fast && in_bytes < (int64_t(1) << 31) && I.N * 8 < (int64_t(1) << 31);
+  ca.N = I.N;
+  ca.N2 = (int32_t)I.N2;
+  ca.S = I.cfg.n_streams;
+  ca.P = I.cfg.n_pairs;
+  for (int p = 0; p < 4; ++p) {
+    ca.px[p] = I.cfg.pair_x[p];
+    ca.py[p] = I.cfg.pair_y[p];
+  }
+  const int cols = ps::colpass_cols((int)I.N1);
+  ca.n_colblk = (int32_t)(I.N2 / cols);
+  ca.n_frames = nf;
+  const int64_t per_frame = (int64_t)ca.n_colblk * ca.P;
+  if (groups <= 0) groups = (plan->n_cu + per_frame / 2) / per_frame;
+  if (groups < 1) groups = 1;
+  if (groups > nf) groups = nf;
+  ca.frames_per_block = (int32_t)((nf + groups - 1) / groups);
+  ca.win = I.win.empty() ? nullptr : ws_ptr<float>(plan, I.off_win);
+  ca.tw_col = ws_ptr<float2>(plan, I.off_tw_col);
+  ca.tw_hi = ca.tw_col;
+  ca.tw_lo = ws_ptr<float2>(plan, I.off_tw_lo);
+  ca.lo_bits = I.m2;
+  ca.T = ws_ptr<float2>(plan, I.off_T);
+  return ca;
+}
+
+int col_tiles(const ps::ColArgs& ca) {
+  const int groups = (ca.n_frames + ca.frames_per_block - 1) / ca.frames_per_block;
+  return groups * ca.P * ca.n_colblk;
+}
+
+ps::RowArgs row_args(ps_plan_t plan, const Inst& I, int nf, bool first) {
+  ps::RowArgs ra{};
+  ra.T = ws_ptr<float2>(plan, I.off_T);
+  ra.N1 = (int32_t)I.N1;
+  ra.P = I.cfg.n_pairs;
+  ra.n_frames = nf;
+  ra.tw_row = ws_ptr<float2>(plan, I.off_tw_row);
+  ra.acc = ws_ptr<double>(plan, I.off_acc);
+  ra.first = first ? 1 : 0;
+  return ra;
+}
+
+// Put a descriptor image into its device region, unless the region already holds exactly these bytes.
+ps_status upload_desc(ps_plan_t plan, ps_plan_s::Desc& d, const std::vector<unsigned char>& bytes) {
+  if (bytes == d.current) return PS_OK;
+  if (bytes.size() > d.cap) return fail(PS_ERR_SIZE, "launch descriptors of %zu bytes exceed the %zu reserved", bytes.size(), d.cap);
+  if (plan->capturing)
+    return fail(PS_ERR_STATE, "launch descriptors changed during graph capture: make the same calls once before capturing");
+  hipError_t e = hipSuccess;
+  if (!d.host) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&d.host), d.cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      d.host = nullptr;
+      return hip_fail(e, "pinned descriptor buffer");
+    }
+  }
+  // an earlier copy out of the staging buffer may still be queued
+  e = hipStreamSynchronize(plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "descriptor upload wait");
+  std::memcpy(d.host, bytes.data(), bytes.size());
+  e = hipMemcpyAsync(plan->ws + d.off, d.host, bytes.size(), hipMemcpyHostToDevice, plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+  d.current = bytes;
+  return PS_OK;
+}
+
+template <class T>
+void append_bytes(std::vector<unsigned char>& v, const T* p, size_t n) {
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(p);
+  v.insert(v.end(), b, b + n * sizeof(T));
+}
+
+// Batching form: every FP32 instance of the call in one column-pass launch per (N1, format) and one row-pass
+// launch per N2, per chunk round; each launch is a persistent grid walking the tiles of all its instances.
+ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples,
+                             std::vector<char>& done) {
+  int64_t rounds = 0;
+  for (size_t i = 0; i < plan->inst.size(); ++i) {
+    const Inst& I = plan->inst[i];
+    if (I.mx()) continue;
+    const int64_t F = n_samples[i] / I.N;
+    rounds = std::max(rounds, (F + I.chunk - 1) / I.chunk);
+  }
+  if (rounds == 0 || rounds > (int64_t)kMaxRounds) return PS_OK;  // nothing to group, or too many chunks
+  std::vector<ps::ColArgs> cols;
+  std::vector<ps::RowArgs> rows;
+  std::vector<int32_t> cend, rend;
+  struct L1 {
+    int kind, len, bits;
+    bool fast;
+    size_t task0, n;
+    int total;
+  };
+  std::vector<L1> launches;
+  for (int64_t r = 0; r < rounds; ++r) {
+    std::vector<L1> col_l, row_l;
+    // column-pass groups
+    std::vector<std::pair<std::vector<int>, std::vector<ps::ColArgs>>> cg;  // key (N1, bits, fast)
+    std::vector<std::pair<int, std::vector<ps::RowArgs>>> rg;                // key N2
+    for (size_t i = 0; i < plan->inst.size(); ++i) {
+      const Inst& I = plan->inst[i];
+      if (I.mx()) continue;
+      const int64_t F = n_samples[i] / I.N, f0 = r * I.chunk;
+      if (f0 >= F) continue;
+      const int nf = (int)std::min<int64_t>(I.chunk, F - f0);
+      bool fast = false;
+      // frame groups of about 8 frames: many instances share the device
+      const ps::ColArgs ca = col_args(plan, I, static_cast<const uint8_t*>(packed_dev[i]), f0, nf, (nf + 7) / 8, &fast);
+      const std::vector<int> key = {(int)I.N1, I.cfg.bits, fast ? 1 : 0};
+      auto it = std::find_if(cg.begin(), cg.end(), [&](const auto& g) { return g.first == key; });
+      if (it == cg.end()) {
+        cg.push_back({key, {}});
+        it = cg.end() - 1;
+      }
+      it->second.push_back(ca);
+      const ps::RowArgs ra = row_args(plan, I, nf, I.first && r == 0);
+      auto jt = std::find_if(rg.begin(), rg.end(), [&](const auto& g) { return g.first == (int)I.N2; });
+      if (jt == rg.end()) {
+        rg.push_back({(int)I.N2, {}});
+        jt = rg.end() - 1;
+      }
+      jt->second.push_back(ra);
+    }
+    for (const auto& g : cg) {
+      L1 l{0, g.first[0], g.first[1], g.first[2] != 0, cols.size(), g.second.size(), 0};
+      int total = 0;
+      for (const ps::ColArgs& ca : g.second) {
+        cols.push_back(ca);
+        total += col_tiles(ca);
+        cend.push_back(total);
+      }
+      l.total = total;
+      launches.push_back(l);
+    }
+    for (const auto& g : rg) {
+      L1 l{1, g.first, 0, false, rows.size(), g.second.size(), 0};
+      int total = 0;
+      for (const ps::RowArgs& ra : g.second) {
+        rows.push_back(ra);
+        total += ra.N1 / 2 / ps::rowpass_units_per_tile(g.first) * ra.P;
+        rend.push_back(total);
+      }
+      l.total = total;
+      launches.push_back(l);
+    }
+  }
+  std::vector<unsigned char> img;
+  append_bytes(img, cols.data(), cols.size());
+  const size_t rows_at = img.size();
+  append_bytes(img, rows.data(), rows.size());
+  const size_t cend_at = img.size();
+  append_bytes(img, cend.data(), cend.size());
+  const size_t rend_at = img.size();
+  append_bytes(img, rend.data(), rend.size());
+  ps_status st = upload_desc(plan, plan->acc_desc, img);
+  if (st != PS_OK) return st;
+  char* dev = plan->ws + plan->acc_desc.off;
+  for (const L1& l : launches) {
+    ps::BatchArgs b{};
+    b.n_tasks = (int32_t)l.n;
+    b.total = l.total;
+    b.n_cu = plan->n_cu;
+    hipError_t e;
+    if (l.kind == 0) {
+      b.tasks = dev + l.task0 * sizeof(ps::ColArgs);
+      b.tile_end = reinterpret_cast<const int32_t*>(dev + cend_at) + l.task0;
+      e = timed(plan, PS_KERNEL_COLPASS, [&](const ps::Launch& x) { return ps::launch_colpass_batch(l.len, l.bits, l.fast, b, x); });
+    } else {
+      b.tasks = dev + rows_at + l.task0 * sizeof(ps::RowArgs);
+      b.tile_end = reinterpret_cast<const int32_t*>(dev + rend_at) + l.task0;
+      e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& x) { return ps::launch_rowpass_batch(l.len, b, x); });
+    }
+    if (e != hipSuccess) return hip_fail(e, "grouped pass launch");
+  }
+  for (size_t i = 0; i < plan->inst.size(); ++i) {
+    Inst& I = plan->inst[i];
+    if (I.mx()) continue;
+    done[i] = 1;
+    const int64_t F = n_samples[i] / I.N;
+    if (F > 0) {
+      I.first = false;
+      I.n_frames += F;
+    }
+  }
   return PS_OK;
 }
 
@@ -371,6 +585,16 @@ ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_
     }
     I.end = off;
   }
+  // descriptors of the grouped launches: up to kMaxRounds chunks per call, one task per instance and pass
+  {
+    const size_t n = (size_t)n_inst;
+    plan->acc_desc.cap = kMaxRounds * n * (sizeof(ps::ColArgs) + sizeof(ps::RowArgs) + 2 * sizeof(int32_t)) + 64;
+    plan->acc_desc.off = off;
+    off = align_up(off + plan->acc_desc.cap);
+    plan->out_desc.cap = n * (sizeof(ps::OutArgs) + sizeof(int32_t)) + 64;
+    plan->out_desc.off = off;
+    off = align_up(off + plan->out_desc.cap);
+  }
   plan->ws_bytes = off;
   *out = plan;
   *workspace_bytes = off;
@@ -466,44 +690,21 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
     if (n_samples[i] > 0 && !packed_dev[i]) return fail(PS_ERR_ARG, "instance %zu: null packed buffer", i);
     if (n_samples[i] / I.N > (int64_t(1) << 40)) return fail(PS_ERR_SIZE, "instance %zu: too many frames", i);
   }
+  std::vector<char> done(plan->inst.size(), 0);
+  if (plan->inst.size() > 1) {
+    st = accumulate_grouped(plan, packed_dev, n_samples, done);
+    if (st != PS_OK) return st;
+  }
   for (size_t i = 0; i < plan->inst.size(); ++i) {
+    if (done[i]) continue;
     Inst& I = plan->inst[i];
     const int64_t F = n_samples[i] / I.N;
-    const int64_t frame_bytes = I.N * I.cfg.n_streams * I.cfg.bits / 8;
     const uint8_t* base = static_cast<const uint8_t*>(packed_dev[i]);
     for (int64_t f0 = 0; f0 < F; f0 += I.chunk) {
       const int nf = (int)((F - f0) < I.chunk ? (F - f0) : I.chunk);
-      ps::ColArgs ca{};
-      ca.in = base + f0 * frame_bytes;
-      const int64_t in_bytes = (int64_t)nf * frame_bytes;
-      ca.in_bytes = in_bytes < (int64_t(1) << 31) ? (uint32_t)in_bytes : 0u;
-      // the int8 two-stream path addresses its input with 32-bit buffer offsets
-      const bool fast = I.fast && in_bytes < (int64_t(1) << 31) && I.N * 8 < (int64_t(1) << 31);
-      ca.N = I.N;
-      ca.N2 = (int32_t)I.N2;
-      ca.S = I.cfg.n_streams;
-      ca.P = I.cfg.n_pairs;
-      for (int p = 0; p < 4; ++p) {
-        ca.px[p] = I.cfg.pair_x[p];
-        ca.py[p] = I.cfg.pair_y[p];
-      }
-      const int cols = ps::colpass_cols((int)I.N1);
-      ca.n_colblk = (int32_t)(I.N2 / cols);
-      ca.n_frames = nf;
-      {
-        // one workgroup per CU: each loops over a group of frames, so that groups x pairs x blocks ~ CUs
-        const int64_t per_frame = (int64_t)ca.n_colblk * ca.P;
-        int64_t groups = (plan->n_cu + per_frame / 2) / per_frame;
-        if (groups < 1) groups = 1;
-        if (groups > nf) groups = nf;
-        ca.frames_per_block = (int32_t)((nf + groups - 1) / groups);
-      }
-      ca.win = I.win.empty() ? nullptr : ws_ptr<float>(plan, I.off_win);
-      ca.tw_col = ws_ptr<float2>(plan, I.off_tw_col);
-      ca.tw_hi = ca.tw_col;
-      ca.tw_lo = ws_ptr<float2>(plan, I.off_tw_lo);
-      ca.lo_bits = I.m2;
-      ca.T = ws_ptr<float2>(plan, I.off_T);
+      bool fast = false;
+      // one workgroup per CU: each loops over a group of frames, so that groups x pairs x blocks ~ CUs
+      const ps::ColArgs ca = col_args(plan, I, base, f0, nf, 0, &fast);
       if (I.mx()) {
         ps_status ms = accumulate_mx(plan, I, ca);
         if (ms != PS_OK) return ms;
@@ -514,14 +715,7 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
       hipError_t e = timed(plan, PS_KERNEL_COLPASS,
                            [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cfg.bits, fast, ca, l); });
       if (e != hipSuccess) return hip_fail(e, "column pass launch");
-      ps::RowArgs ra{};
-      ra.T = ca.T;
-      ra.N1 = (int32_t)I.N1;
-      ra.P = I.cfg.n_pairs;
-      ra.n_frames = nf;
-      ra.tw_row = ws_ptr<float2>(plan, I.off_tw_row);
-      ra.acc = ws_ptr<double>(plan, I.off_acc);
-      ra.first = I.first ? 1 : 0;
+      const ps::RowArgs ra = row_args(plan, I, nf, I.first);
       e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& l) { return ps::launch_rowpass((int)I.N2, ra, l); });
       if (e != hipSuccess) return hip_fail(e, "row pass launch");
       I.first = false;
@@ -578,6 +772,101 @@ ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv
   o.iquv = iquv_dev;
   hipError_t e = timed(plan, PS_KERNEL_STOKES, [&](const ps::Launch& l) { return ps::launch_stokes(o, l); });
   if (e != hipSuccess) return hip_fail(e, "stokes launch");
+  return PS_OK;
+}
+
+ps_status ps_stokes_all(ps_plan_t plan, const ps_cal* cal, float* const* iquv_dev) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if (!iquv_dev) return fail(PS_ERR_ARG, "null output array");
+  std::vector<ps::OutArgs> outs;
+  std::vector<int32_t> ends;
+  int32_t total = 0;
+  for (size_t i = 0; i < plan->inst.size(); ++i) {
+    if (!iquv_dev[i]) continue;
+    const Inst& I = plan->inst[i];
+    if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %zu has no accumulated frames", i);
+    ps::OutArgs o = out_args(plan, I);
+    o.n_frames = (double)I.n_frames;
+    o.sumw2_dev = ws_ptr<double>(plan, I.off_sumw2);
+    o.scale = 1.0 / ((double)I.n_frames * I.sumw2);
+    const double psi = cal ? cal[i].psi : 0.0;
+    o.cos2psi = std::cos(2.0 * psi);
+    o.sin2psi = std::sin(2.0 * psi);
+    if (cal) {
+      o.gain_x = cal[i].gain_x;
+      o.gain_y = cal[i].gain_y;
+      o.dterms = cal[i].dterms;
+    }
+    o.iquv = iquv_dev[i];
+    outs.push_back(o);
+    total += ps::output_tiles(o.N1, o.N2, o.P);
+    ends.push_back(total);
+  }
+  if (outs.empty()) return PS_OK;
+  std::vector<unsigned char> img;
+  append_bytes(img, outs.data(), outs.size());
+  const size_t ends_at = img.size();
+  append_bytes(img, ends.data(), ends.size());
+  if ((st = upload_desc(plan, plan->out_desc, img)) != PS_OK) return st;
+  char* dev = plan->ws + plan->out_desc.off;
+  ps::BatchArgs b{};
+  b.tasks = dev;
+  b.tile_end = reinterpret_cast<const int32_t*>(dev + ends_at);
+  b.n_tasks = (int32_t)outs.size();
+  b.total = total;
+  b.n_cu = plan->n_cu;
+  hipError_t e = timed(plan, PS_KERNEL_STOKES, [&](const ps::Launch& l) { return ps::launch_output_batch(true, b, l); });
+  if (e != hipSuccess) return hip_fail(e, "grouped stokes launch");
+  return PS_OK;
+}
+
+ps_status ps_graph_begin(ps_plan_t plan) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if (plan->capturing) return fail(PS_ERR_STATE, "a capture is already in progress");
+  if (plan->prof) return fail(PS_ERR_STATE, "turn per-kernel profiling off before capturing");
+  if (!plan->stream) return fail(PS_ERR_STATE, "graph capture needs the plan bound to a stream other than the null stream");
+  hipError_t e = hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "begin capture");
+  plan->capturing = true;
+  return PS_OK;
+}
+
+ps_status ps_graph_end(ps_plan_t plan, int32_t keep) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if (!plan->capturing) return fail(PS_ERR_STATE, "no capture in progress");
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(plan->stream, &g);
+  plan->capturing = false;
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  if (!keep) {
+    (void)hipGraphDestroy(g);
+    return PS_OK;
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+  if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+  plan->gexec = x;
+  plan->graph_state.clear();
+  for (const Inst& I : plan->inst) plan->graph_state.push_back({I.first, I.n_frames});
+  return PS_OK;
+}
+
+ps_status ps_graph_launch(ps_plan_t plan) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if (!plan->gexec) return fail(PS_ERR_STATE, "no captured graph");
+  if (plan->capturing) return fail(PS_ERR_STATE, "cannot replay while capturing");
+  hipError_t e = hipGraphLaunch(plan->gexec, plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  for (size_t i = 0; i < plan->inst.size(); ++i) {
+    plan->inst[i].first = plan->graph_state[i].first;
+    plan->inst[i].n_frames = plan->graph_state[i].second;
+  }
   return PS_OK;
 }
 

@@ -151,6 +151,21 @@ struct Launch {
   hipEvent_t stop;
 };
 
+// ---- batching form: one persistent launch per pass and shape over the tiles of many instances
+struct BatchArgs {
+  const void* tasks;        // device array of ColArgs / RowArgs / OutArgs, one per instance
+  const int32_t* tile_end;  // device array: running total of tiles up to and including each task
+  int32_t n_tasks;
+  int32_t total;            // tiles of all tasks
+  int32_t n_cu;             // compute units (the grid is the resident workgroups, at most `total`)
+};
+
+hipError_t launch_colpass_batch(int N1, int bits, bool fast, const BatchArgs& b, const Launch& l);
+hipError_t launch_rowpass_batch(int N2, const BatchArgs& b, const Launch& l);
+hipError_t launch_output_batch(bool stokes, const BatchArgs& b, const Launch& l);
+int rowpass_units_per_tile(int N2);
+int output_tiles(int N1, int N2, int P);
+
 int colpass_cols(int N1);
 hipError_t launch_colpass_mx(int N1, int prec, int bits, const MxColArgs& a, int n_blocks, const Launch& l);
 hipError_t launch_rowpass_mx(int N2, int prec, int accum, const MxRowArgs& a, const Launch& l);

@@ -20,12 +20,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <unordered_map>
+
 #include "polaris_device.h"
 #include "polaris_internal.h"
 
 namespace ps {
+// one tile of the column pass: column block, pair and frame group numbered by blk
 template <int L, int COLS, int V, int BITS, bool FAST>
-__global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass(ColArgs a) {
+__device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
   constexpr int CPR = COLS / V;  // column groups per row
   using SC = Sched<L>;
   constexpr int R0 = SC::R0, RL = SC::radix(SC::NPASS - 1), NSL = SC::ns(SC::NPASS - 1);
@@ -34,7 +38,6 @@ __global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass(ColArgs a) {
   constexpr int NB = (2 * L * COLS * 8 <= 128 * 1024) ? 2 : 1;
   __shared__ __align__(16) float2 tile[NB * L * COLS];
 
-  const int blk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   const int cb = blk % a.n_colblk;
   const int rest = blk / a.n_colblk;
   const int p = rest % a.P;
@@ -99,8 +102,30 @@ __global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass(ColArgs a) {
   }
 }
 
+template <int L, int COLS, int V, int BITS, bool FAST>
+__global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass(ColArgs a) {
+  colpass_tile<L, COLS, V, BITS, FAST>(a, xcd_remap((int)blockIdx.x, (int)gridDim.x));
+}
+
+// Batched (persistent) column pass over the tiles of several instances of the same shape and format: each
+// workgroup walks the global tile list with a grid stride; tile_end holds the running tile totals.
+template <int L, int COLS, int V, int BITS, bool FAST>
+__global__ void __launch_bounds__(L * COLS / (8 * V))
+    k_colpass_batch(const ColArgs* __restrict__ tasks, const int32_t* __restrict__ tile_end, int n_tasks) {
+  const int total = tile_end[n_tasks - 1];
+  int t = 0;
+  for (int tile = (int)blockIdx.x; tile < total; tile += (int)gridDim.x) {
+    while (tile >= tile_end[t]) ++t;
+    const int begin = t ? tile_end[t - 1] : 0;
+    const ColArgs a = tasks[t];
+    colpass_tile<L, COLS, V, BITS, FAST>(a, tile - begin);
+    __syncthreads();  // the next tile reuses the LDS tile
+  }
+}
+
+// one tile of the row pass: units bx*UB .. bx*UB+UB-1 of pair p
 template <int L, int UB, int FB, int SQ>
-__global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
+__device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, const int p) {
   constexpr int NT = UB * FB * L / (4 * SQ);
   constexpr int TPS = L / 8;                       // threads per row sequence
   constexpr int NCH = UB * L < NT ? UB * L : NT;   // threads that own channel slots
@@ -111,12 +136,11 @@ __global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
   constexpr int R0 = SC::R0;
   __shared__ __align__(16) float2 buf[UB * FB * 2 * SEQ];
   const int tid = (int)threadIdx.x;
-  const int p = (int)blockIdx.y;
   const int U = a.N1 / 2;
   // transform role: slot ts of row rr of frames fs + j FS (j < SQ) of unit ub
   const int ts = tid % TPS, q = tid / TPS;
   const int rr = q & 1, fs = (q >> 1) % FS, ub = (q >> 1) / FS;
-  const int u = (int)blockIdx.x * UB + ub;
+  const int u = bx * UB + ub;
   const int row = (u == 0) ? (rr ? a.N1 / 2 : 0) : (rr ? a.N1 - u : u);
   float2* seq[SQ];
 #pragma unroll
@@ -132,7 +156,7 @@ __global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
   for (int k = 0; k < SPT; ++k) {
     const int id = tid + k * NCH;
     const int ubc = id / L, s = id % L;
-    const int uc = (int)blockIdx.x * UB + ubc;
+    const int uc = bx * UB + ubc;
     accp[k] = a.acc + ((int64_t)(p * U + uc) * 4) * L + s;
     sxx[k] = syy[k] = sxr[k] = sxi[k] = 0.0;
     if (owner && !a.first) {
@@ -165,7 +189,7 @@ __global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
       for (int k = 0; k < SPT; ++k) {
         const int id = tid + k * NCH;
         const int ubc = id / L, s = id % L;
-        const int uc = (int)blockIdx.x * UB + ubc;
+        const int uc = bx * UB + ubc;
         const int half = s / (L / 2), k2 = s % (L / 2);
         // bin (row, k2) pairs with bin N - k: rows k1 and N1 - k1 swap, k2 -> N2 - 1 - k2; row 0 -> N2 - k2
         const int phalf = (uc == 0) ? half : 1 - half;
@@ -207,6 +231,26 @@ __global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
   }
 }
 
+template <int L, int UB, int FB, int SQ>
+__global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
+  rowpass_tile<L, UB, FB, SQ>(a, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+template <int L, int UB, int FB, int SQ>
+__global__ void __launch_bounds__(UB * FB * L / (4 * SQ))
+    k_rowpass_batch(const RowArgs* __restrict__ tasks, const int32_t* __restrict__ tile_end, int n_tasks) {
+  const int total = tile_end[n_tasks - 1];
+  int t = 0;
+  for (int tile = (int)blockIdx.x; tile < total; tile += (int)gridDim.x) {
+    while (tile >= tile_end[t]) ++t;
+    const int local = tile - (t ? tile_end[t - 1] : 0);
+    const RowArgs a = tasks[t];
+    const int nbx = a.N1 / 2 / UB;
+    rowpass_tile<L, UB, FB, SQ>(a, local % nbx, local / nbx);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // output: accumulators -> natural channel order (raw spectra, or calibrated Stokes by Eq. 2)
 // ------------------------------------------------------------------------------------------------
@@ -214,13 +258,13 @@ __global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
 constexpr int kOutThreads = 512;  // one channel of the 32 x 16 tile per thread
 
 template <bool STOKES>
-__global__ void __launch_bounds__(kOutThreads) k_output(OutArgs a) {
+__device__ __forceinline__ void output_tile(const OutArgs& a, const int bx, const int by, const int p) {
   constexpr int RT = 32, KT = 16;
   __shared__ double t[4][RT][KT + 1];
   const int L = a.N2, U = a.N1 / 2;
   const int rt = RT < a.N1 ? RT : a.N1;
   const int kt = KT < L / 2 ? KT : L / 2;
-  const int r0 = (int)blockIdx.x * rt, k20 = (int)blockIdx.y * kt, p = (int)blockIdx.z;
+  const int r0 = bx * rt, k20 = by * kt;
   for (int e = (int)threadIdx.x; e < rt * kt; e += kOutThreads) {
     const int rl = e / kt, kk = e % kt;
     const int r = r0 + rl, k2 = k20 + kk;
@@ -289,6 +333,30 @@ __global__ void __launch_bounds__(kOutThreads) k_output(OutArgs a) {
       o[2 * a.C] = (float)Uq;
       o[3 * a.C] = (float)V;
     }
+  }
+}
+
+template <bool STOKES>
+__global__ void __launch_bounds__(kOutThreads) k_output(OutArgs a) {
+  output_tile<STOKES>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z);
+}
+
+// tiles of one instance: (N1 / rt) x (N2 / 2 / kt) x P
+__host__ __device__ inline int output_tiles_x(int N1) { return N1 / (N1 < 32 ? N1 : 32); }
+__host__ __device__ inline int output_tiles_y(int N2) { return N2 / 2 / (N2 / 2 < 16 ? N2 / 2 : 16); }
+
+template <bool STOKES>
+__global__ void __launch_bounds__(kOutThreads)
+    k_output_batch(const OutArgs* __restrict__ tasks, const int32_t* __restrict__ tile_end, int n_tasks) {
+  const int total = tile_end[n_tasks - 1];
+  int t = 0;
+  for (int tile = (int)blockIdx.x; tile < total; tile += (int)gridDim.x) {
+    while (tile >= tile_end[t]) ++t;
+    const int local = tile - (t ? tile_end[t - 1] : 0);
+    const OutArgs a = tasks[t];
+    const int nx = output_tiles_x(a.N1), ny = output_tiles_y(a.N2);
+    output_tile<STOKES>(a, local % nx, (local / nx) % ny, local / (nx * ny));
+    __syncthreads();
   }
 }
 
@@ -385,6 +453,102 @@ hipError_t launch_rowpass(int N2, const RowArgs& a, const Launch& s) {
     case 2048: return rowpass_launch<2048, 1, 2, 2>(a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---- batched (persistent) launches: grid = min(tiles, workgroups resident on the device)
+
+// workgroups of a kernel resident on one CU, queried once per kernel (not a stream operation, so a launch
+// made during graph capture after a first eager launch needs no query)
+template <class K>
+static int resident_per_cu(K kernel, int block) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  const void* key = reinterpret_cast<const void*>(kernel);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  cache[key] = per_cu;
+  return per_cu;
+}
+
+template <class K>
+static unsigned persistent_grid(K kernel, int block, int total, int n_cu) {
+  const long resident = (long)resident_per_cu(kernel, block) * n_cu;
+  return (unsigned)(total < resident ? total : resident);
+}
+
+#define PS_LAUNCH_BATCH(kernel, block, total, n_cu, l, ...)                                          \
+  do {                                                                                             \
+    const unsigned g_ = persistent_grid(kernel, block, total, n_cu);                               \
+    hipExtLaunchKernelGGL(kernel, dim3(g_), dim3(block), 0, (l).stream, (l).start, (l).stop, 0, __VA_ARGS__); \
+  } while (0)
+
+template <int L, int COLS, int V>
+static hipError_t colpass_batch_bits(int bits, bool fast, const BatchArgs& b, const Launch& s) {
+  constexpr int block = L * COLS / (8 * V);
+  const ColArgs* t = static_cast<const ColArgs*>(b.tasks);
+  switch (bits) {
+    case 2: PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 2, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks); break;
+    case 4: PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 4, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks); break;
+    case 8:
+      if (fast) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 8, true>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+      else PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 8, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+      break;
+    case 32: PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 32, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_colpass_batch(int N1, int bits, bool fast, const BatchArgs& b, const Launch& s) {
+  constexpr int V = PS_COLPASS_V;
+  switch (N1) {
+    case 16: return colpass_batch_bits<16, 16, 2>(bits, fast, b, s);
+    case 32: return colpass_batch_bits<32, 16, 2>(bits, fast, b, s);
+    case 64: return colpass_batch_bits<64, 16, 2>(bits, fast, b, s);
+    case 128: return colpass_batch_bits<128, 16, 2>(bits, fast, b, s);
+    case 256: return colpass_batch_bits<256, PS_COLPASS_COLS, V>(bits, fast, b, s);
+    case 512: return colpass_batch_bits<512, PS_COLPASS_COLS, V>(bits, fast, b, s);
+    case 1024: return colpass_batch_bits<1024, 8, 2>(bits, fast, b, s);
+    case 2048: return colpass_batch_bits<2048, 4, 2>(bits, fast, b, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int L, int UB, int FB, int SQ>
+static hipError_t rowpass_batch_launch(const BatchArgs& b, const Launch& s) {
+  constexpr int block = UB * FB * L / (4 * SQ);
+  PS_LAUNCH_BATCH((k_rowpass_batch<L, UB, FB, SQ>), block, b.total, b.n_cu, s,
+                  static_cast<const RowArgs*>(b.tasks), b.tile_end, b.n_tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowpass_batch(int N2, const BatchArgs& b, const Launch& s) {
+  constexpr int SQ = PS_ROWPASS_SQ;
+  switch (N2) {
+    case 16: return rowpass_batch_launch<16, 8, 8, 2>(b, s);
+    case 32: return rowpass_batch_launch<32, 8, 8, 2>(b, s);
+    case 64: return rowpass_batch_launch<64, 4, 8, 2>(b, s);
+    case 128: return rowpass_batch_launch<128, 2, 8, 2>(b, s);
+    case 256: return rowpass_batch_launch<256, 1, 8, SQ>(b, s);
+    case 512: return rowpass_batch_launch<512, 1, 8, SQ>(b, s);
+    case 1024: return rowpass_batch_launch<1024, 1, 4, 2>(b, s);
+    case 2048: return rowpass_batch_launch<2048, 1, 2, 2>(b, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int rowpass_units_per_tile(int N2) { return N2 >= 256 ? 1 : (N2 == 128 ? 2 : (N2 == 64 ? 4 : 8)); }
+
+int output_tiles(int N1, int N2, int P) { return output_tiles_x(N1) * output_tiles_y(N2) * P; }
+
+hipError_t launch_output_batch(bool stokes, const BatchArgs& b, const Launch& s) {
+  const OutArgs* t = static_cast<const OutArgs*>(b.tasks);
+  if (stokes) PS_LAUNCH_BATCH((k_output_batch<true>), kOutThreads, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+  else PS_LAUNCH_BATCH((k_output_batch<false>), kOutThreads, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+  return hipGetLastError();
 }
 
 static dim3 output_grid(const OutArgs& a) {
