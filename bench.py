@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the 16-bit precision-form section")
+    ap.add_argument("--no-batching", action="store_true", help="skip the 64-instance batching section")
+    ap.add_argument("--ring", type=int, default=24, help="distinct input buffers cycled through by the steps")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time (whole integrations)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
     return ap.parse_args()
@@ -238,6 +240,110 @@ def precision_form(pk, torch, dev, steps, warmup, with_oracle=True):
     return res
 
 
+def batching_form(pk, torch, dev, reps):
+    """Batching workload: 64 uneven instances (N = 2^12 .. 2^20, 8 .. 256 frames, 2- or 8-bit, one X/Y pair
+    each).  One integration of all of them as 64 separate plans, as one plan (grouped persistent launches,
+    one Stokes launch), and as that plan's captured hipGraph replayed.  The input of each instance is its own
+    device buffer, filled by repeating a block of quantised correlated noise of its format (the kernels'
+    cost does not depend on the values)."""
+    import numpy as np
+    import synth
+    e, F, bits, rho = synth.batching_params(64)
+    pool = {}
+    for b in (2, 8):
+        d = synth.make_correlated_noise(int(b), 0.25, 1 << 16, 32, seed_extra=int(b))
+        pool[int(b)] = torch.from_numpy(d["packed"]).to(dev)
+    insts, packed = [], []
+    for i in range(64):
+        N, Fi, b = 1 << int(e[i]), int(F[i]), int(bits[i])
+        nbytes = Fi * N * 2 * b // 8
+        src = pool[b]
+        buf = src.repeat((nbytes + src.numel() - 1) // src.numel())[:nbytes].clone()
+        insts.append(pk.Instance(fft_len=N, bits=b))
+        packed.append(buf)
+    samples = int(sum(int(F[i]) * (1 << int(e[i])) * 2 for i in range(64)))
+    outs = [torch.empty((1, 4, I.channels), dtype=torch.float32, device=dev) for I in insts]
+    side = torch.cuda.Stream(dev)
+    with torch.cuda.stream(side):
+        sep = [pk.Plan([I], device=dev, stream=side) for I in insts]
+        grp = pk.Plan(insts, device=dev, stream=side)
+    side.synchronize()
+
+    def run_separate():
+        for p, buf, o in zip(sep, packed, outs):
+            p.reset()
+            p.accumulate(buf)
+            p.stokes(out=o)
+
+    def run_grouped():
+        grp.reset()
+        grp.accumulate(packed)
+        grp.stokes_all(outs)
+
+    def timed(fn):
+        with torch.cuda.stream(side):
+            for _ in range(2):
+                fn()
+            side.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            side.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_sep = timed(run_separate)
+    t_grp = timed(run_grouped)
+    grp.graph_capture(run_grouped)
+    t_graph = timed(grp.graph_replay)
+    del grp
+    # the same with every instance on its autotuned schedule (tuned alone, one shape at a time)
+    from paper_1412_1256_amd import autotune
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "polaris_bench_batch_tune.json")
+    t0 = time.perf_counter()
+    scheds = [autotune.tune(I, device=dev, reps=3, cache=cache)[0] for I in insts]
+    tune_s = time.perf_counter() - t0
+    with torch.cuda.stream(side):
+        tuned = pk.Plan(insts, device=dev, stream=side, schedules=scheds)
+    side.synchronize()
+
+    def run_tuned():
+        tuned.reset()
+        tuned.accumulate(packed)
+        tuned.stokes_all(outs)
+
+    tuned.graph_capture(run_tuned)
+    t_tuned = timed(tuned.graph_replay)
+    return {"workload": "64 instances, N = 2^12..2^20, 8..256 frames, 2/8-bit, one X/Y pair each",
+            "samples_per_integration": samples, "separate_plans_us": t_sep * 1e6, "grouped_us": t_grp * 1e6,
+            "grouped_graph_us": t_graph * 1e6, "grouped_graph_tuned_us": t_tuned * 1e6,
+            "Gsamples_per_s_grouped_graph": samples / t_graph / 1e9,
+            "Gsamples_per_s_grouped_graph_tuned": samples / t_tuned / 1e9,
+            "x_realtime_tuned": samples / 2 / SAMPLE_RATE / t_tuned,
+            "speedup_grouped_vs_separate": t_sep / t_grp, "speedup_graph_vs_separate": t_sep / t_graph,
+            "speedup_tuned_vs_separate": t_sep / t_tuned, "tuning_seconds": tune_s,
+            "launches_separate": 64 * 3, "n_instances": 64}
+
+
+def autotune_form(pk, torch, dev, inst, packed, steps):
+    """The paper workload with the default schedule and with the autotuner's choice (timed on this device)."""
+    from paper_1412_1256_amd import autotune
+    I = pk.Instance.from_synth(inst)
+    best, timings = autotune.tune(I, device=dev, frames=inst["n_frames"], reps=5, cache=os.path.join(
+        os.environ.get("TMPDIR", "/tmp"), "polaris_bench_tune.json"), force=True)
+    res = {"candidates": len(timings), "best": best.__dict__}
+    for name, sched in (("default", None), ("tuned", best)):
+        plan = pk.Plan([I], device=dev, schedules=None if sched is None else [sched])
+        out = torch.empty((1, 4, I.channels), dtype=torch.float32, device=dev)
+
+        def step():
+            plan.reset()
+            plan.accumulate(packed)
+            plan.stokes(psi=0.25, out=out)
+
+        res[f"{name}_us"] = time_steps(torch, dev, step, steps, 3) * 1e6
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -259,12 +365,18 @@ def main():
     N, S, F = inst["fft_len"], inst["n_streams"], inst["n_frames"]
     samples = F * N * S
     packed = torch.from_numpy(inst["packed"]).to(dev)
+    # streaming: each step integrates a different, HBM-resident second of data (a ring of copies larger
+    # than the 256 MB last-level cache), so no step finds its input in cache
+    ring = [packed.clone() for _ in range(max(1, args.ring))]
     plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev)
     iquv = torch.empty((1, 4, N // 2), dtype=torch.float32, device=dev)
+    k = {"i": 0}
 
     def step():
+        buf = ring[k["i"] % len(ring)]
+        k["i"] += 1
         plan.reset()
-        plan.accumulate(packed)
+        plan.accumulate(buf)
         plan.stokes(psi=0.25, out=iquv)
 
     for _ in range(args.warmup):
@@ -307,7 +419,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "paper-shaped integration: 2 int8 streams at 16 Msps, 2^18-pt rect frames, "
-                               "61 frames (0.999424 s), FP32 passes + FP64 accumulation, Stokes",
+                               "61 frames (0.999424 s), FP32 passes + FP64 accumulation, Stokes; each step a "
+                               f"different HBM-resident second of data (ring of {len(ring)})",
                    "n_streams": S, "bits": 8, "fft_len": N, "frames": F, "samples_per_step": samples},
         "x_realtime": (F * N / SAMPLE_RATE) / dt,
         "fft_tflops_nominal_5NlogN": nominal_flop / dt / 1e12,
@@ -319,6 +432,9 @@ def main():
         "roofline": roofline,
     }
     out["fwd_bwd"] = differentiation_form(pk, torch, dev, max(5, args.steps // 2), 2)
+    out["autotune"] = autotune_form(pk, torch, dev, inst, packed, args.steps)
+    if not args.no_batching:
+        out["batching_form"] = batching_form(pk, torch, dev, max(3, args.steps // 10))
     if not args.no_precision:
         out["precision_form"] = precision_form(pk, torch, dev, max(3, args.steps // 10), 1,
                                                with_oracle=not args.no_cpu_baseline)

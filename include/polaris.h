@@ -76,7 +76,7 @@ typedef struct ps_plan_s* ps_plan_t;
  *   accum       PS_ACC_FP64 (any precision), or PS_ACC_KAHAN32 (16-bit passes only): the products of
  *               the frames of one pass launch are summed per channel in registers, in FP64 or in
  *               compensated FP32, then added to FP64 accumulators.
- *   chunk_frames  frames processed per internal pass pair (0 = 64); bounds the workspace.
+ *   chunk_frames  frames processed per internal pass pair (0 = max(64, 2^22 / N)); bounds the workspace.
  *   sample_rate_hz  metadata only (channel width = sample_rate_hz / N).
  */
 typedef struct {
@@ -120,6 +120,34 @@ typedef struct {
 /* Validate n_inst instances, build host tables and report the workspace size (bytes, 256-aligned).
  * Errors: PS_ERR_ARG for bad fields, PS_ERR_UNSUPPORTED for valid but unimplemented options. */
 ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_t* workspace_bytes);
+
+/*
+ * Schedule of one instance's passes (what the autotuner chooses; every field 0 = the default):
+ *   log2_n1         the split N = N1 x N2 of the four-step transform (default floor(log2 N / 2));
+ *   colpass_cols    columns per column-pass workgroup (its LDS tile width and workgroup size);
+ *   rowpass_frames  frames per row-pass workgroup batch (its workgroup size);
+ *   col_wg_per_cu   column-pass workgroups per CU that the frame grouping aims at (1 .. 8);
+ *   rowpass_slots   accumulator slots G (a power of two, 1 .. 64): frame a of the integration goes to slot
+ *                   a mod G, so G frame groups run the row pass in parallel; readers sum the slots in
+ *                   order.  Default: enough for about 256 row-pass workgroups (1 for 16-bit passes).
+ * The results of every schedule agree within rounding; only speed differs.
+ */
+typedef struct {
+  int32_t log2_n1;
+  int32_t colpass_cols;
+  int32_t rowpass_frames;
+  int32_t col_wg_per_cu;
+  int32_t rowpass_slots;
+} ps_schedule;
+
+/* ps_plan with one schedule per instance (sched may be NULL).  PS_ERR_UNSUPPORTED for a schedule that has
+ * no compiled kernels for the instance. */
+ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, int32_t n_inst, ps_plan_t* out,
+                            size_t* workspace_bytes);
+
+/* The schedules that can run an instance (host only): writes up to capacity of them to out (may be NULL)
+ * and their total number to *count. */
+ps_status ps_schedule_candidates(const ps_instance* inst, ps_schedule* out, int32_t capacity, int32_t* count);
 
 /* Attach a device workspace (>= the reported size, 256-byte aligned) and a HIP stream (hipStream_t,
  * NULL = the default stream); uploads the FP64-generated twiddle and window tables and waits for the

@@ -46,6 +46,36 @@ class _CalGrad(C.Structure):
                 ("d_taps", C.c_void_p)]
 
 
+class _Schedule(C.Structure):
+    _fields_ = [("log2_n1", C.c_int32), ("colpass_cols", C.c_int32), ("rowpass_frames", C.c_int32),
+                ("col_wg_per_cu", C.c_int32), ("rowpass_slots", C.c_int32)]
+
+
+@dataclass(frozen=True)
+class Schedule:
+    """Pass schedule of one instance (see ``ps_schedule``); 0 = default."""
+    log2_n1: int = 0
+    colpass_cols: int = 0
+    rowpass_frames: int = 0
+    col_wg_per_cu: int = 0
+    rowpass_slots: int = 0
+
+    def to_c(self) -> _Schedule:
+        return _Schedule(self.log2_n1, self.colpass_cols, self.rowpass_frames, self.col_wg_per_cu,
+                         self.rowpass_slots)
+
+
+def schedule_candidates(instance) -> list:
+    """Every schedule the library can run the instance with."""
+    c = instance.to_c()
+    n = C.c_int32()
+    _check(lib().ps_schedule_candidates(C.byref(c), None, 0, C.byref(n)))
+    arr = (_Schedule * max(1, n.value))()
+    _check(lib().ps_schedule_candidates(C.byref(c), arr, n.value, C.byref(n)))
+    return [Schedule(a.log2_n1, a.colpass_cols, a.rowpass_frames, a.col_wg_per_cu, a.rowpass_slots)
+            for a in arr[:n.value]]
+
+
 _LIB = None
 
 
@@ -78,6 +108,8 @@ def lib():
             "ps_profile_enable": [vp, i32],
             "ps_profile_read": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
             "ps_stokes_all": [vp, C.POINTER(_Cal), C.POINTER(vp)],
+            "ps_plan_scheduled": [C.POINTER(_Instance), C.POINTER(_Schedule), i32, C.POINTER(vp), C.POINTER(sz)],
+            "ps_schedule_candidates": [C.POINTER(_Instance), C.POINTER(_Schedule), i32, C.POINTER(i32)],
             "ps_graph_begin": [vp],
             "ps_graph_end": [vp, i32],
             "ps_graph_launch": [vp],
@@ -161,16 +193,28 @@ def plan_workspace_bytes(instances: Sequence[Instance]) -> int:
 class Plan:
     """A bound plan: host metadata in the library, workspace in a torch uint8 tensor on one device."""
 
-    def __init__(self, instances: Sequence[Instance], device=None, stream=None):
+    def __init__(self, instances: Sequence[Instance], device=None, stream=None, schedules=None, tune: bool = False):
+        """schedules: None or one Schedule (or None) per instance; tune=True takes each instance's schedule
+        from the autotuner (its JSON cache, timing the candidates on this device on a miss)."""
         import torch
         self.torch = torch
         self.instances = list(instances)
+        self.device = torch.device(device if device is not None else "cuda")
+        if tune:
+            from . import autotune
+            schedules = [autotune.best_schedule(i, device=self.device) for i in self.instances]
         arr = (_Instance * len(self.instances))(*[i.to_c() for i in self.instances])
         h = C.c_void_p()
         nbytes = C.c_size_t()
-        _check(lib().ps_plan(arr, len(self.instances), C.byref(h), C.byref(nbytes)))
+        if schedules is None:
+            _check(lib().ps_plan(arr, len(self.instances), C.byref(h), C.byref(nbytes)))
+        else:
+            if len(schedules) != len(self.instances):
+                raise ValueError("one schedule per instance")
+            sarr = (_Schedule * len(self.instances))(*[(x or Schedule()).to_c() for x in schedules])
+            _check(lib().ps_plan_scheduled(arr, sarr, len(self.instances), C.byref(h), C.byref(nbytes)))
+        self.schedules = schedules
         self._h = h
-        self.device = torch.device(device if device is not None else "cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         # the library needs 256-byte alignment; over-allocate and offset
         self._ws_raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)

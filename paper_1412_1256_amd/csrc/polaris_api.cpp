@@ -70,6 +70,10 @@ struct Inst {
   size_t off_wpart = 0, off_ga = 0, off_red = 0, off_norm = 0, off_dw = 0;
   bool taps() const { return cfg.window == PS_WIN_TAPS; }
   std::vector<float> tw_col, tw_row, tw_lo, win, ones;
+  // schedule (autotuner's choices): columns per column-pass workgroup, frames per row-pass batch,
+  // column-pass workgroups per CU aimed at by the frame grouping
+  int cols = 0, fb = 0, col_wgs = 1;
+  int G = 1;  // accumulator slots (row-pass frame groups)
   // precision form: 16-bit DFT matrices of radix 16 and 32 (hi, lo), stage twiddles of the two passes
   bool mx() const { return cfg.precision != PS_PREC_FP32; }
   size_t off_mx16 = 0, off_mx32 = 0, off_tws_col = 0, off_tws_row = 0;
@@ -78,7 +82,9 @@ struct Inst {
   double sumw2 = 0.0;
   bool first = true;
   int64_t n_frames = 0;
-  size_t acc_bytes() const { return (size_t)cfg.n_pairs * (size_t)(N1 / 2) * 4 * (size_t)N2 * sizeof(double); }
+  size_t slot_doubles() const { return (size_t)cfg.n_pairs * (size_t)(N1 / 2) * 4 * (size_t)N2; }
+  size_t acc_bytes() const { return (size_t)G * slot_doubles() * sizeof(double); }
+  int slots_used() const { return (int)std::min<int64_t>(G, n_frames); }
 };
 
 }  // namespace
@@ -289,6 +295,59 @@ ps_status upload(ps_plan_t plan, size_t off, const void* src, size_t bytes) {
   return PS_OK;
 }
 
+// Accumulator slots: enough row-pass frame groups that units x pairs x slots reach about 256 workgroups
+// (1 for the 16-bit passes, whose row pass spreads frames over its waves).
+int default_slots(const ps_instance& c, int N1, int N2) {
+  if (c.precision != PS_PREC_FP32) return 1;
+  const int tiles = N1 / 2 / ps::rowpass_units_per_tile(N2) * c.n_pairs;
+  int G = 1;
+  while (G < 64 && G * tiles < 256) G *= 2;
+  return G;
+}
+
+// Why a schedule cannot run an instance (nullptr when it can).  why: optional message buffer (160 bytes).
+const char* schedule_error(const ps_instance& c, const ps_schedule& s, char* why) {
+  static thread_local char buf[160];
+  char* w = why ? why : buf;
+  const int m = ilog2_exact(c.fft_len);
+  const int m1 = s.log2_n1 ? s.log2_n1 : m / 2, m2 = m - m1;
+  if (c.precision != PS_PREC_FP32) {
+    if (m1 != m / 2 || s.colpass_cols || s.rowpass_frames || s.col_wg_per_cu > 1 || s.rowpass_slots > 1) {
+      snprintf(w, 160, "16-bit passes run with the default schedule only");
+      return w;
+    }
+    return nullptr;
+  }
+  if (m1 < 4 || m1 > 11 || m2 < 4 || m2 > 11) {
+    snprintf(w, 160, "split 2^%d x 2^%d outside 2^4 .. 2^11 per pass", m1, m2);
+    return w;
+  }
+  if (c.window == PS_WIN_TAPS && (m2 > 9 || m1 > 11)) {
+    snprintf(w, 160, "the learnable window's backward needs rows of at most 2^9 points");
+    return w;
+  }
+  const int N1 = 1 << m1, N2 = 1 << m2;
+  const int cols = s.colpass_cols ? s.colpass_cols : ps::colpass_cols(N1);
+  const int fb = s.rowpass_frames ? s.rowpass_frames : ps::rowpass_frames(N2);
+  if (!ps::colpass_has(N1, cols) || N2 % cols) {
+    snprintf(w, 160, "no column pass of %d columns for N1 = %d", cols, N1);
+    return w;
+  }
+  if (!ps::rowpass_has(N2, fb)) {
+    snprintf(w, 160, "no row pass of %d frames per batch for N2 = %d", fb, N2);
+    return w;
+  }
+  if (s.col_wg_per_cu < 0 || s.col_wg_per_cu > 8) {
+    snprintf(w, 160, "col_wg_per_cu %d not in 0..8", s.col_wg_per_cu);
+    return w;
+  }
+  if (s.rowpass_slots < 0 || s.rowpass_slots > 64 || (s.rowpass_slots & (s.rowpass_slots - 1))) {
+    snprintf(w, 160, "rowpass_slots %d is not a power of two in 1..64", s.rowpass_slots);
+    return w;
+  }
+  return nullptr;
+}
+
 // Column-pass arguments of frames f0 .. f0+nf-1 of instance I.  groups: frame groups of the tile grid (0:
 // as many as make the tiles about one per CU).  *fast: the int8 two-stream path (32-bit input offsets).
 ps::ColArgs col_args(ps_plan_t plan, const Inst& I, const uint8_t* base, int64_t f0, int nf, int64_t groups,
@@ -307,11 +366,10 @@ ps::ColArgs col_args(ps_plan_t plan, const Inst& I, const uint8_t* base, int64_t
     ca.px[p] = I.cfg.pair_x[p];
     ca.py[p] = I.cfg.pair_y[p];
   }
-  const int cols = ps::colpass_cols((int)I.N1);
-  ca.n_colblk = (int32_t)(I.N2 / cols);
+  ca.n_colblk = (int32_t)(I.N2 / I.cols);
   ca.n_frames = nf;
   const int64_t per_frame = (int64_t)ca.n_colblk * ca.P;
-  if (groups <= 0) groups = (plan->n_cu + per_frame / 2) / per_frame;
+  if (groups <= 0) groups = ((int64_t)I.col_wgs * plan->n_cu + per_frame / 2) / per_frame;
   if (groups < 1) groups = 1;
   if (groups > nf) groups = nf;
   ca.frames_per_block = (int32_t)((nf + groups - 1) / groups);
@@ -329,7 +387,8 @@ int col_tiles(const ps::ColArgs& ca) {
   return groups * ca.P * ca.n_colblk;
 }
 
-ps::RowArgs row_args(ps_plan_t plan, const Inst& I, int nf, bool first) {
+// Row-pass arguments of nf frames following the F0 frames already in the integration.
+ps::RowArgs row_args(ps_plan_t plan, const Inst& I, int nf, int64_t F0) {
   ps::RowArgs ra{};
   ra.T = ws_ptr<float2>(plan, I.off_T);
   ra.N1 = (int32_t)I.N1;
@@ -337,7 +396,9 @@ ps::RowArgs row_args(ps_plan_t plan, const Inst& I, int nf, bool first) {
   ra.n_frames = nf;
   ra.tw_row = ws_ptr<float2>(plan, I.off_tw_row);
   ra.acc = ws_ptr<double>(plan, I.off_acc);
-  ra.first = first ? 1 : 0;
+  ra.G = I.G;
+  ra.F0 = F0;
+  ra.slot_stride = (int64_t)I.slot_doubles();
   return ra;
 }
 
@@ -389,6 +450,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
   struct L1 {
     int kind, len, bits;
     bool fast;
+    int var;  // columns per workgroup (column pass) or frames per batch (row pass)
     size_t task0, n;
     int total;
   };
@@ -396,8 +458,8 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
   for (int64_t r = 0; r < rounds; ++r) {
     std::vector<L1> col_l, row_l;
     // column-pass groups
-    std::vector<std::pair<std::vector<int>, std::vector<ps::ColArgs>>> cg;  // key (N1, bits, fast)
-    std::vector<std::pair<int, std::vector<ps::RowArgs>>> rg;                // key N2
+    std::vector<std::pair<std::vector<int>, std::vector<ps::ColArgs>>> cg;  // key (N1, bits, fast, columns)
+    std::vector<std::pair<std::vector<int>, std::vector<ps::RowArgs>>> rg;   // key (N2, frames per batch)
     for (size_t i = 0; i < plan->inst.size(); ++i) {
       const Inst& I = plan->inst[i];
       if (I.mx()) continue;
@@ -407,23 +469,24 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
       bool fast = false;
       // frame groups of about 8 frames: many instances share the device
       const ps::ColArgs ca = col_args(plan, I, static_cast<const uint8_t*>(packed_dev[i]), f0, nf, (nf + 7) / 8, &fast);
-      const std::vector<int> key = {(int)I.N1, I.cfg.bits, fast ? 1 : 0};
+      const std::vector<int> key = {(int)I.N1, I.cfg.bits, fast ? 1 : 0, I.cols};
       auto it = std::find_if(cg.begin(), cg.end(), [&](const auto& g) { return g.first == key; });
       if (it == cg.end()) {
         cg.push_back({key, {}});
         it = cg.end() - 1;
       }
       it->second.push_back(ca);
-      const ps::RowArgs ra = row_args(plan, I, nf, I.first && r == 0);
-      auto jt = std::find_if(rg.begin(), rg.end(), [&](const auto& g) { return g.first == (int)I.N2; });
+      const ps::RowArgs ra = row_args(plan, I, nf, I.n_frames + f0);
+      const std::vector<int> rkey = {(int)I.N2, I.fb};
+      auto jt = std::find_if(rg.begin(), rg.end(), [&](const auto& g) { return g.first == rkey; });
       if (jt == rg.end()) {
-        rg.push_back({(int)I.N2, {}});
+        rg.push_back({rkey, {}});
         jt = rg.end() - 1;
       }
       jt->second.push_back(ra);
     }
     for (const auto& g : cg) {
-      L1 l{0, g.first[0], g.first[1], g.first[2] != 0, cols.size(), g.second.size(), 0};
+      L1 l{0, g.first[0], g.first[1], g.first[2] != 0, g.first[3], cols.size(), g.second.size(), 0};
       int total = 0;
       for (const ps::ColArgs& ca : g.second) {
         cols.push_back(ca);
@@ -434,11 +497,11 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
       launches.push_back(l);
     }
     for (const auto& g : rg) {
-      L1 l{1, g.first, 0, false, rows.size(), g.second.size(), 0};
+      L1 l{1, g.first[0], 0, false, g.first[1], rows.size(), g.second.size(), 0};
       int total = 0;
       for (const ps::RowArgs& ra : g.second) {
         rows.push_back(ra);
-        total += ra.N1 / 2 / ps::rowpass_units_per_tile(g.first) * ra.P;
+        total += ra.N1 / 2 / ps::rowpass_units_per_tile(g.first[0]) * ra.P * ra.G;
         rend.push_back(total);
       }
       l.total = total;
@@ -465,11 +528,11 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
     if (l.kind == 0) {
       b.tasks = dev + l.task0 * sizeof(ps::ColArgs);
       b.tile_end = reinterpret_cast<const int32_t*>(dev + cend_at) + l.task0;
-      e = timed(plan, PS_KERNEL_COLPASS, [&](const ps::Launch& x) { return ps::launch_colpass_batch(l.len, l.bits, l.fast, b, x); });
+      e = timed(plan, PS_KERNEL_COLPASS, [&](const ps::Launch& x) { return ps::launch_colpass_batch(l.len, l.var, l.bits, l.fast, b, x); });
     } else {
       b.tasks = dev + rows_at + l.task0 * sizeof(ps::RowArgs);
       b.tile_end = reinterpret_cast<const int32_t*>(dev + rend_at) + l.task0;
-      e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& x) { return ps::launch_rowpass_batch(l.len, b, x); });
+      e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& x) { return ps::launch_rowpass_batch(l.len, l.var, b, x); });
     }
     if (e != hipSuccess) return hip_fail(e, "grouped pass launch");
   }
@@ -536,12 +599,49 @@ ps_status accumulate_mx(ps_plan_t plan, Inst& I, const ps::ColArgs& ca) {
 extern "C" {
 
 ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_t* workspace_bytes) {
+  return ps_plan_scheduled(inst, nullptr, n_inst, out, workspace_bytes);
+}
+
+ps_status ps_schedule_candidates(const ps_instance* inst, ps_schedule* out, int32_t capacity, int32_t* count) {
+  if (!inst || !count) return fail(PS_ERR_ARG, "null argument to ps_schedule_candidates");
+  ps_status st = validate_instance(*inst, 0);
+  if (st != PS_OK) return st;
+  std::vector<ps_schedule> v;
+  const int m = ilog2_exact(inst->fft_len);
+  if (inst->precision != PS_PREC_FP32) {
+    v.push_back(ps_schedule{m / 2, 0, 0, 0, 1});
+  } else {
+    for (int m1 = m / 2 - 1; m1 <= m / 2 + 1; ++m1) {
+      const int N1 = 1 << m1, N2 = 1 << (m - m1);
+      if (m1 < 4 || m - m1 < 4 || m1 > 11 || m - m1 > 11) continue;
+      const int G0 = default_slots(*inst, N1, N2);
+      for (int cols = 4; cols <= 16; cols *= 2)
+        for (int fb = 2; fb <= 8; fb *= 2)
+          for (int wg = 1; wg <= 4; wg *= 2)
+            for (int G = std::max(1, G0 / 2); G <= std::min(64, 2 * G0); G *= 2) {
+              const ps_schedule c{m1, cols, fb, wg, G};
+              if (schedule_error(*inst, c, nullptr) == nullptr) v.push_back(c);
+            }
+    }
+  }
+  *count = (int32_t)v.size();
+  if (out)
+    for (int32_t i = 0; i < capacity && i < (int32_t)v.size(); ++i) out[i] = v[(size_t)i];
+  return PS_OK;
+}
+
+ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, int32_t n_inst, ps_plan_t* out,
+                            size_t* workspace_bytes) {
   if (!inst || !out || !workspace_bytes) return fail(PS_ERR_ARG, "null argument to ps_plan");
   *out = nullptr;
   if (n_inst < 1 || n_inst > 4096) return fail(PS_ERR_ARG, "n_inst %d not in 1..4096", n_inst);
   for (int i = 0; i < n_inst; ++i) {
     ps_status st = validate_instance(inst[i], i);
     if (st != PS_OK) return st;
+    if (sched) {
+      char why[160];
+      if (schedule_error(inst[i], sched[i], why)) return fail(PS_ERR_UNSUPPORTED, "instance %d: %s", i, why);
+    }
   }
   ps_plan_s* plan = new (std::nothrow) ps_plan_s;
   if (!plan) return fail(PS_ERR_ARG, "out of host memory");
@@ -552,13 +652,19 @@ ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_
     I.cfg = inst[i];
     I.N = inst[i].fft_len;
     I.m = ilog2_exact(I.N);
-    I.m1 = I.m / 2;
+    I.m1 = (sched && sched[i].log2_n1) ? sched[i].log2_n1 : I.m / 2;
     I.m2 = I.m - I.m1;
     I.N1 = int64_t(1) << I.m1;
     I.N2 = int64_t(1) << I.m2;
     I.C = I.N / 2;
-    I.chunk = inst[i].chunk_frames ? inst[i].chunk_frames : 64;
-    I.fast = inst[i].bits == 8 && inst[i].n_streams == 2 && inst[i].n_pairs == 1 && inst[i].pair_x[0] == 0 &&
+    I.cols = (sched && sched[i].colpass_cols) ? sched[i].colpass_cols : ps::colpass_cols((int)I.N1);
+    I.fb = (sched && sched[i].rowpass_frames) ? sched[i].rowpass_frames : ps::rowpass_frames((int)I.N2);
+    I.col_wgs = (sched && sched[i].col_wg_per_cu) ? sched[i].col_wg_per_cu : 1;
+    I.G = (sched && sched[i].rowpass_slots) ? sched[i].rowpass_slots : default_slots(I.cfg, (int)I.N1, (int)I.N2);
+    // short transforms take more frames per pass (inter-pass buffer of at most 32 MiB per pair)
+    I.chunk = inst[i].chunk_frames ? inst[i].chunk_frames : (int64_t)std::max<int64_t>(64, (int64_t(1) << 22) / I.N);
+    // word loads of the column pass: 2-, 4- and 8-bit codes of two streams correlated as (0, 1)
+    I.fast = inst[i].bits <= 8 && inst[i].n_streams == 2 && inst[i].n_pairs == 1 && inst[i].pair_x[0] == 0 &&
              inst[i].pair_y[0] == 1;
     build_tables(I);
     I.off_tw_col = off; off = align_up(off + (size_t)I.N1 * 8);
@@ -713,10 +819,10 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
         continue;
       }
       hipError_t e = timed(plan, PS_KERNEL_COLPASS,
-                           [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cfg.bits, fast, ca, l); });
+                           [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cols, I.cfg.bits, fast, ca, l); });
       if (e != hipSuccess) return hip_fail(e, "column pass launch");
-      const ps::RowArgs ra = row_args(plan, I, nf, I.first);
-      e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& l) { return ps::launch_rowpass((int)I.N2, ra, l); });
+      const ps::RowArgs ra = row_args(plan, I, nf, I.n_frames);
+      e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& l) { return ps::launch_rowpass((int)I.N2, I.fb, ra, l); });
       if (e != hipSuccess) return hip_fail(e, "row pass launch");
       I.first = false;
       I.n_frames += nf;
@@ -728,6 +834,8 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
 static ps::OutArgs out_args(ps_plan_t plan, const Inst& I) {
   ps::OutArgs o{};
   o.acc = ws_ptr<double>(plan, I.off_acc);
+  o.slots = I.slots_used();
+  o.slot_stride = (int64_t)I.slot_doubles();
   o.N1 = (int32_t)I.N1;
   o.N2 = (int32_t)I.N2;
   o.P = I.cfg.n_pairs;
@@ -891,6 +999,8 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
   if (I.N2 > 512) return fail(PS_ERR_UNSUPPORTED, "the adjoint is built for fft_len <= 2^18");
   ps::BwChanArgs ca{};
   ca.acc = ws_ptr<double>(plan, I.off_acc);
+  ca.slots = I.slots_used();
+  ca.slot_stride = (int64_t)I.slot_doubles();
   ca.N1 = (int32_t)I.N1;
   ca.P = I.cfg.n_pairs;
   ca.C = I.C;
@@ -934,7 +1044,7 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
       col.px[p] = I.cfg.pair_x[p];
       col.py[p] = I.cfg.pair_y[p];
     }
-    col.n_colblk = (int32_t)(I.N2 / ps::colpass_cols((int)I.N1));
+    col.n_colblk = (int32_t)(I.N2 / ps::colpass_cols((int)I.N1));  // default tiling for the recompute
     col.n_frames = nf;
     {
       const int64_t per_frame = (int64_t)col.n_colblk * col.P;
@@ -949,7 +1059,7 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
     col.tw_lo = ws_ptr<float2>(plan, I.off_tw_lo);
     col.lo_bits = I.m2;
     col.T = ws_ptr<float2>(plan, I.off_T);
-    e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cfg.bits, fast, col, l); });
+    e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, ps::colpass_cols((int)I.N1), I.cfg.bits, fast, col, l); });
     if (e != hipSuccess) return hip_fail(e, "backward forward-recompute launch");
     ps::BwRowArgs ra{};
     ra.T = col.T;

@@ -105,8 +105,15 @@ __global__ void __launch_bounds__(L) k_bw_channel(BwChanArgs a) {
   const double fs = a.n_frames * a.sumw2[0];
   // normalised coherency M (stored sums are 4 XX*, 4 YY*, 4 XY*)
   const double q = 0.25 / fs;
-  const cd mxy = {a.acc[slot + 2 * L] * q, a.acc[slot + 3 * L] * q};
-  const cm2 M = {{a.acc[slot] * q, 0.0}, mxy, cdc(mxy), {a.acc[slot + L] * q, 0.0}};
+  double sum[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double v = a.acc[slot + c * L];
+    for (int g = 1; g < a.slots; ++g) v += a.acc[(int64_t)g * a.slot_stride + slot + c * L];
+    sum[c] = v;
+  }
+  const cd mxy = {sum[2] * q, sum[3] * q};
+  const cm2 M = {{sum[0] * q, 0.0}, mxy, cdc(mxy), {sum[1] * q, 0.0}};
   cd gx = {1.0, 0.0}, gy = {1.0, 0.0}, dx = {0.0, 0.0}, dy = {0.0, 0.0};
   const int64_t gi = 2 * ((int64_t)p * a.C + k);
   if (a.gain_x) gx = {(double)a.gain_x[gi], (double)a.gain_x[gi + 1]};

@@ -237,37 +237,58 @@ struct ColLoader {
   }
 };
 
-// int8, two streams, pair (0, 1): sample t of the pair is the 16-bit word x_t y_t
-template <int V>
-struct ColLoader<8, true, V> {
-  uint32_t raw[8];  // V x (x, y) bytes of each row
+// Two streams, pair (0, 1), 2-, 4- or 8-bit codes: sample t of the pair is the 2*BITS-bit field x_t y_t at
+// bit offset 2*BITS*t, so the V = 2 adjacent columns (t even) of a row are one byte (2-bit), one 16-bit word
+// (4-bit) or one 32-bit word (8-bit), fetched ahead of use.
+template <int BITS, int V>
+struct ColLoaderWords {
+  static_assert(BITS == 2 || BITS == 4 || BITS == 8, "word loader formats");
+  static_assert(BITS == 8 || V == 2, "2- and 4-bit words hold two columns");
+  uint32_t raw[8];  // the row's V x (x, y) codes
   template <int L, int R0>
   __device__ __forceinline__ void fetch(const ColArgs& a, int64_t fb, int ts, int n2b) {
     // row n1 = ts + i L/8 + r L/R0 of frame fb / N: a wave-uniform 64-bit base per (frame, i, r) plus a
-    // 32-bit per-lane offset (the global_load scalar-base form)
-    const uint32_t voff = 2u * (uint32_t)(ts * a.N2 + n2b);
+    // 32-bit per-lane offset (the global_load scalar-base form); byte offset of sample t: t BITS / 4
+    const uint32_t voff = (uint32_t)(ts * a.N2 + n2b) * BITS / 4u;
 #pragma unroll
     for (int i = 0; i < 8 / R0; ++i)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
-        const gbytes base = uniform_gptr(a.in + 2 * (fb + (int64_t)a.N2 * (i * (L / 8) + r * (L / R0))));
-        if constexpr (V == 2)
+        const int64_t t0 = fb + (int64_t)a.N2 * (i * (L / 8) + r * (L / R0));
+        const gbytes base = uniform_gptr(a.in + t0 * BITS / 4);
+        if constexpr (BITS == 8 && V == 2)
           raw[i * R0 + r] = *(const __attribute__((address_space(1))) uint32_t*)(base + voff);
-        else
+        else if constexpr (BITS == 8 || BITS == 4)
           raw[i * R0 + r] = *(const __attribute__((address_space(1))) uint16_t*)(base + voff);
+        else
+          raw[i * R0 + r] = *(const __attribute__((address_space(1))) uint8_t*)(base + voff);
       }
+  }
+  static __device__ __forceinline__ float lvl(uint32_t w, int field) {
+    if constexpr (BITS == 8) {
+      return (float)(int)(int8_t)((w >> (8 * field)) & 0xffu);
+    } else {
+      const int c = (int)((w >> (BITS * field)) & ((1u << BITS) - 1u));
+      return (float)(2 * c - ((1 << BITS) - 1));  // offset binary
+    }
   }
   template <int L, int R0>
   __device__ __forceinline__ void convert(float2 (&v)[V][8], const ColArgs&, int, int, int, int) const {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const uint32_t w = raw[e];
-      v[0][e] = make_float2((float)(int)(int8_t)(w & 0xffu), (float)(int)(int8_t)((w >> 8) & 0xffu));
-      if constexpr (V == 2)
-        v[1][e] = make_float2((float)(int)(int8_t)((w >> 16) & 0xffu), (float)(int)(int8_t)(w >> 24));
+      v[0][e] = make_float2(lvl(w, 0), lvl(w, 1));
+      if constexpr (V == 2) v[1][e] = make_float2(lvl(w, 2), lvl(w, 3));
     }
   }
 };
+
+template <int V>
+struct ColLoader<8, true, V> : ColLoaderWords<8, V> {};
+template <int V>
+struct ColLoader<4, true, V> : ColLoaderWords<4, V> {};
+template <int V>
+struct ColLoader<2, true, V> : ColLoaderWords<2, V> {};
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));

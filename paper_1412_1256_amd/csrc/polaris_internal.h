@@ -31,16 +31,24 @@ struct ColArgs {
   float2* T;                // [n_frames][P][N1][N2]
 };
 
+// Accumulator slots: absolute frame a (counted from ps_reset) is added to slot a mod G, frames of a slot in
+// order; readers sum the slots 0 .. min(G, frames) - 1 in order.  G > 1 lets the row pass of short
+// transforms (few row units) run frame groups in parallel, and the result does not depend on how the
+// frames were split over calls.
 struct RowArgs {
   const float2* T;          // [n_frames][P][N1][N2]
   int32_t N1, P, n_frames;
   const float2* tw_row;     // W_N2^m, m < N2
-  double* acc;              // [P][N1/2][4][N2]: unit-major accumulators of 4 XX*, 4 YY*, 4 XY*
-  int32_t first;            // 1: start from zero instead of the stored sums
+  double* acc;              // [G][P][N1/2][4][N2]: unit-major accumulators of 4 XX*, 4 YY*, 4 XY*
+  int32_t G;                // accumulator slots
+  int64_t F0;               // frames accumulated since ps_reset before this launch
+  int64_t slot_stride;      // doubles per slot
 };
 
 struct OutArgs {
-  const double* acc;        // [P][N1/2][4][N2]
+  const double* acc;        // [slots][P][N1/2][4][N2]
+  int32_t slots;            // slots to sum (min(G, frames))
+  int64_t slot_stride;
   int32_t N1, N2, P;
   int64_t C;
   // Stokes only
@@ -98,7 +106,9 @@ struct WinArgs {            // learnable window from its control points
 };
 
 struct BwChanArgs {         // per-channel adjoint of Eq. 2 and the calibration
-  const double* acc;        // [P][N1/2][4][N2]
+  const double* acc;        // [slots][P][N1/2][4][N2]
+  int32_t slots;
+  int64_t slot_stride;
   int32_t N1, P;
   int64_t C;
   double n_frames;
@@ -160,18 +170,21 @@ struct BatchArgs {
   int32_t n_cu;             // compute units (the grid is the resident workgroups, at most `total`)
 };
 
-hipError_t launch_colpass_batch(int N1, int bits, bool fast, const BatchArgs& b, const Launch& l);
-hipError_t launch_rowpass_batch(int N2, const BatchArgs& b, const Launch& l);
+hipError_t launch_colpass_batch(int N1, int cols, int bits, bool fast, const BatchArgs& b, const Launch& l);
+hipError_t launch_rowpass_batch(int N2, int fb, const BatchArgs& b, const Launch& l);
 hipError_t launch_output_batch(bool stokes, const BatchArgs& b, const Launch& l);
 int rowpass_units_per_tile(int N2);
 int output_tiles(int N1, int N2, int P);
 
-int colpass_cols(int N1);
+int colpass_cols(int N1);     // default columns per column-pass workgroup
+bool colpass_has(int N1, int cols);
+int rowpass_frames(int N2);   // default frames per row-pass workgroup batch
+bool rowpass_has(int N2, int fb);
 hipError_t launch_colpass_mx(int N1, int prec, int bits, const MxColArgs& a, int n_blocks, const Launch& l);
 hipError_t launch_rowpass_mx(int N2, int prec, int accum, const MxRowArgs& a, const Launch& l);
 
-hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, const Launch& l);
-hipError_t launch_rowpass(int N2, const RowArgs& a, const Launch& l);
+hipError_t launch_colpass(int N1, int cols, int bits, bool fast, const ColArgs& a, const Launch& l);
+hipError_t launch_rowpass(int N2, int fb, const RowArgs& a, const Launch& l);
 hipError_t launch_stokes(const OutArgs& a, const Launch& l);
 hipError_t launch_spectra(const OutArgs& a, const Launch& l);
 hipError_t launch_unpack(const void* packed, int bits, int S, int64_t n_time, float* out, hipStream_t s);

@@ -123,9 +123,9 @@ __global__ void __launch_bounds__(L * COLS / (8 * V))
   }
 }
 
-// one tile of the row pass: units bx*UB .. bx*UB+UB-1 of pair p
+// one tile of the row pass: units bx*UB .. bx*UB+UB-1 of pair p, the launch's frames of accumulator slot g
 template <int L, int UB, int FB, int SQ>
-__device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, const int p) {
+__device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, const int p, const int g) {
   constexpr int NT = UB * FB * L / (4 * SQ);
   constexpr int TPS = L / 8;                       // threads per row sequence
   constexpr int NCH = UB * L < NT ? UB * L : NT;   // threads that own channel slots
@@ -149,6 +149,11 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
   PassTw<L> tw;
   tw.load(a.tw_row, ts);
 
+  // this slot's frames of the launch: f = f_first + j G, j < n_loc (absolute frame a = F0 + f, a mod G = g)
+  const int f_first = (int)(((int64_t)g - a.F0 % a.G + a.G) % a.G);
+  const int n_loc = f_first < a.n_frames ? (a.n_frames - f_first + a.G - 1) / a.G : 0;
+  if (n_loc == 0) return;
+  const bool prior = a.F0 > g;  // the slot already holds frames of this integration
   const bool owner = tid < NCH;
   double sxx[SPT], syy[SPT], sxr[SPT], sxi[SPT];
   double* accp[SPT];
@@ -157,9 +162,9 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
     const int id = tid + k * NCH;
     const int ubc = id / L, s = id % L;
     const int uc = bx * UB + ubc;
-    accp[k] = a.acc + ((int64_t)(p * U + uc) * 4) * L + s;
+    accp[k] = a.acc + (int64_t)g * a.slot_stride + ((int64_t)(p * U + uc) * 4) * L + s;
     sxx[k] = syy[k] = sxr[k] = sxi[k] = 0.0;
-    if (owner && !a.first) {
+    if (owner && prior) {
       sxx[k] = accp[k][0];
       syy[k] = accp[k][L];
       sxr[k] = accp[k][2 * L];
@@ -169,11 +174,11 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
 
   const int64_t fstride = (int64_t)a.P * a.N1 * L;  // float2 per frame
   const float2* src = a.T + ((int64_t)p * a.N1 + row) * (int64_t)L + ts;
-  // frames past the end of the launch repeat the last frame (their products are never accumulated)
+  // local frames past the end repeat the last one (their products are never accumulated)
   auto fetch = [&](float2 (&d)[SQ][8], int f0) {
 #pragma unroll
     for (int j = 0; j < SQ; ++j) {
-      const float2* pj = src + (int64_t)min(f0 + fs + j * FS, a.n_frames - 1) * fstride;
+      const float2* pj = src + (int64_t)(f_first + min(f0 + fs + j * FS, n_loc - 1) * a.G) * fstride;
 #pragma unroll
       for (int i = 0; i < 8 / R0; ++i)
 #pragma unroll
@@ -184,7 +189,7 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
     row_chain<L, SQ, 0>(v, ts, tw, seq);
     __syncthreads();
     if (owner) {
-      const int nf = min(FB, a.n_frames - f0);
+      const int nf = min(FB, n_loc - f0);
 #pragma unroll
       for (int k = 0; k < SPT; ++k) {
         const int id = tid + k * NCH;
@@ -212,12 +217,12 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
   };
   float2 va[SQ][8], vb[SQ][8];
   fetch(va, 0);
-  for (int f0 = 0; f0 < a.n_frames; f0 += 2 * FB) {
-    const bool second = f0 + FB < a.n_frames;
+  for (int f0 = 0; f0 < n_loc; f0 += 2 * FB) {
+    const bool second = f0 + FB < n_loc;
     if (second) fetch(vb, f0 + FB);
     batch(va, f0);
     if (!second) break;
-    if (f0 + 2 * FB < a.n_frames) fetch(va, f0 + 2 * FB);
+    if (f0 + 2 * FB < n_loc) fetch(va, f0 + 2 * FB);
     batch(vb, f0 + FB);
   }
   if (owner) {
@@ -233,7 +238,7 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
 
 template <int L, int UB, int FB, int SQ>
 __global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
-  rowpass_tile<L, UB, FB, SQ>(a, (int)blockIdx.x, (int)blockIdx.y);
+  rowpass_tile<L, UB, FB, SQ>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z);
 }
 
 template <int L, int UB, int FB, int SQ>
@@ -246,7 +251,7 @@ __global__ void __launch_bounds__(UB * FB * L / (4 * SQ))
     const int local = tile - (t ? tile_end[t - 1] : 0);
     const RowArgs a = tasks[t];
     const int nbx = a.N1 / 2 / UB;
-    rowpass_tile<L, UB, FB, SQ>(a, local % nbx, local / nbx);
+    rowpass_tile<L, UB, FB, SQ>(a, local % nbx, (local / nbx) % a.P, local / (nbx * a.P));
     __syncthreads();
   }
 }
@@ -274,8 +279,27 @@ __device__ __forceinline__ void output_tile(const OutArgs& a, const int bx, cons
     else if (2 * r < a.N1) { u = r; half = 0; }
     else { u = a.N1 - r; half = 1; }
     const double* src = a.acc + ((int64_t)(p * U + u) * 4) * L + half * (L / 2) + k2;
+    // slots are added in order; their loads go out eight at a time
+    double v[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) t[q][rl][kk] = src[(int64_t)q * L];
+    for (int q = 0; q < 4; ++q) v[q] = src[(int64_t)q * L];
+    int g = 1;
+    for (; g + 8 <= a.slots; g += 8) {
+      double w[8][4];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[j][q] = src[(int64_t)(g + j) * a.slot_stride + (int64_t)q * L];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += w[j][q];
+    }
+    for (; g < a.slots; ++g)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] += src[(int64_t)g * a.slot_stride + (int64_t)q * L];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q][rl][kk] = v[q];
   }
   __syncthreads();
   double scale = a.scale;
@@ -400,8 +424,14 @@ static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, const Laun
   const int groups = (a.n_frames + a.frames_per_block - 1) / a.frames_per_block;
   const dim3 grid((unsigned)(groups * a.P * a.n_colblk)), block(L * COLS / (8 * V));
   switch (bits) {
-    case 2: PS_LAUNCH((k_colpass<L, COLS, V, 2, false>), grid, block, s, a); break;
-    case 4: PS_LAUNCH((k_colpass<L, COLS, V, 4, false>), grid, block, s, a); break;
+    case 2:
+      if (fast) PS_LAUNCH((k_colpass<L, COLS, V, 2, true>), grid, block, s, a);
+      else PS_LAUNCH((k_colpass<L, COLS, V, 2, false>), grid, block, s, a);
+      break;
+    case 4:
+      if (fast) PS_LAUNCH((k_colpass<L, COLS, V, 4, true>), grid, block, s, a);
+      else PS_LAUNCH((k_colpass<L, COLS, V, 4, false>), grid, block, s, a);
+      break;
     case 8:
       if (fast) PS_LAUNCH((k_colpass<L, COLS, V, 8, true>), grid, block, s, a);
       else PS_LAUNCH((k_colpass<L, COLS, V, 8, false>), grid, block, s, a);
@@ -418,8 +448,19 @@ static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, const Laun
 
 int colpass_cols(int N1) { return N1 >= 2048 ? 4 : (N1 >= 1024 ? 8 : PS_COLPASS_COLS); }
 
-hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, const Launch& s) {
+// compiled (N1, columns per workgroup) pairs: the default of each N1, and 8 columns for N1 = 256 and 512
+bool colpass_has(int N1, int cols) {
+  if (cols == colpass_cols(N1)) return N1 >= 16 && N1 <= 2048;
+  return (N1 == 256 || N1 == 512) && cols == 8;
+}
+
+hipError_t launch_colpass(int N1, int cols, int bits, bool fast, const ColArgs& a, const Launch& s) {
   constexpr int V = PS_COLPASS_V;
+  if (cols != colpass_cols(N1)) {
+    if (N1 == 256 && cols == 8) return colpass_bits<256, 8, V>(bits, fast, a, s);
+    if (N1 == 512 && cols == 8) return colpass_bits<512, 8, V>(bits, fast, a, s);
+    return hipErrorInvalidValue;
+  }
   switch (N1) {
     case 16: return colpass_bits<16, 16, 2>(bits, fast, a, s);
     case 32: return colpass_bits<32, 16, 2>(bits, fast, a, s);
@@ -435,13 +476,25 @@ hipError_t launch_colpass(int N1, int bits, bool fast, const ColArgs& a, const L
 
 template <int L, int UB, int FB, int SQ>
 static hipError_t rowpass_launch(const RowArgs& a, const Launch& s) {
-  const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P), block(UB * FB * L / (4 * SQ));
+  const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P, (unsigned)a.G), block(UB * FB * L / (4 * SQ));
   PS_LAUNCH((k_rowpass<L, UB, FB, SQ>), grid, block, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_rowpass(int N2, const RowArgs& a, const Launch& s) {
+// frames per row-pass workgroup batch: the default of each N2, and 4 for N2 = 256 and 512
+int rowpass_frames(int N2) { return N2 >= 2048 ? 2 : (N2 >= 1024 ? 4 : 8); }
+bool rowpass_has(int N2, int fb) {
+  if (fb == rowpass_frames(N2)) return N2 >= 16 && N2 <= 2048;
+  return (N2 == 256 || N2 == 512) && fb == 4;
+}
+
+hipError_t launch_rowpass(int N2, int fb, const RowArgs& a, const Launch& s) {
   constexpr int SQ = PS_ROWPASS_SQ;
+  if (fb != rowpass_frames(N2)) {
+    if (N2 == 256 && fb == 4) return rowpass_launch<256, 1, 4, SQ>(a, s);
+    if (N2 == 512 && fb == 4) return rowpass_launch<512, 1, 4, SQ>(a, s);
+    return hipErrorInvalidValue;
+  }
   switch (N2) {
     case 16: return rowpass_launch<16, 8, 8, 2>(a, s);
     case 32: return rowpass_launch<32, 8, 8, 2>(a, s);
@@ -490,8 +543,14 @@ static hipError_t colpass_batch_bits(int bits, bool fast, const BatchArgs& b, co
   constexpr int block = L * COLS / (8 * V);
   const ColArgs* t = static_cast<const ColArgs*>(b.tasks);
   switch (bits) {
-    case 2: PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 2, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks); break;
-    case 4: PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 4, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks); break;
+    case 2:
+      if (fast) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 2, true>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+      else PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 2, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+      break;
+    case 4:
+      if (fast) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 4, true>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+      else PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 4, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+      break;
     case 8:
       if (fast) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 8, true>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
       else PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 8, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
@@ -502,8 +561,13 @@ static hipError_t colpass_batch_bits(int bits, bool fast, const BatchArgs& b, co
   return hipGetLastError();
 }
 
-hipError_t launch_colpass_batch(int N1, int bits, bool fast, const BatchArgs& b, const Launch& s) {
+hipError_t launch_colpass_batch(int N1, int cols, int bits, bool fast, const BatchArgs& b, const Launch& s) {
   constexpr int V = PS_COLPASS_V;
+  if (cols != colpass_cols(N1)) {
+    if (N1 == 256 && cols == 8) return colpass_batch_bits<256, 8, V>(bits, fast, b, s);
+    if (N1 == 512 && cols == 8) return colpass_batch_bits<512, 8, V>(bits, fast, b, s);
+    return hipErrorInvalidValue;
+  }
   switch (N1) {
     case 16: return colpass_batch_bits<16, 16, 2>(bits, fast, b, s);
     case 32: return colpass_batch_bits<32, 16, 2>(bits, fast, b, s);
@@ -525,8 +589,13 @@ static hipError_t rowpass_batch_launch(const BatchArgs& b, const Launch& s) {
   return hipGetLastError();
 }
 
-hipError_t launch_rowpass_batch(int N2, const BatchArgs& b, const Launch& s) {
+hipError_t launch_rowpass_batch(int N2, int fb, const BatchArgs& b, const Launch& s) {
   constexpr int SQ = PS_ROWPASS_SQ;
+  if (fb != rowpass_frames(N2)) {
+    if (N2 == 256 && fb == 4) return rowpass_batch_launch<256, 1, 4, SQ>(b, s);
+    if (N2 == 512 && fb == 4) return rowpass_batch_launch<512, 1, 4, SQ>(b, s);
+    return hipErrorInvalidValue;
+  }
   switch (N2) {
     case 16: return rowpass_batch_launch<16, 8, 8, 2>(b, s);
     case 32: return rowpass_batch_launch<32, 8, 8, 2>(b, s);

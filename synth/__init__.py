@@ -14,6 +14,7 @@ from .gen import (  # noqa: F401
     make_paper,
     make_precision,
     make_batching,
+    batching_params,
     make_differentiation,
     make_tone_f32,
     make_identical_streams,

@@ -217,14 +217,21 @@ def make_correlated_noise(bits: int, rho: float, fft_len: int, n_frames: int, cf
     return _instance(pack_codes(codes, bits), bits, 2, fft_len, n_frames, window=window)
 
 
-def make_batching(n_inst: int = 64, e_range=(12, 20), f_range=(8, 256), max_frames: int | None = None,
-                  seed_extra: int = 0):
-    """Batching-form set: uneven instances, N = 2^e (e uniform), frames uniform, 2/8-bit mix, rho ~ U(0, .5)."""
+def batching_params(n_inst: int = 64, e_range=(12, 20), f_range=(8, 256), seed_extra: int = 0):
+    """Shapes of the batching-form set: log2 N uniform on e_range, frames uniform on f_range, 2- or 8-bit with
+    probability 1/2, correlation rho ~ U(0, 0.5)."""
     rng = rng_for(4, seed_extra)
     e = rng.integers(e_range[0], e_range[1] + 1, size=n_inst)
     F = rng.integers(f_range[0], f_range[1] + 1, size=n_inst)
     bits = np.where(rng.random(n_inst) < 0.5, 2, 8)
     rho = rng.uniform(0.0, 0.5, size=n_inst)
+    return e, F, bits, rho
+
+
+def make_batching(n_inst: int = 64, e_range=(12, 20), f_range=(8, 256), max_frames: int | None = None,
+                  seed_extra: int = 0):
+    """Batching-form set: uneven instances, N = 2^e (e uniform), frames uniform, 2/8-bit mix, rho ~ U(0, .5)."""
+    e, F, bits, rho = batching_params(n_inst, e_range, f_range, seed_extra)
     out = []
     for i in range(n_inst):
         Fi = int(F[i]) if max_frames is None else int(min(F[i], max_frames))

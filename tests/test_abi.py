@@ -117,3 +117,38 @@ def test_unpack_argument_errors():
     assert pk.STATUS[L.ps_unpack(C.c_void_p(16), 5, 2, 10, C.c_void_p(16), None)] == "PS_ERR_ARG"
     assert pk.STATUS[L.ps_unpack(C.c_void_p(16), 8, 9, 10, C.c_void_p(16), None)] == "PS_ERR_ARG"
     assert L.ps_unpack(C.c_void_p(16), 8, 2, 0, C.c_void_p(16), None) == 0  # empty: nothing enqueued
+
+
+def test_schedule_candidates_and_scheduled_plans():
+    inst = pk.Instance(fft_len=1 << 18, bits=8)
+    cands = pk.schedule_candidates(inst)
+    splits = {c.log2_n1 for c in cands}
+    assert splits == {8, 9, 10}
+    assert pk.Schedule(9, 16, 8, 1, 1) in cands and pk.Schedule(9, 8, 4, 2, 2) in cands
+    for c in cands:
+        arr = (pk._Instance * 1)(inst.to_c())
+        sarr = (pk._Schedule * 1)(c.to_c())
+        h = C.c_void_p()
+        n = C.c_size_t()
+        assert pk.lib().ps_plan_scheduled(arr, sarr, 1, C.byref(h), C.byref(n)) == 0
+        pk.lib().ps_destroy(h)
+    # 16-bit passes: default schedule only
+    assert pk.schedule_candidates(pk.Instance(fft_len=1 << 18, precision="fp16")) == [pk.Schedule(9, 0, 0, 0, 1)]
+    # accumulator slots around the default (which targets about 256 row-pass workgroups)
+    small = {c.rowpass_slots for c in pk.schedule_candidates(pk.Instance(fft_len=1 << 12)) if c.log2_n1 == 6}
+    assert small == {16, 32, 64}
+    # tiny transform: only the split that keeps both passes >= 16 points
+    assert {c.log2_n1 for c in pk.schedule_candidates(pk.Instance(fft_len=256))} == {4}
+
+
+@pytest.mark.parametrize("sched", [pk.Schedule(3, 0, 0, 0), pk.Schedule(9, 4, 0, 0), pk.Schedule(9, 0, 2, 0),
+                                   pk.Schedule(13, 0, 0, 0), pk.Schedule(9, 0, 0, 9), pk.Schedule(9, 0, 0, 0, 3),
+                                   pk.Schedule(9, 0, 0, 0, 128)])
+def test_scheduled_plan_rejects_unbuilt_schedules(sched):
+    arr = (pk._Instance * 1)(pk.Instance(fft_len=1 << 18, bits=8).to_c())
+    sarr = (pk._Schedule * 1)(sched.to_c())
+    h = C.c_void_p()
+    n = C.c_size_t()
+    st = pk.lib().ps_plan_scheduled(arr, sarr, 1, C.byref(h), C.byref(n))
+    assert pk.STATUS[st] == "PS_ERR_UNSUPPORTED", pk.lib().ps_last_error()
+    assert not h.value
