@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-precision", action="store_true", help="skip the 16-bit precision-form section")
     ap.add_argument("--no-batching", action="store_true", help="skip the 64-instance batching section")
     ap.add_argument("--ring", type=int, default=24, help="distinct input buffers cycled through by the steps")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the headline workload (for profiler runs): no other sections, no CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time (whole integrations)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
     return ap.parse_args()
@@ -76,7 +78,9 @@ def kernel_bytes(kind: str, inst: dict, frames: int) -> float:
     return float("nan")
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1412_1256_amd", "csrc", "polaris_kernels.hip")
+# the plain path's device code: the counter record is valid only for these exact sources
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1412_1256_amd", "csrc", f) for f in
+                  ("polaris_kernels.hip", "polaris_device.h", "polaris_internal.h")]
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_paper_2e18.txt")
 KIND_OF = {"k_colpass": "colpass", "k_rowpass": "rowpass", "k_output": "stokes"}
 
@@ -86,7 +90,10 @@ def counter_traffic() -> dict:
     import hashlib
     if not os.path.exists(TRAFFIC_RECORD):
         return {}
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    sha = h.hexdigest()
     out, rec_sha = {}, None
     for line in open(TRAFFIC_RECORD):
         f = line.split()
@@ -431,6 +438,9 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    if args.main_only:
+        print(json.dumps(out), flush=True)
+        return
     out["fwd_bwd"] = differentiation_form(pk, torch, dev, max(5, args.steps // 2), 2)
     out["autotune"] = autotune_form(pk, torch, dev, inst, packed, args.steps)
     if not args.no_batching:

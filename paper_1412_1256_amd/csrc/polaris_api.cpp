@@ -467,8 +467,8 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
       if (f0 >= F) continue;
       const int nf = (int)std::min<int64_t>(I.chunk, F - f0);
       bool fast = false;
-      // frame groups of about 8 frames: many instances share the device
-      const ps::ColArgs ca = col_args(plan, I, static_cast<const uint8_t*>(packed_dev[i]), f0, nf, (nf + 7) / 8, &fast);
+      // the instance's own frame grouping: long transforms keep long frame groups per tile
+      const ps::ColArgs ca = col_args(plan, I, static_cast<const uint8_t*>(packed_dev[i]), f0, nf, 0, &fast);
       const std::vector<int> key = {(int)I.N1, I.cfg.bits, fast ? 1 : 0, I.cols};
       auto it = std::find_if(cg.begin(), cg.end(), [&](const auto& g) { return g.first == key; });
       if (it == cg.end()) {

@@ -27,6 +27,18 @@
 #include "polaris_internal.h"
 
 namespace ps {
+// a kernel-invariant descriptor read through the constant address space (scalar loads into SGPRs)
+template <class T>
+__device__ __forceinline__ T load_const(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "descriptors are whole words");
+  T v;
+  const __attribute__((address_space(4))) uint32_t* src = (const __attribute__((address_space(4))) uint32_t*)(p);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+  return v;
+}
+
 // one tile of the column pass: column block, pair and frame group numbered by blk
 template <int L, int COLS, int V, int BITS, bool FAST>
 __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
@@ -108,7 +120,8 @@ __global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass(ColArgs a) {
 }
 
 // Batched (persistent) column pass over the tiles of several instances of the same shape and format: each
-// workgroup walks the global tile list with a grid stride; tile_end holds the running tile totals.
+// workgroup walks the global tile list with a grid stride; tile_end holds the running tile totals.  The
+// task descriptors are read through the constant address space (scalar loads into SGPRs).
 template <int L, int COLS, int V, int BITS, bool FAST>
 __global__ void __launch_bounds__(L * COLS / (8 * V))
     k_colpass_batch(const ColArgs* __restrict__ tasks, const int32_t* __restrict__ tile_end, int n_tasks) {
@@ -117,7 +130,7 @@ __global__ void __launch_bounds__(L * COLS / (8 * V))
   for (int tile = (int)blockIdx.x; tile < total; tile += (int)gridDim.x) {
     while (tile >= tile_end[t]) ++t;
     const int begin = t ? tile_end[t - 1] : 0;
-    const ColArgs a = tasks[t];
+    const ColArgs a = load_const(tasks + t);
     colpass_tile<L, COLS, V, BITS, FAST>(a, tile - begin);
     __syncthreads();  // the next tile reuses the LDS tile
   }
@@ -249,7 +262,7 @@ __global__ void __launch_bounds__(UB * FB * L / (4 * SQ))
   for (int tile = (int)blockIdx.x; tile < total; tile += (int)gridDim.x) {
     while (tile >= tile_end[t]) ++t;
     const int local = tile - (t ? tile_end[t - 1] : 0);
-    const RowArgs a = tasks[t];
+    const RowArgs a = load_const(tasks + t);
     const int nbx = a.N1 / 2 / UB;
     rowpass_tile<L, UB, FB, SQ>(a, local % nbx, (local / nbx) % a.P, local / (nbx * a.P));
     __syncthreads();
@@ -377,7 +390,7 @@ __global__ void __launch_bounds__(kOutThreads)
   for (int tile = (int)blockIdx.x; tile < total; tile += (int)gridDim.x) {
     while (tile >= tile_end[t]) ++t;
     const int local = tile - (t ? tile_end[t - 1] : 0);
-    const OutArgs a = tasks[t];
+    const OutArgs a = load_const(tasks + t);
     const int nx = output_tiles_x(a.N1), ny = output_tiles_y(a.N2);
     output_tile<STOKES>(a, local % nx, (local / nx) % ny, local / (nx * ny));
     __syncthreads();
