@@ -2,10 +2,13 @@
 """Benchmark of the spectrometer hot path on one MI355X.
 
 One step = one whole integration of the paper-shaped workload: reset, accumulate 61 frames of two int8
-streams (16 Msps, 2^18-point frames: 0.999424 s of data), then calibrated Stokes.  Input is resident in
-HBM before timing starts.  Prints one JSON line with the throughput (input Gsamples/s), the real-time
-factor, the per-kernel roofline of the dominant kernel (timed live with hipEvents on the plan's stream),
-and the FP64 CPU oracle timed on the host on a bounded sample of the same workload.
+streams (16 Msps, 2^18-point frames: 0.999424 s of data), then calibrated Stokes.  Inputs are resident in
+HBM before timing starts; each step integrates a different second of data from a ring of copies (larger
+than the last-level cache) into its own output, and the steps run as a replayed hipGraph of the streaming
+loop (--no-graph: eager launches).  Prints one JSON line with the throughput (input Gsamples/s), the
+real-time factor, the per-kernel roofline of the dominant kernel (timed live with hipEvents on the plan's
+stream), the other forms' sections, and the FP64 CPU oracle timed on the host on a bounded sample of the
+same workload.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
   python bench.py --copy-probe BYTES   # plain device copy, for calibrating HBM byte counters
@@ -32,12 +35,13 @@ SAMPLE_RATE = 16e6             # per stream
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=48)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the 16-bit precision-form section")
     ap.add_argument("--no-batching", action="store_true", help="skip the 64-instance batching section")
     ap.add_argument("--ring", type=int, default=24, help="distinct input buffers cycled through by the steps")
+    ap.add_argument("--no-graph", action="store_true", help="time the headline with eager launches only")
     ap.add_argument("--main-only", action="store_true",
                     help="only the headline workload (for profiler runs): no other sections, no CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time (whole integrations)")
@@ -373,36 +377,62 @@ def main():
     samples = F * N * S
     packed = torch.from_numpy(inst["packed"]).to(dev)
     # streaming: each step integrates a different, HBM-resident second of data (a ring of copies larger
-    # than the 256 MB last-level cache), so no step finds its input in cache
-    ring = [packed.clone() for _ in range(max(1, args.ring))]
-    plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev)
-    iquv = torch.empty((1, 4, N // 2), dtype=torch.float32, device=dev)
-    k = {"i": 0}
+    # than the 256 MB last-level cache) into its own output, so no step finds its input in cache
+    side = torch.cuda.Stream(dev)
+    with torch.cuda.stream(side):
+        ring = [packed.clone() for _ in range(max(1, args.ring))]
+        outs = [torch.empty((1, 4, N // 2), dtype=torch.float32, device=dev) for _ in ring]
+        plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev, stream=side)
+    side.synchronize()
+    pos = {"i": 0}
 
     def step():
-        buf = ring[k["i"] % len(ring)]
-        k["i"] += 1
+        i = pos["i"] % len(ring)
+        pos["i"] += 1
         plan.reset()
-        plan.accumulate(buf)
-        plan.stokes(psi=0.25, out=iquv)
+        plan.accumulate(ring[i])
+        plan.stokes(psi=0.25, out=outs[i])
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize(dev)
-    dt = (time.perf_counter() - t0) / args.steps
+    def ring_pass():
+        for _ in range(len(ring)):
+            step()
 
-    # per-kernel durations, hipEvents around each launch on the plan's stream
+    with torch.cuda.stream(side):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize(dev)
+        dt_eager = (time.perf_counter() - t0) / args.steps
+    dt = dt_eager
+    if not args.no_graph:
+        # the streaming loop as a replayed hipGraph: one capture covers one integration per ring buffer;
+        # exactly K steps are timed (whole replays, then the remainder eagerly)
+        pos["i"] = 0
+        plan.graph_capture(ring_pass)
+        with torch.cuda.stream(side):
+            plan.graph_replay()
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            for _ in range(args.steps // len(ring)):
+                plan.graph_replay()
+            pos["i"] = 0
+            for _ in range(args.steps % len(ring)):
+                step()
+            torch.cuda.synchronize(dev)
+            dt = (time.perf_counter() - t0) / args.steps
+
+    # per-kernel durations, hipEvents around each launch on the plan's stream (eager steps)
     plan.profile_enable(True)
     torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize(dev)
-    dt_prof = (time.perf_counter() - t0) / args.steps
+    with torch.cuda.stream(side):
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize(dev)
+        dt_prof = (time.perf_counter() - t0) / args.steps
     prof = plan.profile_read()
     plan.profile_enable(False)
     kernels = {}
@@ -427,13 +457,15 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "paper-shaped integration: 2 int8 streams at 16 Msps, 2^18-pt rect frames, "
                                "61 frames (0.999424 s), FP32 passes + FP64 accumulation, Stokes; each step a "
-                               f"different HBM-resident second of data (ring of {len(ring)})",
+                               f"different HBM-resident second of data (ring of {len(ring)}), "
+                               + ("eager launches" if args.no_graph else "replayed hipGraph"),
                    "n_streams": S, "bits": 8, "fft_len": N, "frames": F, "samples_per_step": samples},
         "x_realtime": (F * N / SAMPLE_RATE) / dt,
         "fft_tflops_nominal_5NlogN": nominal_flop / dt / 1e12,
         "path_alg_bytes_per_step": path_bytes,
         "path_GBps": path_bytes / dt / 1e9,
         "path_frac_hbm": path_bytes / dt / 1e9 / HBM_PEAK_GBS,
+        "ms_per_step_eager": dt_eager * 1e3,
         "ms_per_step_with_kernel_events": dt_prof * 1e3,
         "kernels": kernels,
         "roofline": roofline,

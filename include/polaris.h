@@ -166,9 +166,10 @@ ps_status ps_reset(ps_plan_t plan);
  *   n_samples[i]    samples per stream, a multiple of fft_len (PS_ERR_SIZE otherwise).
  * Frames are added in order; with FP32 passes, splitting one input over several calls gives bitwise the
  * same sums (with 16-bit passes the same up to the rounding of the per-launch sums).
- * In a plan of several instances, the FP32 instances of a call run together: per chunk round, one
- * persistent column-pass launch per (segment shape, sample format) and one row-pass launch per row length
- * walk the tiles of all of them (up to 8 chunk rounds per call; beyond that instance by instance). */
+ * In a plan of several instances, the FP32 instances of a call run together: per chunk round, instances of
+ * one shape class (split, sample format, schedule) share a persistent column-pass launch and a row-pass
+ * launch that walk the tiles of all of them, in sub-batches of at most 128 MB of inter-pass data, each row
+ * pass right after its column pass (up to 8 chunk rounds per call; beyond that instance by instance). */
 ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples);
 
 /* Raw accumulated products of instance inst into out_dev [n_pairs][4][C] doubles:

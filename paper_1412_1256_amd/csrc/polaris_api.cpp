@@ -275,6 +275,7 @@ T* ws_ptr(ps_plan_t plan, size_t off) {
 
 constexpr size_t kMaxTimed = 16384;
 constexpr size_t kMaxRounds = 8;  // chunks per call handled by the grouped launches
+constexpr int64_t kBatchT = int64_t(128) << 20;  // inter-pass bytes per grouped sub-batch (cache-sized)
 
 // Launch f(launch) on the plan's stream; while profiling, the dispatch stamps a pair of events with the
 // kernel's own start and end.
@@ -456,10 +457,16 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
   };
   std::vector<L1> launches;
   for (int64_t r = 0; r < rounds; ++r) {
-    std::vector<L1> col_l, row_l;
-    // column-pass groups
-    std::vector<std::pair<std::vector<int>, std::vector<ps::ColArgs>>> cg;  // key (N1, bits, fast, columns)
-    std::vector<std::pair<std::vector<int>, std::vector<ps::RowArgs>>> rg;   // key (N2, frames per batch)
+    // Instances of one shape class (N1, N2, format, schedule) share a column-pass and a row-pass launch.
+    // A class is cut into sub-batches whose inter-pass buffers total at most kBatchT bytes, and each
+    // sub-batch's row pass follows its column pass directly, so the intermediate written by one is still in
+    // the last-level cache when the other reads it.
+    struct Member {
+      ps::ColArgs ca;
+      ps::RowArgs ra;
+      int64_t t_bytes;
+    };
+    std::vector<std::pair<std::vector<int>, std::vector<Member>>> classes;
     for (size_t i = 0; i < plan->inst.size(); ++i) {
       const Inst& I = plan->inst[i];
       if (I.mx()) continue;
@@ -469,43 +476,40 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
       bool fast = false;
       // the instance's own frame grouping: long transforms keep long frame groups per tile
       const ps::ColArgs ca = col_args(plan, I, static_cast<const uint8_t*>(packed_dev[i]), f0, nf, 0, &fast);
-      const std::vector<int> key = {(int)I.N1, I.cfg.bits, fast ? 1 : 0, I.cols};
-      auto it = std::find_if(cg.begin(), cg.end(), [&](const auto& g) { return g.first == key; });
-      if (it == cg.end()) {
-        cg.push_back({key, {}});
-        it = cg.end() - 1;
-      }
-      it->second.push_back(ca);
       const ps::RowArgs ra = row_args(plan, I, nf, I.n_frames + f0);
-      const std::vector<int> rkey = {(int)I.N2, I.fb};
-      auto jt = std::find_if(rg.begin(), rg.end(), [&](const auto& g) { return g.first == rkey; });
-      if (jt == rg.end()) {
-        rg.push_back({rkey, {}});
-        jt = rg.end() - 1;
+      const std::vector<int> key = {(int)I.N1, (int)I.N2, I.cfg.bits, fast ? 1 : 0, I.cols, I.fb};
+      auto it = std::find_if(classes.begin(), classes.end(), [&](const auto& c) { return c.first == key; });
+      if (it == classes.end()) {
+        classes.push_back({key, {}});
+        it = classes.end() - 1;
       }
-      jt->second.push_back(ra);
+      it->second.push_back(Member{ca, ra, (int64_t)nf * I.cfg.n_pairs * I.N * 8});
     }
-    for (const auto& g : cg) {
-      L1 l{0, g.first[0], g.first[1], g.first[2] != 0, g.first[3], cols.size(), g.second.size(), 0};
-      int total = 0;
-      for (const ps::ColArgs& ca : g.second) {
-        cols.push_back(ca);
-        total += col_tiles(ca);
-        cend.push_back(total);
+    for (const auto& c : classes) {
+      const std::vector<int>& key = c.first;
+      size_t m = 0;
+      while (m < c.second.size()) {
+        size_t e = m;
+        int64_t bytes = 0;
+        while (e < c.second.size() && (e == m || bytes + c.second[e].t_bytes <= kBatchT)) bytes += c.second[e++].t_bytes;
+        L1 lc{0, key[0], key[2], key[3] != 0, key[4], cols.size(), e - m, 0};
+        L1 lr{1, key[1], 0, false, key[5], rows.size(), e - m, 0};
+        int ct = 0, rt = 0;
+        for (size_t q = m; q < e; ++q) {
+          cols.push_back(c.second[q].ca);
+          ct += col_tiles(c.second[q].ca);
+          cend.push_back(ct);
+          const ps::RowArgs& ra = c.second[q].ra;
+          rows.push_back(ra);
+          rt += ra.N1 / 2 / ps::rowpass_units_per_tile(key[1]) * ra.P * ra.G;
+          rend.push_back(rt);
+        }
+        lc.total = ct;
+        lr.total = rt;
+        launches.push_back(lc);
+        launches.push_back(lr);
+        m = e;
       }
-      l.total = total;
-      launches.push_back(l);
-    }
-    for (const auto& g : rg) {
-      L1 l{1, g.first[0], 0, false, g.first[1], rows.size(), g.second.size(), 0};
-      int total = 0;
-      for (const ps::RowArgs& ra : g.second) {
-        rows.push_back(ra);
-        total += ra.N1 / 2 / ps::rowpass_units_per_tile(g.first[0]) * ra.P * ra.G;
-        rend.push_back(total);
-      }
-      l.total = total;
-      launches.push_back(l);
     }
   }
   std::vector<unsigned char> img;

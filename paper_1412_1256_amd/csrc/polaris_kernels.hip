@@ -26,6 +26,14 @@
 #include "polaris_device.h"
 #include "polaris_internal.h"
 
+#ifndef PS_COLPASS_PREFETCH
+#define PS_COLPASS_PREFETCH 1
+#endif
+// LDS budget of a column-pass workgroup's tiles: two alternating tiles when they fit
+#ifndef PS_COLPASS_LDS_MAX
+#define PS_COLPASS_LDS_MAX (128 * 1024)
+#endif
+
 namespace ps {
 // a kernel-invariant descriptor read through the constant address space (scalar loads into SGPRs)
 template <class T>
@@ -47,7 +55,7 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
   constexpr int R0 = SC::R0, RL = SC::radix(SC::NPASS - 1), NSL = SC::ns(SC::NPASS - 1);
   static_assert(RL == 8 && NSL == L / 8, "last pass must be radix 8");
   // two tiles when they fit beside the workgroup's other needs (one workgroup per CU)
-  constexpr int NB = (2 * L * COLS * 8 <= 128 * 1024) ? 2 : 1;
+  constexpr int NB = (2 * L * COLS * 8 <= PS_COLPASS_LDS_MAX) ? 2 : 1;
   __shared__ __align__(16) float2 tile[NB * L * COLS];
 
   const int cb = blk % a.n_colblk;
@@ -72,11 +80,12 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
       const int m = (ts + r * (L / 8)) * (n2b + c);
       fst[c][r] = cmul(a.tw_hi[m >> a.lo_bits], a.tw_lo[m & mask]);
     }
-  ColLoader<BITS, FAST, V> cur;
-  if (f_begin < f_end) cur.template fetch<L, R0>(a, (int64_t)f_begin * a.N, ts, n2b);
-  for (int f = f_begin; f < f_end; ++f) {
+  // input words are fetched PF frames ahead of their use (PF loaders in rotation)
+  constexpr int PF = PS_COLPASS_PREFETCH;
+  static_assert(PF == 1 || PF == 2, "prefetch distance 1 or 2 frames");
+  auto frame = [&](ColLoader<BITS, FAST, V>& ld, const int f) {
     float2 v[V][8];
-    cur.template convert<L, R0>(v, a, ts, n2b, sx, sy);
+    ld.template convert<L, R0>(v, a, ts, n2b, sx, sy);
     if (a.win) {  // the window is the same for every frame (and cached in L2); read before the prefetch
 #pragma unroll
       for (int i = 0; i < 8 / R0; ++i)
@@ -90,7 +99,7 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
           }
         }
     }
-    if (f + 1 < f_end) cur.template fetch<L, R0>(a, (int64_t)(f + 1) * a.N, ts, n2b);
+    if (f + PF < f_end) ld.template fetch<L, R0>(a, (int64_t)(f + PF) * a.N, ts, n2b);
     col_chain<L, COLS, V, NB, 0>(v, ts, cv, tw, tile);
     // with an odd number of exchanges per frame the next frame's first exchange reuses the tile the last
     // one read: wait for every reader first
@@ -111,6 +120,17 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
         *(__attribute__((address_space(1))) f32x2*)(base + voff) = q;
       }
     }
+  };
+  ColLoader<BITS, FAST, V> ld0, ld1;
+  if (f_begin < f_end) ld0.template fetch<L, R0>(a, (int64_t)f_begin * a.N, ts, n2b);
+  if constexpr (PF == 2) {
+    if (f_begin + 1 < f_end) ld1.template fetch<L, R0>(a, (int64_t)(f_begin + 1) * a.N, ts, n2b);
+    for (int f = f_begin; f < f_end; f += 2) {
+      frame(ld0, f);
+      if (f + 1 < f_end) frame(ld1, f + 1);
+    }
+  } else {
+    for (int f = f_begin; f < f_end; ++f) frame(ld0, f);
   }
 }
 
@@ -127,7 +147,11 @@ __global__ void __launch_bounds__(L * COLS / (8 * V))
     k_colpass_batch(const ColArgs* __restrict__ tasks, const int32_t* __restrict__ tile_end, int n_tasks) {
   const int total = tile_end[n_tasks - 1];
   int t = 0;
-  for (int tile = (int)blockIdx.x; tile < total; tile += (int)gridDim.x) {
+  for (int slot = (int)blockIdx.x; slot < total; slot += (int)gridDim.x) {
+    // the grid is a multiple of 8 (or all tiles), so every slot of this workgroup runs on its XCD: renumber
+    // as the single-instance launch does, keeping neighbouring column blocks on one XCD (increasing per
+    // workgroup, so the task scan stays monotonic)
+    const int tile = xcd_remap(slot, total);
     while (tile >= tile_end[t]) ++t;
     const int begin = t ? tile_end[t - 1] : 0;
     const ColArgs a = load_const(tasks + t);
@@ -539,9 +563,12 @@ static int resident_per_cu(K kernel, int block) {
   return per_cu;
 }
 
+// all tiles, or the resident workgroups rounded down to a multiple of the 8 XCDs (dispatch is round-robin
+// over the XCDs, so a workgroup's grid-stride slots then all run on one XCD)
 template <class K>
 static unsigned persistent_grid(K kernel, int block, int total, int n_cu) {
-  const long resident = (long)resident_per_cu(kernel, block) * n_cu;
+  long resident = (long)resident_per_cu(kernel, block) * n_cu;
+  if (resident >= 16) resident -= resident % 8;
   return (unsigned)(total < resident ? total : resident);
 }
 
