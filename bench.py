@@ -355,6 +355,37 @@ def autotune_form(pk, torch, dev, inst, packed, steps):
     return res
 
 
+def power_form(pk, torch, dev, inst, packed, steps):
+    """Level histograms counted inside the column pass (total power, the paper's bit-distribution method):
+    the paper workload's whole integration and column pass with counting off and on, and the estimates."""
+    res = {}
+    for on in (False, True):
+        plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev)
+        plan.set_histograms(on)
+        out = torch.empty((1, 4, inst["fft_len"] // 2), dtype=torch.float32, device=dev)
+
+        def step():
+            plan.reset()
+            plan.accumulate(packed)
+            plan.stokes(out=out)
+
+        t = time_steps(torch, dev, step, steps, 3)
+        plan.profile_enable(True)
+        for _ in range(steps):
+            step()
+        prof = plan.profile_read()
+        plan.profile_enable(False)
+        key = "on" if on else "off"
+        res[f"{key}_us"] = t * 1e6
+        res[f"colpass_{key}_us"] = prof["colpass"][0] / prof["colpass"][1] * 1e3
+        if on:
+            counts, power, nf = plan.histograms()
+            res["mean_square_level_XY"] = [float(v) for v in power[0, :, 0].cpu()]
+            res["frames_counted"] = nf
+    res["colpass_overhead"] = res["colpass_on_us"] / res["colpass_off_us"] - 1.0
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -475,6 +506,7 @@ def main():
         return
     out["fwd_bwd"] = differentiation_form(pk, torch, dev, max(5, args.steps // 2), 2)
     out["autotune"] = autotune_form(pk, torch, dev, inst, packed, args.steps)
+    out["total_power"] = power_form(pk, torch, dev, inst, packed, max(5, args.steps // 4))
     if not args.no_batching:
         out["batching_form"] = batching_form(pk, torch, dev, max(3, args.steps // 10))
     if not args.no_precision:

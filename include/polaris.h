@@ -187,6 +187,20 @@ ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv
  * [n_pairs][4][C] floats.  PS_ERR_STATE if a selected instance has no accumulated frame. */
 ps_status ps_stokes_all(ps_plan_t plan, const ps_cal* cal, float* const* iquv_dev);
 
+/* Level histograms and total power (Sec. 2: total power from the samplers' bit distributions).
+ * ps_set_histograms switches counting on or off for instance inst (2-, 4- or 8-bit codes, FP32 passes;
+ * PS_ERR_STATE inside an integration).  While on, the column pass counts every sample of each pair's two
+ * streams; the counts start at zero with the first ps_accumulate after ps_reset.
+ * ps_histograms returns, for the current integration (either pointer may be NULL):
+ *   counts_dev  [n_pairs][2 (X, Y)][2^bits] uint64, bins in ascending level order (code c of a 2/4-bit
+ *               sample, level + 128 of an int8 one);
+ *   power_dev   [n_pairs][2][2] doubles: the mean square level (total power in level units) and, for
+ *               2-bit samplers, sigma / threshold = 1 / (sqrt 2 erfinv(P)) from the fraction P of samples
+ *               in the two inner levels (NaN for other formats);
+ *   n_frames    frames counted.  PS_ERR_STATE when nothing has been counted since ps_reset. */
+ps_status ps_set_histograms(ps_plan_t plan, int32_t inst, int32_t enable);
+ps_status ps_histograms(ps_plan_t plan, int32_t inst, uint64_t* counts_dev, double* power_dev, int64_t* n_frames);
+
 /* hipGraph capture of a sequence of calls on the plan's stream (the batching form's streaming loop):
  *   ps_graph_begin   starts capturing the bound stream (not the null stream; profiling must be off);
  *   ps_graph_end     ends the capture; keep != 0 instantiates the graph (replacing an earlier one),

@@ -172,3 +172,40 @@ def run_instance(inst: dict, taps=None, nthreads: int = 0):
     acc, nf = accumulate(inst["packed"], inst["bits"], inst["n_streams"], inst["n_samples"], inst["fft_len"], w,
                          inst["pairs"], nthreads=nthreads)
     return acc, nf, s2, w
+
+
+# ------------------------------------------------------------------------------------------------
+# level histograms and total power (Sec. 2: total power from the samplers' bit distributions)
+
+def level_histograms(packed, bits: int, n_streams: int, n_time: int, pairs) -> np.ndarray:
+    """Counts [P][2 (X, Y)][2^bits] of every sample of each pair's streams, bins in ascending level order.
+    Plain definition: decode every item (the pinned unpack) and count equal levels."""
+    levels = unpack(packed, bits, n_streams, n_time)
+    nbin = 1 << bits
+    lv = np.arange(nbin) - 128 if bits == 8 else 2 * np.arange(nbin) - (nbin - 1)
+    out = np.zeros((len(pairs), 2, nbin), dtype=np.int64)
+    for p, (x, y) in enumerate(pairs):
+        for j, s in enumerate((x, y)):
+            for b in range(nbin):
+                out[p, j, b] = int(np.count_nonzero(levels[s] == lv[b]))
+    return out
+
+
+def total_power(counts: np.ndarray, bits: int) -> np.ndarray:
+    """[P][2][2]: the mean square level, and for 2-bit samplers sigma / threshold from the fraction P of
+    samples in the inner levels, P(|x| < theta) = erf(theta / (sigma sqrt 2)) (NaN for other formats)."""
+    from scipy.special import erfinv
+    nbin = 1 << bits
+    lv = np.arange(nbin) - 128.0 if bits == 8 else 2.0 * np.arange(nbin) - (nbin - 1)
+    P = counts.shape[0]
+    out = np.full((P, 2, 2), np.nan)
+    for p in range(P):
+        for j in range(2):
+            c = counts[p, j].astype(np.float64)
+            n = c.sum()
+            out[p, j, 0] = float((lv * lv * c).sum() / n) if n > 0 else 0.0
+            if bits == 2 and n > 0:
+                pin = (c[1] + c[2]) / n
+                if 0.0 < pin < 1.0:
+                    out[p, j, 1] = 1.0 / (np.sqrt(2.0) * erfinv(pin))
+    return out

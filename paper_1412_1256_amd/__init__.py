@@ -110,6 +110,8 @@ def lib():
             "ps_stokes_all": [vp, C.POINTER(_Cal), C.POINTER(vp)],
             "ps_plan_scheduled": [C.POINTER(_Instance), C.POINTER(_Schedule), i32, C.POINTER(vp), C.POINTER(sz)],
             "ps_schedule_candidates": [C.POINTER(_Instance), C.POINTER(_Schedule), i32, C.POINTER(i32)],
+            "ps_set_histograms": [vp, i32, i32],
+            "ps_histograms": [vp, i32, vp, vp, C.POINTER(i64)],
             "ps_graph_begin": [vp],
             "ps_graph_end": [vp, i32],
             "ps_graph_launch": [vp],
@@ -298,6 +300,21 @@ class Plan:
             calp = arr
         _check(lib().ps_stokes_all(self._h, calp, ptrs))
         return outs
+
+    def set_histograms(self, on: bool = True, inst: int = 0):
+        """Count the level histograms of instance inst's streams from the next integration on."""
+        _check(lib().ps_set_histograms(self._h, inst, 1 if on else 0))
+
+    def histograms(self, inst: int = 0):
+        """(counts int64 [P][2][2^bits], power float64 [P][2][2], frames counted) of the current integration:
+        power = (mean square level, sigma / threshold for 2-bit samplers or NaN)."""
+        I = self.instances[inst]
+        torch = self.torch
+        counts = torch.empty((I.n_pairs, 2, 1 << I.bits), dtype=torch.int64, device=self.device)
+        power = torch.empty((I.n_pairs, 2, 2), dtype=torch.float64, device=self.device)
+        nf = C.c_int64()
+        _check(lib().ps_histograms(self._h, inst, _ptr(counts), _ptr(power), C.byref(nf)))
+        return counts, power, nf.value
 
     # --------------------------------------------------------------------------------------------
     # hipGraph capture of a whole integration (the plan must be bound to a non-default stream)

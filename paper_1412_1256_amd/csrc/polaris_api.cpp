@@ -74,6 +74,12 @@ struct Inst {
   // column-pass workgroups per CU aimed at by the frame grouping
   int cols = 0, fb = 0, col_wgs = 1;
   int G = 1;  // accumulator slots (row-pass frame groups)
+  // level histograms (total power): counted by the column pass while on; zeroed by the first accumulate
+  // after a reset
+  bool hist_on = false, hist_zeroed = false;
+  int64_t hist_frames = 0;
+  size_t off_hist = 0;
+  int64_t hist_bins() const { return cfg.bits <= 8 ? (int64_t(1) << cfg.bits) : 0; }
   // precision form: 16-bit DFT matrices of radix 16 and 32 (hi, lo), stage twiddles of the two passes
   bool mx() const { return cfg.precision != PS_PREC_FP32; }
   size_t off_mx16 = 0, off_mx32 = 0, off_tws_col = 0, off_tws_row = 0;
@@ -112,7 +118,11 @@ struct ps_plan_s {
   // graph of a captured integration and the host state it leaves behind
   hipGraphExec_t gexec = nullptr;
   bool capturing = false;
-  std::vector<std::pair<bool, int64_t>> graph_state;
+  struct InstState {
+    bool first, hist_zeroed;
+    int64_t n_frames, hist_frames;
+  };
+  std::vector<InstState> graph_state;
   ~ps_plan_s() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (acc_desc.host) (void)hipHostFree(acc_desc.host);
@@ -380,6 +390,7 @@ ps::ColArgs col_args(ps_plan_t plan, const Inst& I, const uint8_t* base, int64_t
   ca.tw_lo = ws_ptr<float2>(plan, I.off_tw_lo);
   ca.lo_bits = I.m2;
   ca.T = ws_ptr<float2>(plan, I.off_T);
+  ca.hist = I.hist_on ? ws_ptr<unsigned long long>(plan, I.off_hist) : nullptr;
   return ca;
 }
 
@@ -440,7 +451,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
   int64_t rounds = 0;
   for (size_t i = 0; i < plan->inst.size(); ++i) {
     const Inst& I = plan->inst[i];
-    if (I.mx()) continue;
+    if (I.mx() || I.hist_on) continue;
     const int64_t F = n_samples[i] / I.N;
     rounds = std::max(rounds, (F + I.chunk - 1) / I.chunk);
   }
@@ -469,7 +480,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
     std::vector<std::pair<std::vector<int>, std::vector<Member>>> classes;
     for (size_t i = 0; i < plan->inst.size(); ++i) {
       const Inst& I = plan->inst[i];
-      if (I.mx()) continue;
+      if (I.mx() || I.hist_on) continue;
       const int64_t F = n_samples[i] / I.N, f0 = r * I.chunk;
       if (f0 >= F) continue;
       const int nf = (int)std::min<int64_t>(I.chunk, F - f0);
@@ -542,7 +553,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
   }
   for (size_t i = 0; i < plan->inst.size(); ++i) {
     Inst& I = plan->inst[i];
-    if (I.mx()) continue;
+    if (I.mx() || I.hist_on) continue;
     done[i] = 1;
     const int64_t F = n_samples[i] / I.N;
     if (F > 0) {
@@ -683,6 +694,7 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
       I.off_tws_col = off; off = align_up(off + I.tws_col.size() * 4);
       I.off_tws_row = off; off = align_up(off + I.tws_row.size() * 4);
     }
+    I.off_hist = off; off = align_up(off + (size_t)I.cfg.n_pairs * 2 * (size_t)I.hist_bins() * 8);
     I.off_T = off; off = align_up(off + (size_t)I.chunk * (size_t)I.cfg.n_pairs * (size_t)I.N * 8);
     I.off_acc = off; off = align_up(off + I.acc_bytes());
     const size_t U = (size_t)(I.N1 / 2), P = (size_t)I.cfg.n_pairs;
@@ -748,6 +760,8 @@ ps_status ps_bind(ps_plan_t plan, void* workspace_dev, size_t bytes, void* hip_s
     }
     I.first = true;
     I.n_frames = 0;
+    I.hist_zeroed = false;
+    I.hist_frames = 0;
   }
   hipError_t e = hipStreamSynchronize(plan->stream);
   if (e != hipSuccess) return hip_fail(e, "ps_bind synchronise");
@@ -783,6 +797,8 @@ ps_status ps_reset(ps_plan_t plan) {
   for (Inst& I : plan->inst) {
     I.first = true;
     I.n_frames = 0;
+    I.hist_zeroed = false;
+    I.hist_frames = 0;
   }
   return PS_OK;
 }
@@ -809,6 +825,15 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
     if (done[i]) continue;
     Inst& I = plan->inst[i];
     const int64_t F = n_samples[i] / I.N;
+    if (I.hist_on && F > 0) {
+      if (!I.hist_zeroed) {
+        hipError_t e = ps::launch_zero_u64(ws_ptr<unsigned long long>(plan, I.off_hist),
+                                           (int64_t)I.cfg.n_pairs * 2 * I.hist_bins(), plan->stream);
+        if (e != hipSuccess) return hip_fail(e, "histogram clear");
+        I.hist_zeroed = true;
+      }
+      I.hist_frames += F;
+    }
     const uint8_t* base = static_cast<const uint8_t*>(packed_dev[i]);
     for (int64_t f0 = 0; f0 < F; f0 += I.chunk) {
       const int nf = (int)((F - f0) < I.chunk ? (F - f0) : I.chunk);
@@ -933,6 +958,44 @@ ps_status ps_stokes_all(ps_plan_t plan, const ps_cal* cal, float* const* iquv_de
   return PS_OK;
 }
 
+ps_status ps_set_histograms(ps_plan_t plan, int32_t inst, int32_t enable) {
+  if (!plan) return fail(PS_ERR_ARG, "null plan");
+  ps_status st = check_inst(plan, inst);
+  if (st != PS_OK) return st;
+  Inst& I = plan->inst[(size_t)inst];
+  if (enable && (I.mx() || I.hist_bins() == 0))
+    return fail(PS_ERR_UNSUPPORTED, "instance %d: level histograms need 2-, 4- or 8-bit codes and FP32 passes", inst);
+  if ((enable != 0) != I.hist_on && I.n_frames > 0)
+    return fail(PS_ERR_STATE, "instance %d: switch histograms between integrations (after ps_reset)", inst);
+  I.hist_on = enable != 0;
+  I.hist_zeroed = false;
+  I.hist_frames = 0;
+  return PS_OK;
+}
+
+ps_status ps_histograms(ps_plan_t plan, int32_t inst, uint64_t* counts_dev, double* power_dev, int64_t* n_frames) {
+  ps_status st = check_plan(plan, true);
+  if (st != PS_OK) return st;
+  if ((st = check_inst(plan, inst)) != PS_OK) return st;
+  const Inst& I = plan->inst[(size_t)inst];
+  if (!I.hist_on || !I.hist_zeroed) return fail(PS_ERR_STATE, "instance %d has no histograms in this integration", inst);
+  const int64_t nb = (int64_t)I.cfg.n_pairs * 2 * I.hist_bins();
+  unsigned long long* h = ws_ptr<unsigned long long>(plan, I.off_hist);
+  hipError_t e = hipSuccess;
+  if (counts_dev) {
+    e = ps::launch_copy(h, counts_dev, (size_t)nb * 8, plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "histogram copy");
+  }
+  if (power_dev) {
+    e = timed(plan, PS_KERNEL_OTHER, [&](const ps::Launch& l) {
+      return ps::launch_hist_power(h, I.cfg.n_pairs * 2, I.cfg.bits, power_dev, l);
+    });
+    if (e != hipSuccess) return hip_fail(e, "histogram power launch");
+  }
+  if (n_frames) *n_frames = I.hist_frames;
+  return PS_OK;
+}
+
 ps_status ps_graph_begin(ps_plan_t plan) {
   ps_status st = check_plan(plan, true);
   if (st != PS_OK) return st;
@@ -964,7 +1027,7 @@ ps_status ps_graph_end(ps_plan_t plan, int32_t keep) {
   if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
   plan->gexec = x;
   plan->graph_state.clear();
-  for (const Inst& I : plan->inst) plan->graph_state.push_back({I.first, I.n_frames});
+  for (const Inst& I : plan->inst) plan->graph_state.push_back({I.first, I.hist_zeroed, I.n_frames, I.hist_frames});
   return PS_OK;
 }
 
@@ -976,8 +1039,12 @@ ps_status ps_graph_launch(ps_plan_t plan) {
   hipError_t e = hipGraphLaunch(plan->gexec, plan->stream);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
   for (size_t i = 0; i < plan->inst.size(); ++i) {
-    plan->inst[i].first = plan->graph_state[i].first;
-    plan->inst[i].n_frames = plan->graph_state[i].second;
+    Inst& I = plan->inst[i];
+    const ps_plan_s::InstState& g = plan->graph_state[i];
+    I.first = g.first;
+    I.n_frames = g.n_frames;
+    I.hist_zeroed = g.hist_zeroed;
+    I.hist_frames = g.hist_frames;
   }
   return PS_OK;
 }

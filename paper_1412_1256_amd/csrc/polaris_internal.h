@@ -29,6 +29,7 @@ struct ColArgs {
   const float2* tw_lo;      // W_N^m, m < 2^lo_bits
   int32_t lo_bits;
   float2* T;                // [n_frames][P][N1][N2]
+  unsigned long long* hist; // level histograms [P][2][2^bits] to add to, or nullptr
 };
 
 // Accumulator slots: absolute frame a (counted from ps_reset) is added to slot a mod G, frames of a slot in
@@ -197,5 +198,8 @@ hipError_t launch_bw_rowpass(int N2, const BwRowArgs& a, const Launch& l);
 hipError_t launch_bw_colpass(int N1, int bits, bool fast, const BwColArgs& a, const Launch& l);
 hipError_t launch_bw_taps(const BwTapArgs& a, const Launch& l);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+hipError_t launch_hist_power(const unsigned long long* counts, int n_streams, int bits, double* power,
+                             const Launch& l);
 
 }  // namespace ps

@@ -47,8 +47,59 @@ __device__ __forceinline__ T load_const(const T* p) {
   return v;
 }
 
+// Level histograms of the pair's two streams (bins in ascending level order: code c of a 2- or 4-bit
+// offset-binary sample, level + 128 of an int8 one), counted in LDS and added to the device counts a.hist
+// [P][2][2^BITS] at the end of the tile.  2-bit: four 8-bit counters packed per stream and thread, flushed
+// every frame (at most 16 samples per stream); wider codes: LDS atomics per sample.
+template <int BITS, int NT>
+struct LevelHist {
+  static constexpr int NBIN = 1 << BITS;
+  uint32_t packed[2];
+  static __device__ __forceinline__ int bin(float level) {
+    if constexpr (BITS == 8) return (int)level + 128;
+    else return ((int)level + NBIN - 1) >> 1;
+  }
+  __device__ __forceinline__ void begin(uint32_t* hs) {
+    for (int i = (int)threadIdx.x; i < 2 * NBIN; i += NT) hs[i] = 0;
+    packed[0] = packed[1] = 0;
+    __syncthreads();
+  }
+  template <int V>
+  __device__ __forceinline__ void count(uint32_t* hs, const float2 (&v)[V][8]) {
+#pragma unroll
+    for (int c = 0; c < V; ++c)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int bx = bin(v[c][e].x), by = bin(v[c][e].y);
+        if constexpr (BITS == 2) {
+          packed[0] += 1u << (8 * bx);
+          packed[1] += 1u << (8 * by);
+        } else {
+          atomicAdd(&hs[bx], 1u);
+          atomicAdd(&hs[NBIN + by], 1u);
+        }
+      }
+    if constexpr (BITS == 2) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const uint32_t n = (packed[s] >> (8 * b)) & 0xffu;
+          if (n) atomicAdd(&hs[s * 4 + b], n);
+        }
+        packed[s] = 0;
+      }
+    }
+  }
+  __device__ __forceinline__ void end(const uint32_t* hs, unsigned long long* out, int p) {
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < 2 * NBIN; i += NT)
+      if (hs[i]) atomicAdd(&out[(int64_t)p * 2 * NBIN + i], (unsigned long long)hs[i]);
+  }
+};
+
 // one tile of the column pass: column block, pair and frame group numbered by blk
-template <int L, int COLS, int V, int BITS, bool FAST>
+template <int L, int COLS, int V, int BITS, bool FAST, bool HIST = false>
 __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
   constexpr int CPR = COLS / V;  // column groups per row
   using SC = Sched<L>;
@@ -80,12 +131,18 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
       const int m = (ts + r * (L / 8)) * (n2b + c);
       fst[c][r] = cmul(a.tw_hi[m >> a.lo_bits], a.tw_lo[m & mask]);
     }
+  constexpr int NT = L * COLS / (8 * V);
+  constexpr bool H = HIST && BITS <= 8;
+  __shared__ uint32_t hs[H ? 2 << (BITS <= 8 ? BITS : 0) : 1];
+  LevelHist<BITS <= 8 ? BITS : 8, NT> hist;
+  if constexpr (H) hist.begin(hs);
   // input words are fetched PF frames ahead of their use (PF loaders in rotation)
   constexpr int PF = PS_COLPASS_PREFETCH;
   static_assert(PF == 1 || PF == 2, "prefetch distance 1 or 2 frames");
   auto frame = [&](ColLoader<BITS, FAST, V>& ld, const int f) {
     float2 v[V][8];
     ld.template convert<L, R0>(v, a, ts, n2b, sx, sy);
+    if constexpr (H) hist.count(hs, v);
     if (a.win) {  // the window is the same for every frame (and cached in L2); read before the prefetch
 #pragma unroll
       for (int i = 0; i < 8 / R0; ++i)
@@ -132,11 +189,18 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
   } else {
     for (int f = f_begin; f < f_end; ++f) frame(ld0, f);
   }
+  if constexpr (H) hist.end(hs, a.hist, p);
 }
 
 template <int L, int COLS, int V, int BITS, bool FAST>
 __global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass(ColArgs a) {
   colpass_tile<L, COLS, V, BITS, FAST>(a, xcd_remap((int)blockIdx.x, (int)gridDim.x));
+}
+
+// the column pass that also counts the level histograms of its streams
+template <int L, int COLS, int V, int BITS, bool FAST>
+__global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass_hist(ColArgs a) {
+  colpass_tile<L, COLS, V, BITS, FAST, true>(a, xcd_remap((int)blockIdx.x, (int)gridDim.x));
 }
 
 // Batched (persistent) column pass over the tiles of several instances of the same shape and format: each
@@ -422,6 +486,36 @@ __global__ void __launch_bounds__(kOutThreads)
 }
 
 // ------------------------------------------------------------------------------------------------
+// total power from level histograms: per stream, the mean square level and, for 2-bit samplers, sigma in
+// units of the quantiser threshold from the fraction of samples in the two inner levels,
+// P(|x| < theta) = erf(theta / (sigma sqrt 2))  ->  sigma / theta = 1 / (sqrt 2 erfinv(P))
+// ------------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_hist_power(const unsigned long long* __restrict__ counts, int n_streams,
+                                                   int bits, double* __restrict__ power) {
+  const int s = (int)(blockIdx.x * 64 + threadIdx.x);
+  if (s >= n_streams) return;
+  const int nbin = 1 << bits;
+  const unsigned long long* c = counts + (int64_t)s * nbin;
+  double n = 0.0, m2 = 0.0;
+  for (int b = 0; b < nbin; ++b) {
+    const double level = bits == 8 ? (double)(b - 128) : (double)(2 * b - (nbin - 1));
+    n += (double)c[b];
+    m2 += level * level * (double)c[b];
+  }
+  power[2 * s] = n > 0.0 ? m2 / n : 0.0;
+  double r = __builtin_nan("");
+  if (bits == 2 && n > 0.0) {
+    const double pin = ((double)c[1] + (double)c[2]) / n;
+    if (pin > 0.0 && pin < 1.0) r = 1.0 / (1.4142135623730950488 * erfinv(pin));
+  }
+  power[2 * s + 1] = r;
+}
+
+__global__ void __launch_bounds__(256) k_zero_u64(unsigned long long* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0ull;
+}
+
+// ------------------------------------------------------------------------------------------------
 // stand-alone data translation and a plain device copy
 // ------------------------------------------------------------------------------------------------
 
@@ -460,6 +554,24 @@ template <int L, int COLS, int V>
 static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, const Launch& s) {
   const int groups = (a.n_frames + a.frames_per_block - 1) / a.frames_per_block;
   const dim3 grid((unsigned)(groups * a.P * a.n_colblk)), block(L * COLS / (8 * V));
+  if (a.hist) {
+    switch (bits) {
+      case 2:
+        if (fast) PS_LAUNCH((k_colpass_hist<L, COLS, V, 2, true>), grid, block, s, a);
+        else PS_LAUNCH((k_colpass_hist<L, COLS, V, 2, false>), grid, block, s, a);
+        break;
+      case 4:
+        if (fast) PS_LAUNCH((k_colpass_hist<L, COLS, V, 4, true>), grid, block, s, a);
+        else PS_LAUNCH((k_colpass_hist<L, COLS, V, 4, false>), grid, block, s, a);
+        break;
+      case 8:
+        if (fast) PS_LAUNCH((k_colpass_hist<L, COLS, V, 8, true>), grid, block, s, a);
+        else PS_LAUNCH((k_colpass_hist<L, COLS, V, 8, false>), grid, block, s, a);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (bits) {
     case 2:
       if (fast) PS_LAUNCH((k_colpass<L, COLS, V, 2, true>), grid, block, s, a);
@@ -689,6 +801,20 @@ hipError_t launch_unpack(const void* packed, int bits, int S, int64_t n_time, fl
     case 32: hipLaunchKernelGGL(k_unpack<32>, dim3((unsigned)blocks), dim3(256), 0, s, in, S, n_time, out); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_power(const unsigned long long* counts, int n_streams, int bits, double* power,
+                             const Launch& l) {
+  PS_LAUNCH(k_hist_power, dim3((unsigned)((n_streams + 63) / 64)), dim3(64), l, counts, n_streams, bits, power);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 
