@@ -100,12 +100,18 @@ typedef struct {
  *   dterms          [n_pairs][4] float: d_x (re, im), d_y (re, im) of the leakage matrix
  *                   J = [[1, d_x], [d_y, 1]] (observed v' = G J v); NULL = 0 (Eq. 2 exactly).
  *   psi             parallactic angle psi_m in radians.
+ *   feed            PS_FEED_LINEAR (Eq. 2; pair = X, Y) or PS_FEED_CIRCULAR (pair = R, L): I = (C_rr + C_ll)/2,
+ *                   V = (C_rr - C_ll)/2, Q + iU = C_rl exp(2i psi), the combination of R = (X + iY)/sqrt 2,
+ *                   L = (X - iY)/sqrt 2 (so both feeds give the same Stokes for the same sky).
  */
+enum { PS_FEED_LINEAR = 0, PS_FEED_CIRCULAR = 1 };
 typedef struct {
   const float* gain_x;
   const float* gain_y;
   const float* dterms;
   double psi;
+  int32_t feed;
+  int32_t reserved;
 } ps_cal;
 
 /* Gradient outputs of ps_calibrate_backward, device memory, NULL = not wanted.  Complex gradients are

@@ -37,7 +37,7 @@ def _lib():
         lib.or_dft.argtypes = [dp, dp, i64, dp, dp]
         lib.or_accumulate.argtypes = [u8, C.c_int, C.c_int, i64, i64, dp, C.c_int, ip, ip, C.c_int, dp,
                                       C.POINTER(i64)]
-        lib.or_stokes.argtypes = [dp, C.c_int, i64, i64, C.c_double, dp, dp, dp, C.c_double, dp]
+        lib.or_stokes.argtypes = [dp, C.c_int, i64, i64, C.c_double, dp, dp, dp, C.c_double, C.c_int, dp]
         lib.or_calibrate_backward.argtypes = [u8, C.c_int, C.c_int, i64, i64, dp, dp, C.c_int, C.c_int, ip, ip,
                                               dp, i64, C.c_double, dp, dp, dp, C.c_double, dp, C.c_int,
                                               dp, dp, dp, dp, dp]
@@ -126,14 +126,16 @@ def accumulate(packed, bits, n_streams, n_time, fft_len, w, pairs, nthreads=0):
     return acc, nf.value
 
 
-def stokes(acc, n_frames, sumw2, gain_x=None, gain_y=None, dterms=None, psi=0.0):
+def stokes(acc, n_frames, sumw2, gain_x=None, gain_y=None, dterms=None, psi=0.0, feed="linear"):
+    """Eq. 2 (linear feeds) or the circular-feed combination (streams R, L) of the calibrated coherency."""
     acc = np.ascontiguousarray(acc, dtype=np.float64)
     P, _, C_ = acc.shape
     gx = _cplx_arg(gain_x, (P, C_))
     gy = _cplx_arg(gain_y, (P, C_))
     dt = _cplx_arg(dterms, (P, 2))
     out = np.empty((P, 4, C_), dtype=np.float64)
-    _check(_lib().or_stokes(_dp(acc), P, C_, n_frames, sumw2, _dp(gx), _dp(gy), _dp(dt), psi, _dp(out)),
+    f = {"linear": 0, "circular": 1}[feed]
+    _check(_lib().or_stokes(_dp(acc), P, C_, n_frames, sumw2, _dp(gx), _dp(gy), _dp(dt), psi, f, _dp(out)),
            "stokes")
     return out
 

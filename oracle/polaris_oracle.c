@@ -380,6 +380,19 @@ static mat2 m2_inv(mat2 a) {
   return r;
 }
 
+/* Circular feeds (no formula in the paper; reading): R = (X + iY)/sqrt 2, L = (X - iY)/sqrt 2 give
+ * C_rr = I + V, C_ll = I - V, C_rl = (Q + iU) at psi = 0, and the parallactic angle rotates Q + iU by
+ * exp(2 i psi) as Eq. 2 does for linear feeds.  Rows act on [C_rr, C_rl, C_lr, C_ll], factor 1/2 included. */
+static void or_circular_matrix(double psi, cplx m[4][4]) {
+  cplx e = cexp(2.0 * I * psi), ec = conj(e);
+  cplx row[4][4] = {{1.0, 0.0, 0.0, 1.0},
+                    {0.0, e, ec, 0.0},
+                    {0.0, -I * e, I * ec, 0.0},
+                    {1.0, 0.0, 0.0, -1.0}};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) m[i][j] = 0.5 * row[i][j];
+}
+
 /* the 4x4 Stokes matrix of Eq. 2, including its factor 1/2, acting on [C_xx, C_xy, C_yx, C_yy] */
 static void or_eq2_matrix(double psi, cplx m[4][4]) {
   double c2 = cos(2.0 * psi), s2 = sin(2.0 * psi);
@@ -415,12 +428,17 @@ static mat2 or_normalised(const double* a, int64_t C, int64_t k, double scale) {
 }
 
 int or_stokes(const double* acc, int n_pairs, int64_t n_chan, int64_t n_frames, double sumw2,
-              const double* gain_x, const double* gain_y, const double* dterms, double psi, double* iquv) {
+              const double* gain_x, const double* gain_y, const double* dterms, double psi, int feed,
+              double* iquv) {
   if (!acc || !iquv || n_pairs <= 0 || n_chan <= 0 || n_frames <= 0 || !(sumw2 > 0.0)) return OR_ERR_ARG;
+  if (feed != OR_FEED_LINEAR && feed != OR_FEED_CIRCULAR) return OR_ERR_ARG;
   int64_t C = n_chan;
   double scale = 1.0 / ((double)n_frames * sumw2);
   cplx m[4][4];
-  or_eq2_matrix(psi, m);
+  if (feed == OR_FEED_CIRCULAR)
+    or_circular_matrix(psi, m);
+  else
+    or_eq2_matrix(psi, m);
   for (int p = 0; p < n_pairs; ++p) {
     const double* a = acc + (int64_t)p * 4 * C;
     for (int64_t k = 0; k < C; ++k) {

@@ -34,9 +34,12 @@ int or_accumulate(const uint8_t* packed, int bits, int n_streams, int64_t n_time
                   double* acc, int64_t* n_frames);
 
 /* Calibrated Stokes iquv[p][0..3][k] = I, Q, U, V from raw products (Eq. 2 with gains and leakage).
- * gain_x, gain_y: [p][k] complex or NULL (= 1); dterms: [p] x (d_x re, im, d_y re, im) or NULL (= 0). */
+ * gain_x, gain_y: [p][k] complex or NULL (= 1); dterms: [p] x (d_x re, im, d_y re, im) or NULL (= 0).
+ * feed: OR_FEED_LINEAR (Eq. 2) or OR_FEED_CIRCULAR (the pair's streams are R, L). */
+enum { OR_FEED_LINEAR = 0, OR_FEED_CIRCULAR = 1 };
 int or_stokes(const double* acc, int n_pairs, int64_t n_chan, int64_t n_frames, double sumw2,
-              const double* gain_x, const double* gain_y, const double* dterms, double psi, double* iquv);
+              const double* gain_x, const double* gain_y, const double* dterms, double psi, int feed,
+              double* iquv);
 
 /* Gradient of a loss L(iquv) given g_iquv = dL/d iquv ([p][4][k]).  Complex gradients are returned as
  * (dL/dRe, dL/dIm).  d_w is dL/dw[n]; d_taps folds it onto the piecewise-linear taps.  NULL outputs are

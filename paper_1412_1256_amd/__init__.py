@@ -38,7 +38,11 @@ class _Instance(C.Structure):
 
 
 class _Cal(C.Structure):
-    _fields_ = [("gain_x", C.c_void_p), ("gain_y", C.c_void_p), ("dterms", C.c_void_p), ("psi", C.c_double)]
+    _fields_ = [("gain_x", C.c_void_p), ("gain_y", C.c_void_p), ("dterms", C.c_void_p), ("psi", C.c_double),
+                ("feed", C.c_int32), ("reserved", C.c_int32)]
+
+
+FEED = {"linear": 0, "circular": 1}
 
 
 class _CalGrad(C.Structure):
@@ -260,21 +264,24 @@ class Plan:
         _check(lib().ps_spectra(self._h, inst, _ptr(out), C.byref(nf)))
         return out, nf.value
 
-    def _cal(self, gain_x, gain_y, dterms, psi):
+    def _cal(self, gain_x, gain_y, dterms, psi, feed="linear"):
         cal = _Cal()
         cal.gain_x = None if gain_x is None else gain_x.data_ptr()
         cal.gain_y = None if gain_y is None else gain_y.data_ptr()
         cal.dterms = None if dterms is None else dterms.data_ptr()
         cal.psi = float(psi)
+        cal.feed = FEED[feed] if isinstance(feed, str) else int(feed)
         return cal
 
-    def stokes(self, inst: int = 0, gain_x=None, gain_y=None, dterms=None, psi: float = 0.0, out=None):
-        """Calibrated I, Q, U, V [n_pairs][4][C] float32.  gains: float32 [P][C][2] (or complex64 [P][C])."""
+    def stokes(self, inst: int = 0, gain_x=None, gain_y=None, dterms=None, psi: float = 0.0, out=None,
+               feed="linear"):
+        """Calibrated I, Q, U, V [n_pairs][4][C] float32.  gains: float32 [P][C][2] (or complex64 [P][C]).
+        feed: "linear" (Eq. 2, pair = X, Y) or "circular" (pair = R, L)."""
         I = self.instances[inst]
         gain_x, gain_y, dterms = (self._as_f32(gain_x), self._as_f32(gain_y), self._as_f32(dterms))
         if out is None:
             out = self.torch.empty((I.n_pairs, 4, I.channels), dtype=self.torch.float32, device=self.device)
-        cal = self._cal(gain_x, gain_y, dterms, psi)
+        cal = self._cal(gain_x, gain_y, dterms, psi, feed)
         _check(lib().ps_stokes(self._h, inst, C.byref(cal), _ptr(out)))
         return out
 

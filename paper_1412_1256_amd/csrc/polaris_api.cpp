@@ -901,6 +901,9 @@ ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv
   const double psi = cal ? cal->psi : 0.0;
   o.cos2psi = std::cos(2.0 * psi);
   o.sin2psi = std::sin(2.0 * psi);
+  if (cal && cal->feed != PS_FEED_LINEAR && cal->feed != PS_FEED_CIRCULAR)
+    return fail(PS_ERR_ARG, "unknown feed %d", cal->feed);
+  o.circular = (cal && cal->feed == PS_FEED_CIRCULAR) ? 1 : 0;
   if (cal) {
     o.gain_x = cal->gain_x;
     o.gain_y = cal->gain_y;
@@ -930,6 +933,9 @@ ps_status ps_stokes_all(ps_plan_t plan, const ps_cal* cal, float* const* iquv_de
     const double psi = cal ? cal[i].psi : 0.0;
     o.cos2psi = std::cos(2.0 * psi);
     o.sin2psi = std::sin(2.0 * psi);
+    if (cal && cal[i].feed != PS_FEED_LINEAR && cal[i].feed != PS_FEED_CIRCULAR)
+      return fail(PS_ERR_ARG, "instance %zu: unknown feed %d", i, cal[i].feed);
+    o.circular = (cal && cal[i].feed == PS_FEED_CIRCULAR) ? 1 : 0;
     if (cal) {
       o.gain_x = cal[i].gain_x;
       o.gain_y = cal[i].gain_y;
@@ -1057,6 +1063,8 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
   Inst& I = plan->inst[(size_t)inst];
   if (!dL_diquv_dev || !grad) return fail(PS_ERR_ARG, "null upstream gradient or gradient outputs");
   if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %d has no accumulated frames", inst);
+  if (cal && cal->feed != PS_FEED_LINEAR)
+    return fail(PS_ERR_UNSUPPORTED, "the adjoint is built for linear feeds (Eq. 2)");
   const bool want_taps = grad->d_taps != nullptr;
   if (want_taps) {
     if (!I.taps()) return fail(PS_ERR_ARG, "d_taps requested for an instance without a PS_WIN_TAPS window");

@@ -60,6 +60,7 @@ struct OutArgs {
   const float* gain_y;
   const float* dterms;      // [P][4] or nullptr
   double cos2psi, sin2psi;
+  int32_t circular;         // 1: the pair's streams are R, L
   float* iquv;              // [P][4][C]
   double* spectra;          // [P][4][C] (raw sums) when producing spectra
 };

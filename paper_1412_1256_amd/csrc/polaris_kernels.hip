@@ -446,12 +446,21 @@ __device__ __forceinline__ void output_tile(const OutArgs& a, const int bx, cons
         cxy = cda(cdm(t00, cdc(f10)), cdm(t01, cdc(f11)));
         cyy = cda(cdm(t10, cdc(f10)), cdm(t11, cdc(f11))).x;
       }
-      // Eq. 2 rows acting on [C_xx, C_xy, C_yx, C_yy] with C_yx = conj C_xy
       const double c2 = a.cos2psi, s2 = a.sin2psi;
-      const double I = 0.5 * (cxx + cyy);
-      const double Q = 0.5 * (c2 * (cxx - cyy) - s2 * 2.0 * cxy.x);
-      const double Uq = 0.5 * (s2 * (cxx - cyy) + c2 * 2.0 * cxy.x);
-      const double V = cxy.y;  // Re(-i C_xy + i C_yx) / 2
+      double I, Q, Uq, V;
+      if (a.circular) {
+        // streams R, L: I = (C_rr + C_ll)/2, V = (C_rr - C_ll)/2, Q + iU = C_rl exp(2i psi)
+        I = 0.5 * (cxx + cyy);
+        V = 0.5 * (cxx - cyy);
+        Q = c2 * cxy.x - s2 * cxy.y;
+        Uq = s2 * cxy.x + c2 * cxy.y;
+      } else {
+        // Eq. 2 rows acting on [C_xx, C_xy, C_yx, C_yy] with C_yx = conj C_xy
+        I = 0.5 * (cxx + cyy);
+        Q = 0.5 * (c2 * (cxx - cyy) - s2 * 2.0 * cxy.x);
+        Uq = 0.5 * (s2 * (cxx - cyy) + c2 * 2.0 * cxy.x);
+        V = cxy.y;  // Re(-i C_xy + i C_yx) / 2
+      }
       float* o = a.iquv + (int64_t)p * 4 * a.C + k;
       o[0] = (float)I;
       o[a.C] = (float)Q;

@@ -29,7 +29,7 @@ def test_every_declared_function_is_exported():
 def test_instance_struct_layout_matches_header():
     assert C.sizeof(pk._Instance) == 80
     assert pk._Instance.fft_len.offset == 64
-    assert C.sizeof(pk._Cal) == 32
+    assert C.sizeof(pk._Cal) == 40 and pk._Cal.feed.offset == 32
 
 
 def _plan(**kw):

@@ -320,3 +320,30 @@ def test_reused_input_buffer_between_calls(pk, torch_dev):
     e = spectra_err(got.cpu().numpy(), acc)
     say(f"  spectra err {e.ravel().tolist()}")
     assert np.all(e < TOL), e
+
+
+@pytest.mark.parametrize("psi", [0.0, 0.7])
+def test_circular_feeds(pk, torch_dev, psi):
+    """Streams taken as R, L: the circular-feed combination with gains and leakage against the oracle."""
+    torch, dev = torch_dev
+    say(f"circular feeds psi={psi}")
+    inst = synth.make_correlated_noise(8, 0.4, 1 << 14, 40, seed_extra=90)
+    rng = np.random.default_rng(90)
+    C = inst["fft_len"] // 2
+    gx = (1 + 0.05 * (rng.standard_normal((1, C)) + 1j * rng.standard_normal((1, C)))).astype(np.complex64)
+    gy = (1 + 0.05 * (rng.standard_normal((1, C)) + 1j * rng.standard_normal((1, C)))).astype(np.complex64)
+    dt = (0.02 * np.exp(1j * rng.uniform(0, 6.28, (1, 2)))).astype(np.complex64)
+    acc, nf, s2, _ = oracle.run_instance(inst)
+    ref = oracle.stokes(acc, nf, s2, gain_x=gx.astype(np.complex128), gain_y=gy.astype(np.complex128),
+                        dterms=dt.astype(np.complex128), psi=psi, feed="circular")
+    plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev)
+    plan.reset()
+    plan.accumulate(torch.from_numpy(inst["packed"]).to(dev))
+    got = plan.stokes(gain_x=torch.from_numpy(gx).to(dev), gain_y=torch.from_numpy(gy).to(dev),
+                      dterms=torch.from_numpy(dt).to(dev), psi=psi, feed="circular").cpu().numpy()
+    e = stokes_err(got.astype(np.float64), ref)
+    say(f"  err {e.tolist()}")
+    assert np.all(e < TOL)
+    with pytest.raises(pk.PolarisError) as ex:
+        plan.stokes(feed=5)
+    assert ex.value.code == "PS_ERR_ARG"

@@ -87,3 +87,41 @@ def test_unpolarized_noise_has_small_q_u_v():
     I = st[0][1:]
     for q in st[1:]:
         assert np.sqrt(np.mean((q[1:] / I) ** 2)) < 3 / np.sqrt(nf)
+
+
+# ------------------------------------------------------------------------------------------------
+# circular feeds (a reading: R = (X + iY)/sqrt 2, L = (X - iY)/sqrt 2; the paper gives no formula)
+
+def _coherency_acc(X, Y):
+    """raw products acc[1][4][C] (XX*, YY*, Re XY*, Im XY*) of one frame of spectra X, Y"""
+    xy = X * np.conj(Y)
+    return np.stack([np.abs(X) ** 2, np.abs(Y) ** 2, xy.real, xy.imag])[None]
+
+
+@pytest.mark.parametrize("psi", [0.0, 0.3, -1.1])
+def test_circular_feeds_see_the_same_sky(psi):
+    """The same field sampled by linear feeds (X, Y) and by circular feeds (R, L) gives the same Stokes."""
+    rng = np.random.default_rng(21)
+    C = 64
+    X = rng.standard_normal(C) + 1j * rng.standard_normal(C)
+    Y = rng.standard_normal(C) + 1j * rng.standard_normal(C)
+    R = (X + 1j * Y) / np.sqrt(2.0)
+    L = (X - 1j * Y) / np.sqrt(2.0)
+    lin = oracle.stokes(_coherency_acc(X, Y), 1, 1.0, psi=psi)
+    circ = oracle.stokes(_coherency_acc(R, L), 1, 1.0, psi=psi, feed="circular")
+    assert np.allclose(lin, circ, rtol=0, atol=1e-12 * np.max(np.abs(lin)))
+
+
+def test_circular_pure_states():
+    C = 8
+    ones = np.ones(C, dtype=complex)
+    # right-circular only: V = I; left only: V = -I
+    r = oracle.stokes(_coherency_acc(ones, 0 * ones), 1, 1.0, feed="circular")[0]
+    assert np.allclose(r[0], 0.5) and np.allclose(r[3], 0.5) and np.allclose(r[1:3], 0.0)
+    l_ = oracle.stokes(_coherency_acc(0 * ones, ones), 1, 1.0, feed="circular")[0]
+    assert np.allclose(l_[3], -0.5)
+    # equal R and L in phase: linear polarization, Q = I, and psi rotates it into U
+    q = oracle.stokes(_coherency_acc(ones, ones), 1, 1.0, feed="circular")[0]
+    assert np.allclose(q[1], q[0]) and np.allclose(q[2], 0.0) and np.allclose(q[3], 0.0)
+    u = oracle.stokes(_coherency_acc(ones, ones), 1, 1.0, psi=np.pi / 4, feed="circular")[0]
+    assert np.allclose(u[2], u[0]) and np.allclose(u[1], 0.0, atol=1e-15)
