@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-WIN = {"rect": 0, "hann": 1, "taps": 2}
+WIN = {"rect": 0, "hann": 1, "taps": 2, "hamming": 3, "blackman": 4}
 
 
 def _lib():
@@ -35,10 +35,10 @@ def _lib():
         lib.or_window.argtypes = [C.c_int, i64, dp, C.c_int, dp, dp]
         lib.or_fft.argtypes = [dp, dp, i64]
         lib.or_dft.argtypes = [dp, dp, i64, dp, dp]
-        lib.or_accumulate.argtypes = [u8, C.c_int, C.c_int, i64, i64, dp, C.c_int, ip, ip, C.c_int, dp,
+        lib.or_accumulate.argtypes = [u8, C.c_int, C.c_int, i64, i64, i64, dp, C.c_int, ip, ip, C.c_int, dp,
                                       C.POINTER(i64)]
         lib.or_stokes.argtypes = [dp, C.c_int, i64, i64, C.c_double, dp, dp, dp, C.c_double, C.c_int, dp]
-        lib.or_calibrate_backward.argtypes = [u8, C.c_int, C.c_int, i64, i64, dp, dp, C.c_int, C.c_int, ip, ip,
+        lib.or_calibrate_backward.argtypes = [u8, C.c_int, C.c_int, i64, i64, i64, dp, dp, C.c_int, C.c_int, ip, ip,
                                               dp, i64, C.c_double, dp, dp, dp, C.c_double, dp, C.c_int,
                                               dp, dp, dp, dp, dp]
         for f in ("or_unpack", "or_window", "or_fft", "or_dft", "or_accumulate", "or_stokes",
@@ -111,8 +111,8 @@ def _pairs(pairs):
     return px, py
 
 
-def accumulate(packed, bits, n_streams, n_time, fft_len, w, pairs, nthreads=0):
-    """Raw products acc[p][4][C] and the frame count."""
+def accumulate(packed, bits, n_streams, n_time, fft_len, w, pairs, nthreads=0, hop=0):
+    """Raw products acc[p][4][C] and the frame count; frame f starts at sample f * hop (0: fft_len)."""
     packed = np.ascontiguousarray(packed, dtype=np.uint8)
     w = np.ascontiguousarray(w, dtype=np.float64)
     px, py = _pairs(pairs)
@@ -120,7 +120,7 @@ def accumulate(packed, bits, n_streams, n_time, fft_len, w, pairs, nthreads=0):
     acc = np.empty((len(pairs), 4, C_), dtype=np.float64)
     nf = C.c_int64(0)
     ip = C.POINTER(C.c_int)
-    _check(_lib().or_accumulate(_u8(packed), bits, n_streams, n_time, fft_len, _dp(w), len(pairs),
+    _check(_lib().or_accumulate(_u8(packed), bits, n_streams, n_time, fft_len, hop, _dp(w), len(pairs),
                                 px.ctypes.data_as(ip), py.ctypes.data_as(ip), nthreads, _dp(acc), C.byref(nf)),
            "accumulate")
     return acc, nf.value
@@ -141,7 +141,7 @@ def stokes(acc, n_frames, sumw2, gain_x=None, gain_y=None, dterms=None, psi=0.0,
 
 
 def calibrate_backward(packed, bits, n_streams, n_time, fft_len, w, pairs, acc, n_frames, sumw2, g_iquv,
-                       gain_x=None, gain_y=None, dterms=None, psi=0.0, taps=None, nthreads=0):
+                       gain_x=None, gain_y=None, dterms=None, psi=0.0, taps=None, nthreads=0, hop=0):
     """Returns dict with d_gain_x, d_gain_y ([P][C] complex), d_dterms ([P][2] complex), d_w, d_taps."""
     packed = np.ascontiguousarray(packed, dtype=np.uint8)
     w = np.ascontiguousarray(w, dtype=np.float64)
@@ -160,7 +160,7 @@ def calibrate_backward(packed, bits, n_streams, n_time, fft_len, w, pairs, acc, 
     dtaps = np.zeros(0 if t is None else t.size)
     ip = C.POINTER(C.c_int)
     _check(_lib().or_calibrate_backward(
-        _u8(packed), bits, n_streams, n_time, fft_len, _dp(w), _dp(t), 0 if t is None else t.size, P,
+        _u8(packed), bits, n_streams, n_time, fft_len, hop, _dp(w), _dp(t), 0 if t is None else t.size, P,
         px.ctypes.data_as(ip), py.ctypes.data_as(ip), _dp(acc), n_frames, sumw2, _dp(gx), _dp(gy), _dp(dt), psi,
         _dp(g), nthreads, _dp(dgx), _dp(dgy), _dp(ddt), _dp(dw), _dp(dtaps) if t is not None else None),
         "calibrate_backward")
@@ -172,7 +172,7 @@ def run_instance(inst: dict, taps=None, nthreads: int = 0):
     """Raw products, frame count and window sum of squares of a synth instance dict."""
     w, s2 = window(inst["window"], inst["fft_len"], taps=taps)
     acc, nf = accumulate(inst["packed"], inst["bits"], inst["n_streams"], inst["n_samples"], inst["fft_len"], w,
-                         inst["pairs"], nthreads=nthreads)
+                         inst["pairs"], nthreads=nthreads, hop=inst.get("hop", 0))
     return acc, nf, s2, w
 
 
@@ -181,7 +181,9 @@ def run_instance(inst: dict, taps=None, nthreads: int = 0):
 
 def level_histograms(packed, bits: int, n_streams: int, n_time: int, pairs) -> np.ndarray:
     """Counts [P][2 (X, Y)][2^bits] of every sample of each pair's streams, bins in ascending level order.
-    Plain definition: decode every item (the pinned unpack) and count equal levels."""
+    Plain definition: decode every item (the pinned unpack) and count equal levels.  (With overlapped
+    frames every sample is counted once, as it leaves the segmentation: pass the samples up to the last
+    N - hop of the stream, which are counted with the next call's data.)"""
     levels = unpack(packed, bits, n_streams, n_time)
     nbin = 1 << bits
     lv = np.arange(nbin) - 128 if bits == 8 else 2 * np.arange(nbin) - (nbin - 1)

@@ -83,6 +83,10 @@ int or_window(int kind, int64_t n, const double* taps, int n_taps, double* w, do
       v = 1.0;
     } else if (kind == OR_WIN_HANN) { /* periodic (DFT-even) Hann */
       v = 0.5 - 0.5 * cos(OR_TWO_PI * (double)i / (double)n);
+    } else if (kind == OR_WIN_HAMMING) { /* periodic Hamming, coefficients 0.54 and 0.46 */
+      v = 0.54 - 0.46 * cos(OR_TWO_PI * (double)i / (double)n);
+    } else if (kind == OR_WIN_BLACKMAN) { /* periodic Blackman, coefficients 0.42, 0.5 and 0.08 */
+      v = 0.42 - 0.5 * cos(OR_TWO_PI * (double)i / (double)n) + 0.08 * cos(2.0 * OR_TWO_PI * (double)i / (double)n);
     } else if (kind == OR_WIN_TAPS) {
       if (!taps || n_taps < 2) return OR_ERR_ARG;
       double u = (double)i * (double)(n_taps - 1) / (double)(n - 1);
@@ -238,11 +242,12 @@ static int or_thread_count(int nthreads, int64_t n_blocks) {
   return n;
 }
 
-/* the windowed frame f of stream s as a complex sequence (x_w, 0), transformed in place */
-static void or_frame_spectrum(const uint8_t* packed, int bits, int S, int64_t N, int64_t f, int s,
+/* the windowed frame f (samples f*hop .. f*hop + N - 1) of stream s as a complex sequence (x_w, 0),
+ * transformed in place */
+static void or_frame_spectrum(const uint8_t* packed, int bits, int S, int64_t N, int64_t hop, int64_t f, int s,
                               const double* w, const double* c, const double* sn, double* re, double* im) {
   for (int64_t n = 0; n < N; ++n) {
-    re[n] = w[n] * or_level(packed, bits, S, f * N + n, s);
+    re[n] = w[n] * or_level(packed, bits, S, f * hop + n, s);
     im[n] = 0.0;
   }
   or_fft_core(re, im, N, c, sn);
@@ -256,7 +261,7 @@ typedef struct {
   const uint8_t* packed;
   int bits, S, P;
   const int *px, *py;
-  int64_t N, C, F;
+  int64_t N, C, F, hop;
   const double* w;
   const double *c, *s;
   double* acc; /* [P][4][C] */
@@ -279,7 +284,7 @@ static void* or_acc_worker(void* arg) {
     int64_t f_end = (b + 1) * OR_FRAME_BLOCK < J->F ? (b + 1) * OR_FRAME_BLOCK : J->F;
     for (int64_t f = b * OR_FRAME_BLOCK; f < f_end; ++f) {
       for (int s = 0; s < J->S; ++s)
-        or_frame_spectrum(J->packed, J->bits, J->S, N, f, s, J->w, J->c, J->s, re + s * N, im + s * N);
+        or_frame_spectrum(J->packed, J->bits, J->S, N, J->hop, f, s, J->w, J->c, J->s, re + s * N, im + s * N);
       for (int p = 0; p < J->P; ++p) {
         const double *xr = re + J->px[p] * N, *xi = im + J->px[p] * N;
         const double *yr = re + J->py[p] * N, *yi = im + J->py[p] * N;
@@ -307,13 +312,24 @@ static int or_check_pairs(int S, int P, const int* px, const int* py) {
   return 1;
 }
 
-int or_accumulate(const uint8_t* packed, int bits, int n_streams, int64_t n_time, int64_t fft_len,
+/* Segmentation (Sec. 3.1): frame f covers samples f*hop .. f*hop + N - 1; every whole frame of the buffer
+ * is taken.  hop = N (contiguous frames) or N / 2^j (overlap of 1 - 2^-j; the paper mentions 50 %). */
+static int or_hop_ok(int64_t fft_len, int64_t hop) {
+  return hop > 0 && hop <= fft_len && fft_len % hop == 0 && or_is_pow2(hop);
+}
+
+static int64_t or_frame_count(int64_t n_time, int64_t fft_len, int64_t hop) {
+  return n_time < fft_len ? 0 : (n_time - fft_len) / hop + 1;
+}
+
+int or_accumulate(const uint8_t* packed, int bits, int n_streams, int64_t n_time, int64_t fft_len, int64_t hop,
                   const double* w, int n_pairs, const int* pair_x, const int* pair_y, int nthreads,
                   double* acc, int64_t* n_frames) {
+  if (hop == 0) hop = fft_len;
   if (!packed || !w || !acc || !or_bits_ok(bits) || !or_is_pow2(fft_len) || n_time < 0 ||
-      !or_check_pairs(n_streams, n_pairs, pair_x, pair_y) || n_time % fft_len)
+      !or_check_pairs(n_streams, n_pairs, pair_x, pair_y) || n_time % fft_len || !or_hop_ok(fft_len, hop))
     return OR_ERR_ARG;
-  int64_t N = fft_len, C = N / 2, F = n_time / N;
+  int64_t N = fft_len, C = N / 2, F = or_frame_count(n_time, N, hop);
   memset(acc, 0, sizeof(double) * (size_t)(4 * C * n_pairs));
   if (n_frames) *n_frames = F;
   if (F == 0) return OR_OK;
@@ -325,7 +341,7 @@ int or_accumulate(const uint8_t* packed, int bits, int n_streams, int64_t n_time
   or_sched_init(&q);
   int64_t n_blocks = (F + OR_FRAME_BLOCK - 1) / OR_FRAME_BLOCK;
   int nt = or_thread_count(nthreads, n_blocks);
-  or_acc_job job = {packed, bits, n_streams, n_pairs, pair_x, pair_y, N, C, F, w, c, s, acc, &q, OR_OK};
+  or_acc_job job = {packed, bits, n_streams, n_pairs, pair_x, pair_y, N, C, F, hop, w, c, s, acc, &q, OR_OK};
   pthread_t* th = malloc(sizeof(pthread_t) * (size_t)nt);
   for (int i = 0; i < nt; ++i) pthread_create(&th[i], NULL, or_acc_worker, &job);
   for (int i = 0; i < nt; ++i) pthread_join(th[i], NULL);
@@ -476,7 +492,7 @@ typedef struct {
   const uint8_t* packed;
   int bits, S, P;
   const int *px, *py;
-  int64_t N, C, F;
+  int64_t N, C, F, hop;
   const double* w;
   const double *c, *s;
   const cplx* gA; /* [P][C][4]: Gb(A) entries 00, 01, 10, 11 */
@@ -506,7 +522,7 @@ static void* or_grad_worker(void* arg) {
     int64_t f_end = (b + 1) * OR_FRAME_BLOCK < J->F ? (b + 1) * OR_FRAME_BLOCK : J->F;
     for (int64_t f = b * OR_FRAME_BLOCK; f < f_end; ++f) {
       for (int s = 0; s < J->S; ++s)
-        or_frame_spectrum(J->packed, J->bits, J->S, N, f, s, J->w, J->c, J->s, re + s * N, im + s * N);
+        or_frame_spectrum(J->packed, J->bits, J->S, N, J->hop, f, s, J->w, J->c, J->s, re + s * N, im + s * N);
       for (int p = 0; p < J->P; ++p) {
         int sx = J->px[p], sy = J->py[p];
         for (int which = 0; which < 2; ++which) {
@@ -525,7 +541,7 @@ static void* or_grad_worker(void* arg) {
           /* Re sum_k Gb_k e^{+i theta} = Re sum_k conj(Gb_k) e^{-i theta} */
           or_fft_core(hr, hi, N, J->c, J->s);
           int src = which == 0 ? sx : sy;
-          for (int64_t n = 0; n < N; ++n) part[n] += or_level(J->packed, J->bits, J->S, f * N + n, src) * hr[n];
+          for (int64_t n = 0; n < N; ++n) part[n] += or_level(J->packed, J->bits, J->S, f * J->hop + n, src) * hr[n];
         }
       }
     }
@@ -538,14 +554,15 @@ static void* or_grad_worker(void* arg) {
 }
 
 int or_calibrate_backward(const uint8_t* packed, int bits, int n_streams, int64_t n_time, int64_t fft_len,
-                          const double* w, const double* taps, int n_taps, int n_pairs, const int* pair_x,
+                          int64_t hop, const double* w, const double* taps, int n_taps, int n_pairs, const int* pair_x,
                           const int* pair_y, const double* acc, int64_t n_frames, double sumw2,
                           const double* gain_x, const double* gain_y, const double* dterms, double psi,
                           const double* g_iquv, int nthreads, double* d_gain_x, double* d_gain_y,
                           double* d_dterms, double* d_w, double* d_taps) {
+  if (hop == 0) hop = fft_len;
   if (!packed || !w || !acc || !g_iquv || !or_bits_ok(bits) || !or_is_pow2(fft_len) ||
       !or_check_pairs(n_streams, n_pairs, pair_x, pair_y) || n_time % fft_len || n_frames <= 0 ||
-      n_time / fft_len != n_frames || !(sumw2 > 0.0))
+      !or_hop_ok(fft_len, hop) || or_frame_count(n_time, fft_len, hop) != n_frames || !(sumw2 > 0.0))
     return OR_ERR_ARG;
   int64_t N = fft_len, C = N / 2, F = n_frames;
   double fs = (double)F * sumw2;
@@ -607,7 +624,7 @@ int or_calibrate_backward(const uint8_t* packed, int bits, int n_streams, int64_
     or_sched_init(&q);
     int64_t n_blocks = (F + OR_FRAME_BLOCK - 1) / OR_FRAME_BLOCK;
     int nt = or_thread_count(nthreads, n_blocks);
-    or_grad_job job = {packed, bits, n_streams, n_pairs, pair_x, pair_y, N, C, F, w, c, s, gA, dw, &q, OR_OK};
+    or_grad_job job = {packed, bits, n_streams, n_pairs, pair_x, pair_y, N, C, F, hop, w, c, s, gA, dw, &q, OR_OK};
     pthread_t* th = malloc(sizeof(pthread_t) * (size_t)nt);
     for (int i = 0; i < nt; ++i) pthread_create(&th[i], NULL, or_grad_worker, &job);
     for (int i = 0; i < nt; ++i) pthread_join(th[i], NULL);

@@ -14,7 +14,7 @@ extern "C" {
 #endif
 
 enum { OR_OK = 0, OR_ERR_ARG = -1, OR_ERR_MEM = -2 };
-enum { OR_WIN_RECT = 0, OR_WIN_HANN = 1, OR_WIN_TAPS = 2 };
+enum { OR_WIN_RECT = 0, OR_WIN_HANN = 1, OR_WIN_TAPS = 2, OR_WIN_HAMMING = 3, OR_WIN_BLACKMAN = 4 };
 
 /* Decode n_time x n_streams items of a packed buffer into levels, out[s * n_time + t]. */
 int or_unpack(const uint8_t* packed, int bits, int n_streams, int64_t n_time, double* out);
@@ -28,8 +28,9 @@ int or_fft(double* re, double* im, int64_t n);
 /* Brute-force DFT of the same convention (any n). */
 int or_dft(const double* re, const double* im, int64_t n, double* out_re, double* out_im);
 
-/* Raw accumulated products acc[p][q][k], q = XX*, YY*, Re XY*, Im XY*; k < fft_len/2; frames = n_time/fft_len. */
-int or_accumulate(const uint8_t* packed, int bits, int n_streams, int64_t n_time, int64_t fft_len,
+/* Raw accumulated products acc[p][q][k], q = XX*, YY*, Re XY*, Im XY*; k < fft_len/2.  Frame f covers
+ * samples f*hop .. f*hop + fft_len - 1 (hop 0 = fft_len; else fft_len / 2^j); frames = (n_time - fft_len)/hop + 1. */
+int or_accumulate(const uint8_t* packed, int bits, int n_streams, int64_t n_time, int64_t fft_len, int64_t hop,
                   const double* w, int n_pairs, const int* pair_x, const int* pair_y, int nthreads,
                   double* acc, int64_t* n_frames);
 
@@ -45,7 +46,7 @@ int or_stokes(const double* acc, int n_pairs, int64_t n_chan, int64_t n_frames, 
  * (dL/dRe, dL/dIm).  d_w is dL/dw[n]; d_taps folds it onto the piecewise-linear taps.  NULL outputs are
  * skipped. */
 int or_calibrate_backward(const uint8_t* packed, int bits, int n_streams, int64_t n_time, int64_t fft_len,
-                          const double* w, const double* taps, int n_taps, int n_pairs, const int* pair_x,
+                          int64_t hop, const double* w, const double* taps, int n_taps, int n_pairs, const int* pair_x,
                           const int* pair_y, const double* acc, int64_t n_frames, double sumw2,
                           const double* gain_x, const double* gain_y, const double* dterms, double psi,
                           const double* g_iquv, int nthreads, double* d_gain_x, double* d_gain_y,

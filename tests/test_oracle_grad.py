@@ -33,7 +33,7 @@ def _loss(s, taps=None, gx=None, gy=None, dt=None):
     dt = s["dt"] if dt is None else dt
     inst = s["inst"]
     w, s2 = oracle.window("taps", N, taps=taps)
-    acc, nf = oracle.accumulate(inst["packed"], 8, 2, inst["n_samples"], N, w, inst["pairs"])
+    acc, nf = oracle.accumulate(inst["packed"], 8, 2, inst["n_samples"], N, w, inst["pairs"], hop=s.get("hop", 0))
     st = oracle.stokes(acc, nf, s2, gain_x=gx, gain_y=gy, dterms=dt, psi=s["psi"])
     # L = sum c * P + 0.5 sum P^2 / scale  (upstream gradient c + P / scale)
     return float(np.sum(s["wts"] * st) + 0.5 * np.sum(st ** 2) / 1e4), st
@@ -42,11 +42,12 @@ def _loss(s, taps=None, gx=None, gy=None, dt=None):
 def _analytic(s):
     inst = s["inst"]
     w, s2 = oracle.window("taps", N, taps=s["taps"])
-    acc, nf = oracle.accumulate(inst["packed"], 8, 2, inst["n_samples"], N, w, inst["pairs"])
+    acc, nf = oracle.accumulate(inst["packed"], 8, 2, inst["n_samples"], N, w, inst["pairs"], hop=s.get("hop", 0))
     _, st = _loss(s)
     g = s["wts"] + st / 1e4
     return oracle.calibrate_backward(inst["packed"], 8, 2, inst["n_samples"], N, w, inst["pairs"], acc, nf, s2, g,
-                                     gain_x=s["gx"], gain_y=s["gy"], dterms=s["dt"], psi=s["psi"], taps=s["taps"])
+                                     gain_x=s["gx"], gain_y=s["gy"], dterms=s["dt"], psi=s["psi"], taps=s["taps"],
+                                     hop=s.get("hop", 0))
 
 
 def _cfd(f, h):
@@ -95,3 +96,19 @@ def test_tap_gradient(setup):
         fd = _cfd(f, 1e-5)
         an = g["d_taps"][j]
         assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (j, fd, an)
+
+
+@pytest.mark.parametrize("hop", [N // 2, N // 4])
+def test_tap_gradient_overlapped_frames(setup, hop):
+    """Overlapped segmentation (frame f at sample f * hop): every sample enters several frames, each with its
+    own window position."""
+    s = dict(setup, hop=hop)
+    g = _analytic(s)
+    for j in [0, 20, 63]:
+        def f(h):
+            t = s["taps"].copy()
+            t[j] += h
+            return _loss(s, taps=t)[0]
+        fd = _cfd(f, 1e-5)
+        an = g["d_taps"][j]
+        assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (hop, j, fd, an)
