@@ -386,6 +386,76 @@ def power_form(pk, torch, dev, inst, packed, steps):
     return res
 
 
+def _ring_integrations(pk, torch, dev, inst, ring, steps, warmup=3):
+    """Whole integrations (reset, accumulate, Stokes of every pair) of an instance, each from the next
+    HBM-resident buffer of a ring; returns the mean time per integration and per-kernel averages."""
+    side = torch.cuda.Stream(dev)
+    with torch.cuda.stream(side):
+        plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev, stream=side)
+        out = torch.empty((len(inst["pairs"]), 4, inst["fft_len"] // 2), dtype=torch.float32, device=dev)
+    pos = [0]
+
+    def step():
+        buf = ring[pos[0] % len(ring)]
+        pos[0] += 1
+        plan.reset()
+        plan.accumulate(buf)
+        plan.stokes(psi=0.25, out=out)
+
+    with torch.cuda.stream(side):
+        t = time_steps(torch, dev, step, steps, warmup)
+        plan.profile_enable(True)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize(dev)
+    prof = plan.profile_read()
+    plan.profile_enable(False)
+    kern = {k: {"launches": n / steps, "avg_us": ms / n * 1e3} for k, (ms, n) in prof.items()}
+    return t, kern, plan
+
+
+def overlap_form(pk, torch, dev, inst, ring, steps):
+    """The paper workload (2 int8 streams, 2^18 points, 0.999 s of data) with 50 % overlapped frames and
+    a Hamming window (Sec. 3.1), against contiguous rectangular frames, on the same streamed input."""
+    N = inst["fft_len"]
+    res = {}
+    for name, hop, window in (("contiguous_rect", N, "rect"), ("half_overlap_hamming", N // 2, "hamming")):
+        d = dict(inst, hop=hop, window=window)
+        t, kern, plan = _ring_integrations(pk, torch, dev, d, ring, steps)
+        frames = (inst["n_samples"] - N) // hop + 1
+        r = {"frames": frames, "us": t * 1e6, "Gsamples_per_s": inst["n_samples"] * 2 / t / 1e9,
+             "frames_per_s": frames / t, "x_realtime": inst["n_samples"] / SAMPLE_RATE / t}
+        for k in ("colpass", "rowpass", "stokes"):
+            if k in kern:
+                r[f"{k}_us"] = kern[k]["avg_us"]
+                r[f"{k}_launches"] = kern[k]["launches"]
+        # column pass: each frame's input bytes (overlapped samples are read by both frames) + intermediate
+        cp = kernel_bytes("colpass", d, frames)
+        r["colpass_GBps_frame_bytes"] = cp / (r["colpass_us"] * 1e-6) / 1e9 if "colpass_us" in r else None
+        res[name] = r
+    res["time_ratio"] = res["half_overlap_hamming"]["us"] / res["contiguous_rect"]["us"]
+    return res
+
+
+def modes_form(pk, torch, dev, steps, ring_n):
+    """Table 1's two sampler modes with all four IFs, one second of data per integration: 8 MHz (16 Msps,
+    4-bit, 2^18 points) and 4 MHz (8 Msps, 8-bit, 2^17 points), each from a ring of HBM-resident buffers."""
+    import synth
+    res = {}
+    for mode in ("8MHz", "4MHz"):
+        d = synth.make_mode(mode, n_frames=61)
+        packed = torch.from_numpy(d["packed"]).to(dev)
+        ring = [packed] + [packed.clone() for _ in range(max(1, ring_n) - 1)]
+        t, kern, _ = _ring_integrations(pk, torch, dev, d, ring, steps)
+        seconds = d["n_samples"] / d["sample_rate_hz"]
+        res[mode] = {"bits": d["bits"], "fft_len": d["fft_len"], "n_streams": 4, "frames": d["n_frames"],
+                     "data_seconds": seconds, "us": t * 1e6,
+                     "Gsamples_per_s": d["n_samples"] * 4 / t / 1e9, "x_realtime": seconds / t,
+                     "kernels_us": {k: v["avg_us"] for k, v in kern.items()}}
+        del ring, packed
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -507,6 +577,8 @@ def main():
     out["fwd_bwd"] = differentiation_form(pk, torch, dev, max(5, args.steps // 2), 2)
     out["autotune"] = autotune_form(pk, torch, dev, inst, packed, args.steps)
     out["total_power"] = power_form(pk, torch, dev, inst, packed, max(5, args.steps // 4))
+    out["overlap_form"] = overlap_form(pk, torch, dev, inst, ring, max(8, args.steps // 2))
+    out["table1_modes"] = modes_form(pk, torch, dev, max(8, args.steps // 2), args.ring)
     if not args.no_batching:
         out["batching_form"] = batching_form(pk, torch, dev, max(3, args.steps // 10))
     if not args.no_precision:

@@ -49,8 +49,8 @@ typedef enum {
   PS_ERR_HIP = 6           /* a HIP runtime call or kernel launch failed */
 } ps_status;
 
-/* window kinds (Sec. 3.1: rectangular online; others are applied as apodisation) */
-enum { PS_WIN_RECT = 0, PS_WIN_HANN = 1, PS_WIN_TAPS = 2 };
+/* window kinds (Sec. 3.1: rectangular online; Hanning, Hamming and Blackman as apodisation), periodic forms */
+enum { PS_WIN_RECT = 0, PS_WIN_HANN = 1, PS_WIN_TAPS = 2, PS_WIN_HAMMING = 3, PS_WIN_BLACKMAN = 4 };
 /* arithmetic of the transform passes */
 enum { PS_PREC_FP32 = 0, PS_PREC_FP16 = 1, PS_PREC_BF16 = 2 };
 /* accumulator of the integration */
@@ -66,10 +66,12 @@ typedef struct ps_plan_s* ps_plan_t;
  *               32 (little-endian float32, a test format).  Item t*S + s of the buffer sits at bit
  *               offset (t*S + s)*bits, least significant bits first.
  *   fft_len     N, a power of two, 2^8 .. 2^22; channels C = N/2; one segment = N samples per stream.
- *   window      PS_WIN_RECT, PS_WIN_HANN (periodic) or PS_WIN_TAPS (n_taps control points, linear
- *               interpolation at u = n (n_taps - 1)/(N - 1); all ones until ps_set_window_taps).
+ *   window      PS_WIN_RECT; PS_WIN_HANN (0.5 - 0.5 cos 2 pi n/N), PS_WIN_HAMMING (0.54 - 0.46 cos) or
+ *               PS_WIN_BLACKMAN (0.42 - 0.5 cos + 0.08 cos 4 pi n/N), all periodic; or PS_WIN_TAPS (n_taps
+ *               control points, linear interpolation at u = n (n_taps - 1)/(N - 1); all ones until
+ *               ps_set_window_taps).
  *   precision   PS_PREC_FP32: FP32 transforms.  PS_PREC_FP16 / PS_PREC_BF16 (the precision form,
- *               fft_len 2^16 .. 2^18, rect or Hann window): each pass as 16 x R blocked DFT matrix
+ *               fft_len 2^16 .. 2^18, any window but PS_WIN_TAPS): each pass as 16 x R blocked DFT matrix
  *               products on the matrix cores with 16-bit inputs and FP32 accumulation, a 16-bit
  *               inter-pass buffer; every stage is scaled by 1/radix (exact), so FP16 values stay within
  *               the input range (|level| < 65504).
@@ -78,6 +80,12 @@ typedef struct ps_plan_s* ps_plan_t;
  *               compensated FP32, then added to FP64 accumulators.
  *   chunk_frames  frames processed per internal pass pair (0 = max(64, 2^22 / N)); bounds the workspace.
  *   sample_rate_hz  metadata only (channel width = sample_rate_hz / N).
+ *   hop         segmentation (Sec. 3.1, 50 % overlap): frame f of the stream starts at sample f * hop;
+ *               0 or N = contiguous frames, N/2 = 50 % overlap, N/4 or N/8 = 75 or 87.5 %.  An integration
+ *               of T samples (in any number of ps_accumulate calls) has (T - N)/hop + 1 frames; the
+ *               last N - hop samples of each call are kept in the workspace and transformed with the next
+ *               call's first samples.  With level histograms on, every sample is counted once (the first
+ *               hop samples of each frame).
  */
 typedef struct {
   int32_t n_streams;
@@ -92,6 +100,7 @@ typedef struct {
   int32_t chunk_frames;
   int64_t fft_len;
   double sample_rate_hz;
+  int64_t hop;
 } ps_instance;
 
 /*
@@ -227,7 +236,9 @@ ps_status ps_graph_launch(ps_plan_t plan);
 ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed_dev, int64_t n_samples,
                                 const ps_cal* cal, const float* dL_diquv_dev, const ps_cal_grad* grad);
 
-/* Integration state (accumulators; the frame count is kept by the plan) for checkpoint and resume. */
+/* Integration state for checkpoint and resume: the accumulators and, for overlapped segmentation, the
+ * samples waiting for the next call (the frame count is passed separately).  Device buffers of
+ * ps_state_bytes bytes; export and import are enqueued on the plan's stream. */
 ps_status ps_state_bytes(ps_plan_t plan, int32_t inst, size_t* bytes);
 ps_status ps_state_export(ps_plan_t plan, int32_t inst, void* dst_dev, int64_t* n_frames);
 ps_status ps_state_import(ps_plan_t plan, int32_t inst, const void* src_dev, int64_t n_frames);

@@ -15,7 +15,7 @@ __all__ = ["PolarisError", "Instance", "Plan", "unpack", "lib", "LIB_PATH", "WIN
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpolaris.so")
 
-WIN = {"rect": 0, "hann": 1, "taps": 2}
+WIN = {"rect": 0, "hann": 1, "taps": 2, "hamming": 3, "blackman": 4}
 PREC = {"fp32": 0, "fp16": 1, "bf16": 2}
 ACC = {"fp64": 0, "kahan32": 1}
 
@@ -34,7 +34,7 @@ class _Instance(C.Structure):
     _fields_ = [("n_streams", C.c_int32), ("n_pairs", C.c_int32), ("pair_x", C.c_int32 * 4),
                 ("pair_y", C.c_int32 * 4), ("bits", C.c_int32), ("window", C.c_int32), ("n_taps", C.c_int32),
                 ("precision", C.c_int32), ("accum", C.c_int32), ("chunk_frames", C.c_int32),
-                ("fft_len", C.c_int64), ("sample_rate_hz", C.c_double)]
+                ("fft_len", C.c_int64), ("sample_rate_hz", C.c_double), ("hop", C.c_int64)]
 
 
 class _Cal(C.Structure):
@@ -153,6 +153,7 @@ class Instance:
     accum: str = "fp64"
     chunk_frames: int = 0
     sample_rate_hz: float = 16e6
+    hop: int = 0  # samples between frame starts: 0 or fft_len (contiguous), fft_len / 2 (50 % overlap), / 4, / 8
 
     def to_c(self) -> _Instance:
         s = _Instance()
@@ -169,6 +170,7 @@ class Instance:
         s.chunk_frames = self.chunk_frames
         s.fft_len = self.fft_len
         s.sample_rate_hz = self.sample_rate_hz
+        s.hop = self.hop
         return s
 
     @property
@@ -182,7 +184,7 @@ class Instance:
     @staticmethod
     def from_synth(d: dict, **over) -> "Instance":
         kw = dict(fft_len=d["fft_len"], bits=d["bits"], n_streams=d["n_streams"], pairs=tuple(d["pairs"]),
-                  window=d["window"], n_taps=64 if d["window"] == "taps" else 0)
+                  window=d["window"], n_taps=64 if d["window"] == "taps" else 0, hop=d.get("hop", 0))
         kw.update(over)
         return Instance(**kw)
 

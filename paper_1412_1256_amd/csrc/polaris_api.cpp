@@ -63,7 +63,7 @@ struct Inst {
   ps_instance cfg{};
   int m = 0, m1 = 0, m2 = 0;
   int64_t N = 0, C = 0, N1 = 0, N2 = 0, chunk = 0;
-  bool fast = false;
+  int load_mode = 0;  // column-pass loader: 0 decode at use, 1 two-stream words, 2 four-stream words
   size_t off_tw_col = 0, off_tw_row = 0, off_tw_lo = 0, off_win = 0, off_taps = 0, off_sumw2 = 0;
   size_t off_T = 0, off_acc = 0, end = 0;
   // differentiation form: window partial sums, Gb(A), per-unit partials, normaliser terms, partial dL/dw
@@ -88,6 +88,14 @@ struct Inst {
   double sumw2 = 0.0;
   bool first = true;
   int64_t n_frames = 0;
+  // segmentation: frame f at sample f * hop; with overlap the last N - hop samples of a call wait in the
+  // first half of the staging buffer [2][N - hop samples]
+  int64_t hop = 0;
+  size_t off_stage = 0;
+  bool overlap() const { return hop < N; }
+  int64_t bits_per_sample() const { return (int64_t)cfg.n_streams * cfg.bits; }
+  size_t tail_bytes() const { return (size_t)((N - hop) * bits_per_sample() / 8); }
+  int64_t frames_in(int64_t T) const { return T < N ? 0 : (T - N) / hop + 1; }
   size_t slot_doubles() const { return (size_t)cfg.n_pairs * (size_t)(N1 / 2) * 4 * (size_t)N2; }
   size_t acc_bytes() const { return (size_t)G * slot_doubles() * sizeof(double); }
   int slots_used() const { return (int)std::min<int64_t>(G, n_frames); }
@@ -147,8 +155,11 @@ ps_status validate_instance(const ps_instance& c, int idx) {
   if (m < 0) return fail(PS_ERR_ARG, "instance %d: fft_len %lld is not a power of two", idx, (long long)c.fft_len);
   if (m < 8 || m > 22)
     return fail(PS_ERR_UNSUPPORTED, "instance %d: fft_len 2^%d outside the supported 2^8 .. 2^22", idx, m);
-  if (c.window != PS_WIN_RECT && c.window != PS_WIN_HANN && c.window != PS_WIN_TAPS)
+  if (c.window != PS_WIN_RECT && c.window != PS_WIN_HANN && c.window != PS_WIN_TAPS && c.window != PS_WIN_HAMMING &&
+      c.window != PS_WIN_BLACKMAN)
     return fail(PS_ERR_ARG, "instance %d: unknown window %d", idx, c.window);
+  if (c.hop != 0 && c.hop != c.fft_len && c.hop != c.fft_len / 2 && c.hop != c.fft_len / 4 && c.hop != c.fft_len / 8)
+    return fail(PS_ERR_ARG, "instance %d: hop %lld is not 0, fft_len, fft_len/2, /4 or /8", idx, (long long)c.hop);
   if (c.window == PS_WIN_TAPS && (c.n_taps < 2 || c.n_taps > 4096))
     return fail(PS_ERR_ARG, "instance %d: n_taps %d not in 2..4096", idx, c.n_taps);
   if (c.precision != PS_PREC_FP32 && c.precision != PS_PREC_FP16 && c.precision != PS_PREC_BF16)
@@ -250,10 +261,15 @@ void build_tables(Inst& I) {
   twiddle_table(I.tw_lo, I.N, I.N2);  // W_N^m, m < N2; W_N^(q*N2) = W_N1^q reuses tw_col
   I.win.clear();
   double s = 0.0;
-  if (I.cfg.window == PS_WIN_HANN) {
+  if (I.cfg.window == PS_WIN_HANN || I.cfg.window == PS_WIN_HAMMING || I.cfg.window == PS_WIN_BLACKMAN) {
+    // periodic cosine-sum windows a0 - a1 cos(2 pi n/N) + a2 cos(4 pi n/N), evaluated in FP64
+    double a0 = 0.5, a1 = 0.5, a2 = 0.0;
+    if (I.cfg.window == PS_WIN_HAMMING) a0 = 0.54, a1 = 0.46;
+    if (I.cfg.window == PS_WIN_BLACKMAN) a0 = 0.42, a1 = 0.5, a2 = 0.08;
     I.win.resize((size_t)I.N);
     for (int64_t n = 0; n < I.N; ++n) {
-      const double w = 0.5 - 0.5 * std::cos(kTwoPi * (double)n / (double)I.N);
+      const double ph = kTwoPi * (double)n / (double)I.N;
+      const double w = a0 - a1 * std::cos(ph) + a2 * std::cos(2.0 * ph);
       I.win[(size_t)n] = (float)w;
       s += w * w;
     }
@@ -360,16 +376,17 @@ const char* schedule_error(const ps_instance& c, const ps_schedule& s, char* why
 }
 
 // Column-pass arguments of frames f0 .. f0+nf-1 of instance I.  groups: frame groups of the tile grid (0:
-// as many as make the tiles about one per CU).  *fast: the int8 two-stream path (32-bit input offsets).
+// as many as make the tiles about one per CU).  *mode: the column-pass loader mode of this launch.
 ps::ColArgs col_args(ps_plan_t plan, const Inst& I, const uint8_t* base, int64_t f0, int nf, int64_t groups,
-                     bool* fast) {
-  const int64_t frame_bytes = I.N * I.cfg.n_streams * I.cfg.bits / 8;
+                     int* mode) {
   ps::ColArgs ca{};
-  ca.in = base + f0 * frame_bytes;
-  const int64_t in_bytes = (int64_t)nf * frame_bytes;
+  ca.in = base + f0 * I.hop * I.bits_per_sample() / 8;
+  const int64_t in_bytes = ((int64_t)(nf - 1) * I.hop + I.N) * I.bits_per_sample() / 8;
   ca.in_bytes = in_bytes < (int64_t(1) << 31) ? (uint32_t)in_bytes : 0u;
-  *fast = I.fast && in_bytes < (int64_t(1) << 31) && I.N * 8 < (int64_t(1) << 31);
+  *mode = in_bytes < (int64_t(1) << 31) && I.N * 8 < (int64_t(1) << 31) ? I.load_mode : 0;
   ca.N = I.N;
+  ca.hop = I.hop;
+  ca.hist_rows = (int32_t)(I.hop / I.N2);
   ca.N2 = (int32_t)I.N2;
   ca.S = I.cfg.n_streams;
   ca.P = I.cfg.n_pairs;
@@ -452,7 +469,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
   for (size_t i = 0; i < plan->inst.size(); ++i) {
     const Inst& I = plan->inst[i];
     if (I.mx() || I.hist_on) continue;
-    const int64_t F = n_samples[i] / I.N;
+    const int64_t F = I.frames_in(n_samples[i]);
     rounds = std::max(rounds, (F + I.chunk - 1) / I.chunk);
   }
   if (rounds == 0 || rounds > (int64_t)kMaxRounds) return PS_OK;  // nothing to group, or too many chunks
@@ -461,7 +478,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
   std::vector<int32_t> cend, rend;
   struct L1 {
     int kind, len, bits;
-    bool fast;
+    int mode;  // column-pass loader mode
     int var;  // columns per workgroup (column pass) or frames per batch (row pass)
     size_t task0, n;
     int total;
@@ -481,14 +498,14 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
     for (size_t i = 0; i < plan->inst.size(); ++i) {
       const Inst& I = plan->inst[i];
       if (I.mx() || I.hist_on) continue;
-      const int64_t F = n_samples[i] / I.N, f0 = r * I.chunk;
+      const int64_t F = I.frames_in(n_samples[i]), f0 = r * I.chunk;
       if (f0 >= F) continue;
       const int nf = (int)std::min<int64_t>(I.chunk, F - f0);
-      bool fast = false;
+      int mode = 0;
       // the instance's own frame grouping: long transforms keep long frame groups per tile
-      const ps::ColArgs ca = col_args(plan, I, static_cast<const uint8_t*>(packed_dev[i]), f0, nf, 0, &fast);
+      const ps::ColArgs ca = col_args(plan, I, static_cast<const uint8_t*>(packed_dev[i]), f0, nf, 0, &mode);
       const ps::RowArgs ra = row_args(plan, I, nf, I.n_frames + f0);
-      const std::vector<int> key = {(int)I.N1, (int)I.N2, I.cfg.bits, fast ? 1 : 0, I.cols, I.fb};
+      const std::vector<int> key = {(int)I.N1, (int)I.N2, I.cfg.bits, mode, I.cols, I.fb};
       auto it = std::find_if(classes.begin(), classes.end(), [&](const auto& c) { return c.first == key; });
       if (it == classes.end()) {
         classes.push_back({key, {}});
@@ -503,8 +520,8 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
         size_t e = m;
         int64_t bytes = 0;
         while (e < c.second.size() && (e == m || bytes + c.second[e].t_bytes <= kBatchT)) bytes += c.second[e++].t_bytes;
-        L1 lc{0, key[0], key[2], key[3] != 0, key[4], cols.size(), e - m, 0};
-        L1 lr{1, key[1], 0, false, key[5], rows.size(), e - m, 0};
+        L1 lc{0, key[0], key[2], key[3], key[4], cols.size(), e - m, 0};
+        L1 lr{1, key[1], 0, 0, key[5], rows.size(), e - m, 0};
         int ct = 0, rt = 0;
         for (size_t q = m; q < e; ++q) {
           cols.push_back(c.second[q].ca);
@@ -543,7 +560,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
     if (l.kind == 0) {
       b.tasks = dev + l.task0 * sizeof(ps::ColArgs);
       b.tile_end = reinterpret_cast<const int32_t*>(dev + cend_at) + l.task0;
-      e = timed(plan, PS_KERNEL_COLPASS, [&](const ps::Launch& x) { return ps::launch_colpass_batch(l.len, l.var, l.bits, l.fast, b, x); });
+      e = timed(plan, PS_KERNEL_COLPASS, [&](const ps::Launch& x) { return ps::launch_colpass_batch(l.len, l.var, l.bits, l.mode, b, x); });
     } else {
       b.tasks = dev + rows_at + l.task0 * sizeof(ps::RowArgs);
       b.tile_end = reinterpret_cast<const int32_t*>(dev + rend_at) + l.task0;
@@ -555,7 +572,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
     Inst& I = plan->inst[i];
     if (I.mx() || I.hist_on) continue;
     done[i] = 1;
-    const int64_t F = n_samples[i] / I.N;
+    const int64_t F = I.frames_in(n_samples[i]);
     if (F > 0) {
       I.first = false;
       I.n_frames += F;
@@ -606,6 +623,52 @@ ps_status accumulate_mx(ps_plan_t plan, Inst& I, const ps::ColArgs& ca) {
     return ps::launch_rowpass_mx((int)I.N2, c.precision, c.accum, r, l);
   });
   if (e != hipSuccess) return hip_fail(e, "16-bit row pass launch");
+  return PS_OK;
+}
+
+// Frames 0 .. F-1 of the buffer at base (frame f at sample f * hop) in chunks of the instance's chunk size:
+// the column and row passes (or their 16-bit forms) of each chunk, frames in order.
+ps_status run_frames(ps_plan_t plan, Inst& I, const uint8_t* base, int64_t F) {
+  for (int64_t f0 = 0; f0 < F; f0 += I.chunk) {
+    const int nf = (int)((F - f0) < I.chunk ? (F - f0) : I.chunk);
+    int mode = 0;
+    // one workgroup per CU: each loops over a group of frames, so that groups x pairs x blocks ~ CUs
+    const ps::ColArgs ca = col_args(plan, I, base, f0, nf, 0, &mode);
+    if (I.mx()) {
+      ps_status ms = accumulate_mx(plan, I, ca);
+      if (ms != PS_OK) return ms;
+      I.first = false;
+      I.n_frames += nf;
+      continue;
+    }
+    hipError_t e = timed(plan, PS_KERNEL_COLPASS,
+                         [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cols, I.cfg.bits, mode, ca, l); });
+    if (e != hipSuccess) return hip_fail(e, "column pass launch");
+    const ps::RowArgs ra = row_args(plan, I, nf, I.n_frames);
+    e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& l) { return ps::launch_rowpass((int)I.N2, I.fb, ra, l); });
+    if (e != hipSuccess) return hip_fail(e, "row pass launch");
+    I.first = false;
+    I.n_frames += nf;
+  }
+  return PS_OK;
+}
+
+// Overlapped segmentation across calls (T samples in this one).  The previous call's last N - hop samples
+// wait in the first half of the staging buffer; this call's first N - hop samples are copied behind them,
+// and the (N - hop) / hop frames that start in the waiting samples are transformed from there.  Then this
+// call's last N - hop samples take the first half.  Stream order keeps the copies and passes apart.
+ps_status overlap_frames(ps_plan_t plan, Inst& I, const uint8_t* base, int64_t T) {
+  uint8_t* stage = ws_ptr<uint8_t>(plan, I.off_stage);
+  const size_t half = I.tail_bytes();
+  if (I.n_frames > 0) {
+    hipError_t e = ps::launch_copy(base, stage + half, half, plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "overlap staging copy");
+    ps_status st = run_frames(plan, I, stage, (I.N - I.hop) / I.hop);
+    if (st != PS_OK) return st;
+  }
+  const size_t call_bytes = (size_t)(T * I.bits_per_sample() / 8);
+  hipError_t e = ps::launch_copy(base + call_bytes - half, stage, half, plan->stream);
+  if (e != hipSuccess) return hip_fail(e, "overlap tail copy");
   return PS_OK;
 }
 
@@ -672,15 +735,20 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
     I.N1 = int64_t(1) << I.m1;
     I.N2 = int64_t(1) << I.m2;
     I.C = I.N / 2;
+    I.hop = inst[i].hop ? inst[i].hop : I.N;
     I.cols = (sched && sched[i].colpass_cols) ? sched[i].colpass_cols : ps::colpass_cols((int)I.N1);
     I.fb = (sched && sched[i].rowpass_frames) ? sched[i].rowpass_frames : ps::rowpass_frames((int)I.N2);
     I.col_wgs = (sched && sched[i].col_wg_per_cu) ? sched[i].col_wg_per_cu : 1;
     I.G = (sched && sched[i].rowpass_slots) ? sched[i].rowpass_slots : default_slots(I.cfg, (int)I.N1, (int)I.N2);
     // short transforms take more frames per pass (inter-pass buffer of at most 32 MiB per pair)
     I.chunk = inst[i].chunk_frames ? inst[i].chunk_frames : (int64_t)std::max<int64_t>(64, (int64_t(1) << 22) / I.N);
-    // word loads of the column pass: 2-, 4- and 8-bit codes of two streams correlated as (0, 1)
-    I.fast = inst[i].bits <= 8 && inst[i].n_streams == 2 && inst[i].n_pairs == 1 && inst[i].pair_x[0] == 0 &&
-             inst[i].pair_y[0] == 1;
+    // word loads of the column pass: 2-, 4- and 8-bit codes of two streams correlated as (0, 1), or of four
+    // streams (any pairs)
+    if (inst[i].bits <= 8 && inst[i].n_streams == 2 && inst[i].n_pairs == 1 && inst[i].pair_x[0] == 0 &&
+        inst[i].pair_y[0] == 1)
+      I.load_mode = 1;
+    else if (inst[i].bits <= 8 && inst[i].n_streams == 4)
+      I.load_mode = 2;
     build_tables(I);
     I.off_tw_col = off; off = align_up(off + (size_t)I.N1 * 8);
     I.off_tw_row = off; off = align_up(off + (size_t)I.N2 * 8);
@@ -695,6 +763,7 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
       I.off_tws_row = off; off = align_up(off + I.tws_row.size() * 4);
     }
     I.off_hist = off; off = align_up(off + (size_t)I.cfg.n_pairs * 2 * (size_t)I.hist_bins() * 8);
+    I.off_stage = off; off = align_up(off + 2 * I.tail_bytes());
     I.off_T = off; off = align_up(off + (size_t)I.chunk * (size_t)I.cfg.n_pairs * (size_t)I.N * 8);
     I.off_acc = off; off = align_up(off + I.acc_bytes());
     const size_t U = (size_t)(I.N1 / 2), P = (size_t)I.cfg.n_pairs;
@@ -816,6 +885,26 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
     if (n_samples[i] > 0 && !packed_dev[i]) return fail(PS_ERR_ARG, "instance %zu: null packed buffer", i);
     if (n_samples[i] / I.N > (int64_t(1) << 40)) return fail(PS_ERR_SIZE, "instance %zu: too many frames", i);
   }
+  // First, per instance: the histogram clear and, with overlapped frames, the frames that span the
+  // previous call and this one (they precede this call's own frames in the integration).
+  for (size_t i = 0; i < plan->inst.size(); ++i) {
+    Inst& I = plan->inst[i];
+    const int64_t T = n_samples[i];
+    if (T == 0) continue;
+    if (I.hist_on) {
+      if (!I.hist_zeroed) {
+        hipError_t e = ps::launch_zero_u64(ws_ptr<unsigned long long>(plan, I.off_hist),
+                                           (int64_t)I.cfg.n_pairs * 2 * I.hist_bins(), plan->stream);
+        if (e != hipSuccess) return hip_fail(e, "histogram clear");
+        I.hist_zeroed = true;
+      }
+      I.hist_frames += I.frames_in(T) + (I.overlap() && I.n_frames > 0 ? (I.N - I.hop) / I.hop : 0);
+    }
+    if (I.overlap()) {
+      st = overlap_frames(plan, I, static_cast<const uint8_t*>(packed_dev[i]), T);
+      if (st != PS_OK) return st;
+    }
+  }
   std::vector<char> done(plan->inst.size(), 0);
   if (plan->inst.size() > 1) {
     st = accumulate_grouped(plan, packed_dev, n_samples, done);
@@ -824,38 +913,8 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
   for (size_t i = 0; i < plan->inst.size(); ++i) {
     if (done[i]) continue;
     Inst& I = plan->inst[i];
-    const int64_t F = n_samples[i] / I.N;
-    if (I.hist_on && F > 0) {
-      if (!I.hist_zeroed) {
-        hipError_t e = ps::launch_zero_u64(ws_ptr<unsigned long long>(plan, I.off_hist),
-                                           (int64_t)I.cfg.n_pairs * 2 * I.hist_bins(), plan->stream);
-        if (e != hipSuccess) return hip_fail(e, "histogram clear");
-        I.hist_zeroed = true;
-      }
-      I.hist_frames += F;
-    }
-    const uint8_t* base = static_cast<const uint8_t*>(packed_dev[i]);
-    for (int64_t f0 = 0; f0 < F; f0 += I.chunk) {
-      const int nf = (int)((F - f0) < I.chunk ? (F - f0) : I.chunk);
-      bool fast = false;
-      // one workgroup per CU: each loops over a group of frames, so that groups x pairs x blocks ~ CUs
-      const ps::ColArgs ca = col_args(plan, I, base, f0, nf, 0, &fast);
-      if (I.mx()) {
-        ps_status ms = accumulate_mx(plan, I, ca);
-        if (ms != PS_OK) return ms;
-        I.first = false;
-        I.n_frames += nf;
-        continue;
-      }
-      hipError_t e = timed(plan, PS_KERNEL_COLPASS,
-                           [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cols, I.cfg.bits, fast, ca, l); });
-      if (e != hipSuccess) return hip_fail(e, "column pass launch");
-      const ps::RowArgs ra = row_args(plan, I, nf, I.n_frames);
-      e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& l) { return ps::launch_rowpass((int)I.N2, I.fb, ra, l); });
-      if (e != hipSuccess) return hip_fail(e, "row pass launch");
-      I.first = false;
-      I.n_frames += nf;
-    }
+    st = run_frames(plan, I, static_cast<const uint8_t*>(packed_dev[i]), I.frames_in(n_samples[i]));
+    if (st != PS_OK) return st;
   }
   return PS_OK;
 }
@@ -1071,9 +1130,9 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
     if (I.N2 > 512) return fail(PS_ERR_UNSUPPORTED, "the window adjoint is built for fft_len <= 2^18");
     if (!packed_dev) return fail(PS_ERR_ARG, "null packed input");
     if (n_samples < 0 || n_samples % I.N) return fail(PS_ERR_SIZE, "n_samples is not a multiple of fft_len");
-    if (n_samples / I.N != I.n_frames)
+    if (I.frames_in(n_samples) != I.n_frames)
       return fail(PS_ERR_STATE, "the input has %lld frames but the integration has %lld",
-                  (long long)(n_samples / I.N), (long long)I.n_frames);
+                  (long long)I.frames_in(n_samples), (long long)I.n_frames);
   }
   if (I.N2 > 512) return fail(PS_ERR_UNSUPPORTED, "the adjoint is built for fft_len <= 2^18");
   ps::BwChanArgs ca{};
@@ -1105,17 +1164,18 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
   if (!want_taps) return PS_OK;
 
   const int64_t F = I.n_frames;
-  const int64_t frame_bytes = I.N * I.cfg.n_streams * I.cfg.bits / 8;
   const uint8_t* base = static_cast<const uint8_t*>(packed_dev);
   int groups_used = 0;
   for (int64_t f0 = 0; f0 < F; f0 += I.chunk) {
     const int nf = (int)((F - f0) < I.chunk ? (F - f0) : I.chunk);
     ps::ColArgs col{};
-    col.in = base + f0 * frame_bytes;
-    const int64_t in_bytes = (int64_t)nf * frame_bytes;
+    col.in = base + f0 * I.hop * I.bits_per_sample() / 8;
+    const int64_t in_bytes = ((int64_t)(nf - 1) * I.hop + I.N) * I.bits_per_sample() / 8;
     col.in_bytes = in_bytes < (int64_t(1) << 31) ? (uint32_t)in_bytes : 0u;
-    const bool fast = I.fast && in_bytes < (int64_t(1) << 31);
+    const int mode = in_bytes < (int64_t(1) << 31) ? I.load_mode : 0;
+    const bool fast = mode == 1;  // the backward's own column pass has the int8 two-stream word loader
     col.N = I.N;
+    col.hop = I.hop;
     col.N2 = (int32_t)I.N2;
     col.S = I.cfg.n_streams;
     col.P = I.cfg.n_pairs;
@@ -1138,7 +1198,7 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
     col.tw_lo = ws_ptr<float2>(plan, I.off_tw_lo);
     col.lo_bits = I.m2;
     col.T = ws_ptr<float2>(plan, I.off_T);
-    e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, ps::colpass_cols((int)I.N1), I.cfg.bits, fast, col, l); });
+    e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, ps::colpass_cols((int)I.N1), I.cfg.bits, mode, col, l); });
     if (e != hipSuccess) return hip_fail(e, "backward forward-recompute launch");
     ps::BwRowArgs ra{};
     ra.T = col.T;
@@ -1192,7 +1252,8 @@ ps_status ps_state_bytes(ps_plan_t plan, int32_t inst, size_t* bytes) {
   if (st != PS_OK) return st;
   if ((st = check_inst(plan, inst)) != PS_OK) return st;
   if (!bytes) return fail(PS_ERR_ARG, "null bytes");
-  *bytes = plan->inst[(size_t)inst].acc_bytes();
+  const Inst& I = plan->inst[(size_t)inst];
+  *bytes = I.acc_bytes() + (I.overlap() ? I.tail_bytes() : 0);
   return PS_OK;
 }
 
@@ -1204,6 +1265,8 @@ ps_status ps_state_export(ps_plan_t plan, int32_t inst, void* dst_dev, int64_t* 
   if (!dst_dev) return fail(PS_ERR_ARG, "null destination");
   if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %d has no accumulated frames", inst);
   hipError_t e = ps::launch_copy(plan->ws + I.off_acc, dst_dev, I.acc_bytes(), plan->stream);
+  if (e == hipSuccess && I.overlap())
+    e = ps::launch_copy(plan->ws + I.off_stage, static_cast<char*>(dst_dev) + I.acc_bytes(), I.tail_bytes(), plan->stream);
   if (e != hipSuccess) return hip_fail(e, "state export");
   if (n_frames) *n_frames = I.n_frames;
   return PS_OK;
@@ -1217,6 +1280,8 @@ ps_status ps_state_import(ps_plan_t plan, int32_t inst, const void* src_dev, int
   if (!src_dev) return fail(PS_ERR_ARG, "null source");
   if (n_frames <= 0) return fail(PS_ERR_ARG, "n_frames must be positive");
   hipError_t e = ps::launch_copy(src_dev, plan->ws + I.off_acc, I.acc_bytes(), plan->stream);
+  if (e == hipSuccess && I.overlap())
+    e = ps::launch_copy(static_cast<const char*>(src_dev) + I.acc_bytes(), plan->ws + I.off_stage, I.tail_bytes(), plan->stream);
   if (e != hipSuccess) return hip_fail(e, "state import");
   I.n_frames = n_frames;
   I.first = false;

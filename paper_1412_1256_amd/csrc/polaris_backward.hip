@@ -364,7 +364,7 @@ __global__ void __launch_bounds__(L * COLS / 16) k_bw_colpass(BwColArgs a) {
     if constexpr (NB == 2 && (SC::NPASS - 1) % 2 == 1) __syncthreads();
     // samples x, y at n = (ts + r L/8) N2 + n2b + c
     ColLoader<BITS, FAST, V> ld;
-    ld.template fetch<L, 8>(a.col, (int64_t)f * a.col.N, ts, n2b);
+    ld.template fetch<L, 8>(a.col, (int64_t)f * a.col.hop, ts, n2b);
     float2 xs[V][8];
     ld.template convert<L, 8>(xs, a.col, ts, n2b, sx, sy);
 #pragma unroll

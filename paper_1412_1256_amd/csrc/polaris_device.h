@@ -152,21 +152,6 @@ __device__ __forceinline__ float level_of(const uint8_t* __restrict__ in, int64_
   }
 }
 
-// two adjacent samples t, t+1 (t even) of streams sx (real part) and sy (imaginary part)
-template <int BITS, bool FAST>
-__device__ __forceinline__ void load_pair2(const uint8_t* __restrict__ in, int S, int sx, int sy, int64_t t,
-                                           float2& z0, float2& z1) {
-  if constexpr (FAST) {  // 8-bit, two streams, pair (0, 1): x0 y0 x1 y1 in one aligned 32-bit word
-    const uint32_t w = *reinterpret_cast<const uint32_t*>(in + 2 * t);
-    z0 = make_float2((float)(int)(int8_t)(w & 0xffu), (float)(int)(int8_t)((w >> 8) & 0xffu));
-    z1 = make_float2((float)(int)(int8_t)((w >> 16) & 0xffu), (float)(int)(int8_t)(w >> 24));
-  } else {
-    const int64_t i0 = t * S, i1 = (t + 1) * S;
-    z0 = make_float2(level_of<BITS>(in, i0 + sx), level_of<BITS>(in, i0 + sy));
-    z1 = make_float2(level_of<BITS>(in, i1 + sx), level_of<BITS>(in, i1 + sy));
-  }
-}
-
 // ------------------------------------------------------------------------------------------------
 // per-thread pass twiddles.  A thread keeps the same slot ts for every frame it transforms, so the
 // twiddles of its passes are loaded once into registers: pass p >= 1 is radix 8 with one task per thread,
@@ -213,9 +198,9 @@ __device__ __forceinline__ int swz(int e) {
 // current one is transformed.  Each thread owns V adjacent columns (8 points of each).
 // ------------------------------------------------------------------------------------------------
 
-// Input of 8 rows x V adjacent columns of one thread.  The int8 two-stream path fetches the next frame's
-// raw words ahead of use; the other formats decode at use.
-template <int BITS, bool FAST, int V>
+// Input of 8 rows x V adjacent columns of one thread.  Loader modes: 0 decodes every code at use; 1 (two
+// streams, pair (0, 1)) and 2 (four streams) fetch the next frame's raw words ahead of use.
+template <int BITS, int FAST, int V>
 struct ColLoader {
   int64_t fbase;
   template <int L, int R0>
@@ -237,74 +222,79 @@ struct ColLoader {
   }
 };
 
-// Two streams, pair (0, 1), 2-, 4- or 8-bit codes: sample t of the pair is the 2*BITS-bit field x_t y_t at
-// bit offset 2*BITS*t, so the V = 2 adjacent columns (t even) of a row are one byte (2-bit), one 16-bit word
-// (4-bit) or one 32-bit word (8-bit), fetched ahead of use.
+// NS = 2 or 4 interleaved streams of 2-, 4- or 8-bit codes: time sample t is the NS*BITS-bit field at bit
+// offset NS*BITS*t, so the V adjacent columns (t a multiple of V) of a row are one word of V*NS*BITS bits
+// (8 to 64), fetched ahead of use.  Two streams form the pair (0, 1); of four, the pair's streams sx, sy are
+// picked from the word by shifts.
 // input words are read once: stream them past the caches (keeps the last-level cache for the
 // intermediate buffer; about 4 % faster with input streamed from HBM)
 #ifndef PS_INPUT_NONTEMPORAL
 #define PS_INPUT_NONTEMPORAL 1
 #endif
 
-template <int BITS, int V>
+template <int BITS, int V, int NS>
 struct ColLoaderWords {
   static_assert(BITS == 2 || BITS == 4 || BITS == 8, "word loader formats");
-  static_assert(BITS == 8 || V == 2, "2- and 4-bit words hold two columns");
-  uint32_t raw[8];  // the row's V x (x, y) codes
+  static_assert(NS == 2 || NS == 4, "two or four streams");
+  static constexpr int WBITS = V * NS * BITS;  // bits of one row's word
+  static_assert(WBITS >= 8 && WBITS <= 64, "one load per row");
+  using word = typename std::conditional<(WBITS > 32), uint64_t, uint32_t>::type;
+  word raw[8];  // the row's V x NS codes
+  template <class T>
+  static __device__ __forceinline__ word load(gbytes p) {
+#if PS_INPUT_NONTEMPORAL
+    // read once: streamed past the caches
+    return (word)__builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
+#else
+    return (word)*(const __attribute__((address_space(1))) T*)p;
+#endif
+  }
   template <int L, int R0>
   __device__ __forceinline__ void fetch(const ColArgs& a, int64_t fb, int ts, int n2b) {
     // row n1 = ts + i L/8 + r L/R0 of frame fb / N: a wave-uniform 64-bit base per (frame, i, r) plus a
-    // 32-bit per-lane offset (the global_load scalar-base form); byte offset of sample t: t BITS / 4
-    const uint32_t voff = (uint32_t)(ts * a.N2 + n2b) * BITS / 4u;
+    // 32-bit per-lane offset (the global_load scalar-base form); byte offset of sample t: t NS BITS / 8
+    const uint32_t voff = (uint32_t)(ts * a.N2 + n2b) * (NS * BITS) / 8u;
 #pragma unroll
     for (int i = 0; i < 8 / R0; ++i)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
         const int64_t t0 = fb + (int64_t)a.N2 * (i * (L / 8) + r * (L / R0));
-        const gbytes base = uniform_gptr(a.in + t0 * BITS / 4);
-#if PS_INPUT_NONTEMPORAL
-        // read once: streamed past the caches
-        if constexpr (BITS == 8 && V == 2)
-          raw[i * R0 + r] = __builtin_nontemporal_load((const __attribute__((address_space(1))) uint32_t*)(base + voff));
-        else if constexpr (BITS == 8 || BITS == 4)
-          raw[i * R0 + r] = __builtin_nontemporal_load((const __attribute__((address_space(1))) uint16_t*)(base + voff));
-        else
-          raw[i * R0 + r] = __builtin_nontemporal_load((const __attribute__((address_space(1))) uint8_t*)(base + voff));
-#else
-        if constexpr (BITS == 8 && V == 2)
-          raw[i * R0 + r] = *(const __attribute__((address_space(1))) uint32_t*)(base + voff);
-        else if constexpr (BITS == 8 || BITS == 4)
-          raw[i * R0 + r] = *(const __attribute__((address_space(1))) uint16_t*)(base + voff);
-        else
-          raw[i * R0 + r] = *(const __attribute__((address_space(1))) uint8_t*)(base + voff);
-#endif
+        const gbytes p = uniform_gptr(a.in + t0 * (NS * BITS) / 8) + voff;
+        if constexpr (WBITS == 64) raw[i * R0 + r] = load<uint64_t>(p);
+        else if constexpr (WBITS == 32) raw[i * R0 + r] = load<uint32_t>(p);
+        else if constexpr (WBITS == 16) raw[i * R0 + r] = load<uint16_t>(p);
+        else raw[i * R0 + r] = load<uint8_t>(p);
       }
   }
-  static __device__ __forceinline__ float lvl(uint32_t w, int field) {
-    if constexpr (BITS == 8) {
-      return (float)(int)(int8_t)((w >> (8 * field)) & 0xffu);
-    } else {
-      const int c = (int)((w >> (BITS * field)) & ((1u << BITS) - 1u));
-      return (float)(2 * c - ((1 << BITS) - 1));  // offset binary
-    }
+  static __device__ __forceinline__ float lvl(word w, int field) {
+    const uint32_t c = (uint32_t)(w >> (BITS * field)) & ((1u << BITS) - 1u);
+    if constexpr (BITS == 8) return (float)(int)(int8_t)c;
+    else return (float)(2 * (int)c - ((1 << BITS) - 1));  // offset binary
   }
   template <int L, int R0>
-  __device__ __forceinline__ void convert(float2 (&v)[V][8], const ColArgs&, int, int, int, int) const {
+  __device__ __forceinline__ void convert(float2 (&v)[V][8], const ColArgs&, int, int, int sx, int sy) const {
+    const int fx = NS == 2 ? 0 : sx, fy = NS == 2 ? 1 : sy;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const uint32_t w = raw[e];
-      v[0][e] = make_float2(lvl(w, 0), lvl(w, 1));
-      if constexpr (V == 2) v[1][e] = make_float2(lvl(w, 2), lvl(w, 3));
+      const word w = raw[e];
+#pragma unroll
+      for (int c = 0; c < V; ++c) v[c][e] = make_float2(lvl(w, c * NS + fx), lvl(w, c * NS + fy));
     }
   }
 };
 
 template <int V>
-struct ColLoader<8, true, V> : ColLoaderWords<8, V> {};
+struct ColLoader<8, 1, V> : ColLoaderWords<8, V, 2> {};
 template <int V>
-struct ColLoader<4, true, V> : ColLoaderWords<4, V> {};
+struct ColLoader<4, 1, V> : ColLoaderWords<4, V, 2> {};
 template <int V>
-struct ColLoader<2, true, V> : ColLoaderWords<2, V> {};
+struct ColLoader<2, 1, V> : ColLoaderWords<2, V, 2> {};
+template <int V>
+struct ColLoader<8, 2, V> : ColLoaderWords<8, V, 4> {};
+template <int V>
+struct ColLoader<4, 2, V> : ColLoaderWords<4, V, 4> {};
+template <int V>
+struct ColLoader<2, 2, V> : ColLoaderWords<2, V, 4> {};
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));

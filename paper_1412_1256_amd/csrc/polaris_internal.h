@@ -17,6 +17,7 @@ struct ColArgs {
   const uint8_t* in;        // packed input of the first frame of this launch
   uint32_t in_bytes;        // bytes of input in this launch (< 2^31 on the int8 two-stream path)
   int64_t N;                // frame length
+  int64_t hop;              // samples from one frame's start to the next (N, or N / 2^j for overlap)
   int32_t N2;               // columns
   int32_t S, P;             // streams, pairs
   int32_t px[4], py[4];     // pair -> stream
@@ -30,6 +31,8 @@ struct ColArgs {
   int32_t lo_bits;
   float2* T;                // [n_frames][P][N1][N2]
   unsigned long long* hist; // level histograms [P][2][2^bits] to add to, or nullptr
+  int32_t hist_rows;        // rows n1 < hist_rows (the frame's first hop samples) are counted
+  int32_t pad_;
 };
 
 // Accumulator slots: absolute frame a (counted from ps_reset) is added to slot a mod G, frames of a slot in
@@ -172,7 +175,7 @@ struct BatchArgs {
   int32_t n_cu;             // compute units (the grid is the resident workgroups, at most `total`)
 };
 
-hipError_t launch_colpass_batch(int N1, int cols, int bits, bool fast, const BatchArgs& b, const Launch& l);
+hipError_t launch_colpass_batch(int N1, int cols, int bits, int mode, const BatchArgs& b, const Launch& l);
 hipError_t launch_rowpass_batch(int N2, int fb, const BatchArgs& b, const Launch& l);
 hipError_t launch_output_batch(bool stokes, const BatchArgs& b, const Launch& l);
 int rowpass_units_per_tile(int N2);
@@ -185,7 +188,7 @@ bool rowpass_has(int N2, int fb);
 hipError_t launch_colpass_mx(int N1, int prec, int bits, const MxColArgs& a, int n_blocks, const Launch& l);
 hipError_t launch_rowpass_mx(int N2, int prec, int accum, const MxRowArgs& a, const Launch& l);
 
-hipError_t launch_colpass(int N1, int cols, int bits, bool fast, const ColArgs& a, const Launch& l);
+hipError_t launch_colpass(int N1, int cols, int bits, int mode, const ColArgs& a, const Launch& l);
 hipError_t launch_rowpass(int N2, int fb, const RowArgs& a, const Launch& l);
 hipError_t launch_stokes(const OutArgs& a, const Launch& l);
 hipError_t launch_spectra(const OutArgs& a, const Launch& l);

@@ -50,7 +50,9 @@ __device__ __forceinline__ T load_const(const T* p) {
 // Level histograms of the pair's two streams (bins in ascending level order: code c of a 2- or 4-bit
 // offset-binary sample, level + 128 of an int8 one), counted in LDS and added to the device counts a.hist
 // [P][2][2^BITS] at the end of the tile.  2-bit: four 8-bit counters packed per stream and thread, flushed
-// every frame (at most 16 samples per stream); wider codes: LDS atomics per sample.
+// every frame (at most 16 samples per stream); wider codes: LDS atomics per sample.  Element e of a column
+// is counted when bit e of rows is set (overlapped frames count only their first hop samples, so that every
+// sample of the stream is counted once).
 template <int BITS, int NT>
 struct LevelHist {
   static constexpr int NBIN = 1 << BITS;
@@ -65,16 +67,17 @@ struct LevelHist {
     __syncthreads();
   }
   template <int V>
-  __device__ __forceinline__ void count(uint32_t* hs, const float2 (&v)[V][8]) {
+  __device__ __forceinline__ void count(uint32_t* hs, const float2 (&v)[V][8], const uint32_t rows) {
 #pragma unroll
     for (int c = 0; c < V; ++c)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int bx = bin(v[c][e].x), by = bin(v[c][e].y);
+        const uint32_t on = (rows >> e) & 1u;
         if constexpr (BITS == 2) {
-          packed[0] += 1u << (8 * bx);
-          packed[1] += 1u << (8 * by);
-        } else {
+          packed[0] += on << (8 * bx);
+          packed[1] += on << (8 * by);
+        } else if (on) {
           atomicAdd(&hs[bx], 1u);
           atomicAdd(&hs[NBIN + by], 1u);
         }
@@ -99,7 +102,7 @@ struct LevelHist {
 };
 
 // one tile of the column pass: column block, pair and frame group numbered by blk
-template <int L, int COLS, int V, int BITS, bool FAST, bool HIST = false>
+template <int L, int COLS, int V, int BITS, int FAST, bool HIST = false>
 __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
   constexpr int CPR = COLS / V;  // column groups per row
   using SC = Sched<L>;
@@ -135,14 +138,22 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
   constexpr bool H = HIST && BITS <= 8;
   __shared__ uint32_t hs[H ? 2 << (BITS <= 8 ? BITS : 0) : 1];
   LevelHist<BITS <= 8 ? BITS : 8, NT> hist;
-  if constexpr (H) hist.begin(hs);
+  uint32_t hrows = 0;  // elements of this thread's rows within the frame's first hop samples
+  if constexpr (H) {
+    hist.begin(hs);
+#pragma unroll
+    for (int i = 0; i < 8 / R0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r)
+        if (pin<L, R0>(ts, i, r) < a.hist_rows) hrows |= 1u << (i * R0 + r);
+  }
   // input words are fetched PF frames ahead of their use (PF loaders in rotation)
   constexpr int PF = PS_COLPASS_PREFETCH;
   static_assert(PF == 1 || PF == 2, "prefetch distance 1 or 2 frames");
   auto frame = [&](ColLoader<BITS, FAST, V>& ld, const int f) {
     float2 v[V][8];
     ld.template convert<L, R0>(v, a, ts, n2b, sx, sy);
-    if constexpr (H) hist.count(hs, v);
+    if constexpr (H) hist.count(hs, v, hrows);
     if (a.win) {  // the window is the same for every frame (and cached in L2); read before the prefetch
 #pragma unroll
       for (int i = 0; i < 8 / R0; ++i)
@@ -156,7 +167,7 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
           }
         }
     }
-    if (f + PF < f_end) ld.template fetch<L, R0>(a, (int64_t)(f + PF) * a.N, ts, n2b);
+    if (f + PF < f_end) ld.template fetch<L, R0>(a, (int64_t)(f + PF) * a.hop, ts, n2b);
     col_chain<L, COLS, V, NB, 0>(v, ts, cv, tw, tile);
     // with an odd number of exchanges per frame the next frame's first exchange reuses the tile the last
     // one read: wait for every reader first
@@ -179,9 +190,9 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
     }
   };
   ColLoader<BITS, FAST, V> ld0, ld1;
-  if (f_begin < f_end) ld0.template fetch<L, R0>(a, (int64_t)f_begin * a.N, ts, n2b);
+  if (f_begin < f_end) ld0.template fetch<L, R0>(a, (int64_t)f_begin * a.hop, ts, n2b);
   if constexpr (PF == 2) {
-    if (f_begin + 1 < f_end) ld1.template fetch<L, R0>(a, (int64_t)(f_begin + 1) * a.N, ts, n2b);
+    if (f_begin + 1 < f_end) ld1.template fetch<L, R0>(a, (int64_t)(f_begin + 1) * a.hop, ts, n2b);
     for (int f = f_begin; f < f_end; f += 2) {
       frame(ld0, f);
       if (f + 1 < f_end) frame(ld1, f + 1);
@@ -192,13 +203,13 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
   if constexpr (H) hist.end(hs, a.hist, p);
 }
 
-template <int L, int COLS, int V, int BITS, bool FAST>
+template <int L, int COLS, int V, int BITS, int FAST>
 __global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass(ColArgs a) {
   colpass_tile<L, COLS, V, BITS, FAST>(a, xcd_remap((int)blockIdx.x, (int)gridDim.x));
 }
 
 // the column pass that also counts the level histograms of its streams
-template <int L, int COLS, int V, int BITS, bool FAST>
+template <int L, int COLS, int V, int BITS, int FAST>
 __global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass_hist(ColArgs a) {
   colpass_tile<L, COLS, V, BITS, FAST, true>(a, xcd_remap((int)blockIdx.x, (int)gridDim.x));
 }
@@ -206,7 +217,7 @@ __global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass_hist(ColArgs a) 
 // Batched (persistent) column pass over the tiles of several instances of the same shape and format: each
 // workgroup walks the global tile list with a grid stride; tile_end holds the running tile totals.  The
 // task descriptors are read through the constant address space (scalar loads into SGPRs).
-template <int L, int COLS, int V, int BITS, bool FAST>
+template <int L, int COLS, int V, int BITS, int FAST>
 __global__ void __launch_bounds__(L * COLS / (8 * V))
     k_colpass_batch(const ColArgs* __restrict__ tasks, const int32_t* __restrict__ tile_end, int n_tasks) {
   const int total = tile_end[n_tasks - 1];
@@ -559,42 +570,42 @@ __global__ void __launch_bounds__(256) k_copy_words(const uint32_t* __restrict__
 #define PS_LAUNCH(kernel, grid, block, l, ...) \
   hipExtLaunchKernelGGL(kernel, grid, block, 0, (l).stream, (l).start, (l).stop, 0, __VA_ARGS__)
 
+// loader mode 0 (decode at use), 1 (two streams, pair (0, 1)) or 2 (four streams) of one code width
+template <int L, int COLS, int V, int BITS, bool HIST>
+static void colpass_mode(int mode, dim3 grid, dim3 block, const ColArgs& a, const Launch& s) {
+  if constexpr (HIST) {
+    if (mode == 1) PS_LAUNCH((k_colpass_hist<L, COLS, V, BITS, 1>), grid, block, s, a);
+    else if (mode == 2) PS_LAUNCH((k_colpass_hist<L, COLS, V, BITS, 2>), grid, block, s, a);
+    else PS_LAUNCH((k_colpass_hist<L, COLS, V, BITS, 0>), grid, block, s, a);
+  } else {
+    if (mode == 1) PS_LAUNCH((k_colpass<L, COLS, V, BITS, 1>), grid, block, s, a);
+    else if (mode == 2) PS_LAUNCH((k_colpass<L, COLS, V, BITS, 2>), grid, block, s, a);
+    else PS_LAUNCH((k_colpass<L, COLS, V, BITS, 0>), grid, block, s, a);
+  }
+}
+
 template <int L, int COLS, int V>
-static hipError_t colpass_bits(int bits, bool fast, const ColArgs& a, const Launch& s) {
+static hipError_t colpass_bits(int bits, int mode, const ColArgs& a, const Launch& s) {
   const int groups = (a.n_frames + a.frames_per_block - 1) / a.frames_per_block;
   const dim3 grid((unsigned)(groups * a.P * a.n_colblk)), block(L * COLS / (8 * V));
-  if (a.hist) {
-    switch (bits) {
-      case 2:
-        if (fast) PS_LAUNCH((k_colpass_hist<L, COLS, V, 2, true>), grid, block, s, a);
-        else PS_LAUNCH((k_colpass_hist<L, COLS, V, 2, false>), grid, block, s, a);
-        break;
-      case 4:
-        if (fast) PS_LAUNCH((k_colpass_hist<L, COLS, V, 4, true>), grid, block, s, a);
-        else PS_LAUNCH((k_colpass_hist<L, COLS, V, 4, false>), grid, block, s, a);
-        break;
-      case 8:
-        if (fast) PS_LAUNCH((k_colpass_hist<L, COLS, V, 8, true>), grid, block, s, a);
-        else PS_LAUNCH((k_colpass_hist<L, COLS, V, 8, false>), grid, block, s, a);
-        break;
-      default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-  }
+  const bool hist = a.hist != nullptr;
   switch (bits) {
     case 2:
-      if (fast) PS_LAUNCH((k_colpass<L, COLS, V, 2, true>), grid, block, s, a);
-      else PS_LAUNCH((k_colpass<L, COLS, V, 2, false>), grid, block, s, a);
+      if (hist) colpass_mode<L, COLS, V, 2, true>(mode, grid, block, a, s);
+      else colpass_mode<L, COLS, V, 2, false>(mode, grid, block, a, s);
       break;
     case 4:
-      if (fast) PS_LAUNCH((k_colpass<L, COLS, V, 4, true>), grid, block, s, a);
-      else PS_LAUNCH((k_colpass<L, COLS, V, 4, false>), grid, block, s, a);
+      if (hist) colpass_mode<L, COLS, V, 4, true>(mode, grid, block, a, s);
+      else colpass_mode<L, COLS, V, 4, false>(mode, grid, block, a, s);
       break;
     case 8:
-      if (fast) PS_LAUNCH((k_colpass<L, COLS, V, 8, true>), grid, block, s, a);
-      else PS_LAUNCH((k_colpass<L, COLS, V, 8, false>), grid, block, s, a);
+      if (hist) colpass_mode<L, COLS, V, 8, true>(mode, grid, block, a, s);
+      else colpass_mode<L, COLS, V, 8, false>(mode, grid, block, a, s);
       break;
-    case 32: PS_LAUNCH((k_colpass<L, COLS, V, 32, false>), grid, block, s, a); break;
+    case 32:
+      if (hist) return hipErrorInvalidValue;
+      PS_LAUNCH((k_colpass<L, COLS, V, 32, 0>), grid, block, s, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -612,22 +623,22 @@ bool colpass_has(int N1, int cols) {
   return (N1 == 256 || N1 == 512) && cols == 8;
 }
 
-hipError_t launch_colpass(int N1, int cols, int bits, bool fast, const ColArgs& a, const Launch& s) {
+hipError_t launch_colpass(int N1, int cols, int bits, int mode, const ColArgs& a, const Launch& s) {
   constexpr int V = PS_COLPASS_V;
   if (cols != colpass_cols(N1)) {
-    if (N1 == 256 && cols == 8) return colpass_bits<256, 8, V>(bits, fast, a, s);
-    if (N1 == 512 && cols == 8) return colpass_bits<512, 8, V>(bits, fast, a, s);
+    if (N1 == 256 && cols == 8) return colpass_bits<256, 8, V>(bits, mode, a, s);
+    if (N1 == 512 && cols == 8) return colpass_bits<512, 8, V>(bits, mode, a, s);
     return hipErrorInvalidValue;
   }
   switch (N1) {
-    case 16: return colpass_bits<16, 16, 2>(bits, fast, a, s);
-    case 32: return colpass_bits<32, 16, 2>(bits, fast, a, s);
-    case 64: return colpass_bits<64, 16, 2>(bits, fast, a, s);
-    case 128: return colpass_bits<128, 16, 2>(bits, fast, a, s);
-    case 256: return colpass_bits<256, PS_COLPASS_COLS, V>(bits, fast, a, s);
-    case 512: return colpass_bits<512, PS_COLPASS_COLS, V>(bits, fast, a, s);
-    case 1024: return colpass_bits<1024, 8, 2>(bits, fast, a, s);
-    case 2048: return colpass_bits<2048, 4, 2>(bits, fast, a, s);
+    case 16: return colpass_bits<16, 16, 2>(bits, mode, a, s);
+    case 32: return colpass_bits<32, 16, 2>(bits, mode, a, s);
+    case 64: return colpass_bits<64, 16, 2>(bits, mode, a, s);
+    case 128: return colpass_bits<128, 16, 2>(bits, mode, a, s);
+    case 256: return colpass_bits<256, PS_COLPASS_COLS, V>(bits, mode, a, s);
+    case 512: return colpass_bits<512, PS_COLPASS_COLS, V>(bits, mode, a, s);
+    case 1024: return colpass_bits<1024, 8, 2>(bits, mode, a, s);
+    case 2048: return colpass_bits<2048, 4, 2>(bits, mode, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -699,45 +710,47 @@ static unsigned persistent_grid(K kernel, int block, int total, int n_cu) {
     hipExtLaunchKernelGGL(kernel, dim3(g_), dim3(block), 0, (l).stream, (l).start, (l).stop, 0, __VA_ARGS__); \
   } while (0)
 
-template <int L, int COLS, int V>
-static hipError_t colpass_batch_bits(int bits, bool fast, const BatchArgs& b, const Launch& s) {
+template <int L, int COLS, int V, int BITS>
+static void colpass_batch_mode(int mode, const BatchArgs& b, const Launch& s) {
   constexpr int block = L * COLS / (8 * V);
   const ColArgs* t = static_cast<const ColArgs*>(b.tasks);
+  if constexpr (BITS == 32) {
+    PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 32, 0>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+    return;
+  }
+  if (mode == 1) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, BITS, 1>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+  else if (mode == 2) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, BITS, 2>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+  else PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, BITS, 0>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+}
+
+template <int L, int COLS, int V>
+static hipError_t colpass_batch_bits(int bits, int mode, const BatchArgs& b, const Launch& s) {
   switch (bits) {
-    case 2:
-      if (fast) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 2, true>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
-      else PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 2, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
-      break;
-    case 4:
-      if (fast) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 4, true>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
-      else PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 4, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
-      break;
-    case 8:
-      if (fast) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 8, true>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
-      else PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 8, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
-      break;
-    case 32: PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 32, false>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks); break;
+    case 2: colpass_batch_mode<L, COLS, V, 2>(mode, b, s); break;
+    case 4: colpass_batch_mode<L, COLS, V, 4>(mode, b, s); break;
+    case 8: colpass_batch_mode<L, COLS, V, 8>(mode, b, s); break;
+    case 32: colpass_batch_mode<L, COLS, V, 32>(0, b, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_colpass_batch(int N1, int cols, int bits, bool fast, const BatchArgs& b, const Launch& s) {
+hipError_t launch_colpass_batch(int N1, int cols, int bits, int mode, const BatchArgs& b, const Launch& s) {
   constexpr int V = PS_COLPASS_V;
   if (cols != colpass_cols(N1)) {
-    if (N1 == 256 && cols == 8) return colpass_batch_bits<256, 8, V>(bits, fast, b, s);
-    if (N1 == 512 && cols == 8) return colpass_batch_bits<512, 8, V>(bits, fast, b, s);
+    if (N1 == 256 && cols == 8) return colpass_batch_bits<256, 8, V>(bits, mode, b, s);
+    if (N1 == 512 && cols == 8) return colpass_batch_bits<512, 8, V>(bits, mode, b, s);
     return hipErrorInvalidValue;
   }
   switch (N1) {
-    case 16: return colpass_batch_bits<16, 16, 2>(bits, fast, b, s);
-    case 32: return colpass_batch_bits<32, 16, 2>(bits, fast, b, s);
-    case 64: return colpass_batch_bits<64, 16, 2>(bits, fast, b, s);
-    case 128: return colpass_batch_bits<128, 16, 2>(bits, fast, b, s);
-    case 256: return colpass_batch_bits<256, PS_COLPASS_COLS, V>(bits, fast, b, s);
-    case 512: return colpass_batch_bits<512, PS_COLPASS_COLS, V>(bits, fast, b, s);
-    case 1024: return colpass_batch_bits<1024, 8, 2>(bits, fast, b, s);
-    case 2048: return colpass_batch_bits<2048, 4, 2>(bits, fast, b, s);
+    case 16: return colpass_batch_bits<16, 16, 2>(bits, mode, b, s);
+    case 32: return colpass_batch_bits<32, 16, 2>(bits, mode, b, s);
+    case 64: return colpass_batch_bits<64, 16, 2>(bits, mode, b, s);
+    case 128: return colpass_batch_bits<128, 16, 2>(bits, mode, b, s);
+    case 256: return colpass_batch_bits<256, PS_COLPASS_COLS, V>(bits, mode, b, s);
+    case 512: return colpass_batch_bits<512, PS_COLPASS_COLS, V>(bits, mode, b, s);
+    case 1024: return colpass_batch_bits<1024, 8, 2>(bits, mode, b, s);
+    case 2048: return colpass_batch_bits<2048, 4, 2>(bits, mode, b, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj) {
             const gbytes fb = uniform_gptr(
-                c.in + ((int64_t)f * c.N + (int64_t)(R * jj + 4 * w + j + 16 * h) * N2) * BPT);
+                c.in + ((int64_t)f * c.hop + (int64_t)(R * jj + 4 * w + j + 16 * h) * N2) * BPT);
             in[j][h][jj].fetch(fb, lane_t);
           }
     }
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
         w4v xb[1];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-          const int64_t tt = (int64_t)f * c.N + (int64_t)(R * jj + b + 16 * h) * N2 + lane_t;
+          const int64_t tt = (int64_t)f * c.hop + (int64_t)(R * jj + b + 16 * h) * N2 + lane_t;
           float2 v = in[j][h][jj].level(c, tt, sx, sy);
           if constexpr (WIN) {
             const gbytes wb = uniform_gptr(reinterpret_cast<const uint8_t*>(c.win + (R * jj + b + 16 * h) * N2));

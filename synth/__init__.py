@@ -20,4 +20,6 @@ from .gen import (  # noqa: F401
     make_identical_streams,
     make_fully_polarized_f32,
     make_correlated_noise,
+    MODES,
+    make_mode,
 )

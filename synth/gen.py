@@ -202,6 +202,35 @@ def make_precision(n_frames: int = 610, fft_len: int = 2 ** 18, rho: float = 0.0
     return _instance(pack_codes(codes, 8), 8, 4, fft_len, n_frames, window="rect", pairs=[(0, 2), (1, 3)])
 
 
+MODES = {
+    # Table 1: IF bandwidth, sampling rate, code width, FFT length (channels = N / 2), four IFs X0, X1, Y0, Y1
+    "8MHz": dict(bits=4, fft_len=2 ** 18, sample_rate_hz=16e6),
+    "4MHz": dict(bits=8, fft_len=2 ** 17, sample_rate_hz=8e6),
+}
+
+
+def make_mode(mode: str, n_frames: int = 61, rho: float = 0.05, seed_extra: int = 0):
+    """One of the sampler modes of Table 1 with its four IFs X0, X1, Y0, Y1 (pairs (0, 2), (1, 3)): per
+    band, the paper-shaped line model (see make_paper) quantised by that mode's sampler (4-bit: step sigma/2;
+    8-bit: sigma = 16 LSB).  61 frames are 0.999 s of data in either mode."""
+    m = MODES[mode]
+    rng = rng_for(6, seed_extra, m["bits"])
+    N = m["fft_len"]
+    C = N // 2
+    I, Q, U, V = _line_model(C + 1, C, rho)
+    sigma = 16.0 if m["bits"] == 8 else 1.0
+    T = n_frames * N
+    codes = np.empty((T, 4), dtype=np.uint8)
+    for band in range(2):
+        ts = _spectral_streams(rng, N, n_frames, I + Q, I - Q, U + 1j * V, sigma)
+        q = quantize(ts, m["bits"], sigma=sigma)
+        codes[:, band] = q[:, 0]       # X_band
+        codes[:, 2 + band] = q[:, 1]   # Y_band
+    d = _instance(pack_codes(codes, m["bits"]), m["bits"], 4, N, n_frames, window="rect", pairs=[(0, 2), (1, 3)])
+    d["sample_rate_hz"] = m["sample_rate_hz"]
+    return d
+
+
 def make_correlated_noise(bits: int, rho: float, fft_len: int, n_frames: int, cfg: int = 100,
                           seed_extra: int = 0, window: str = "rect"):
     """Two streams of N(0,1) noise with correlation rho, quantised (sigma = 1; 8-bit uses 16 LSB)."""

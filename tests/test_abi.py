@@ -27,8 +27,8 @@ def test_every_declared_function_is_exported():
 
 
 def test_instance_struct_layout_matches_header():
-    assert C.sizeof(pk._Instance) == 80
-    assert pk._Instance.fft_len.offset == 64
+    assert C.sizeof(pk._Instance) == 88
+    assert pk._Instance.fft_len.offset == 64 and pk._Instance.hop.offset == 80
     assert C.sizeof(pk._Cal) == 40 and pk._Cal.feed.offset == 32
 
 
@@ -67,6 +67,10 @@ def test_valid_plan_reports_aligned_workspace():
     (dict(fft_len=1 << 20, precision="fp16"), "PS_ERR_UNSUPPORTED"),
     (dict(fft_len=1 << 12, precision="bf16"), "PS_ERR_UNSUPPORTED"),
     (dict(fft_len=1 << 16, precision="fp16", window="taps", n_taps=64), "PS_ERR_UNSUPPORTED"),
+    (dict(hop=384), "PS_ERR_ARG"),
+    (dict(hop=64), "PS_ERR_ARG"),
+    (dict(hop=2048), "PS_ERR_ARG"),
+    (dict(hop=-512), "PS_ERR_ARG"),
 ])
 def test_plan_rejects_bad_instances(kw, code):
     st, h, n = _plan(**kw)
@@ -152,3 +156,29 @@ def test_scheduled_plan_rejects_unbuilt_schedules(sched):
     st = pk.lib().ps_plan_scheduled(arr, sarr, 1, C.byref(h), C.byref(n))
     assert pk.STATUS[st] == "PS_ERR_UNSUPPORTED", pk.lib().ps_last_error()
     assert not h.value
+
+
+@pytest.mark.parametrize("hop", [0, 1024, 512, 256, 128])
+def test_plan_accepts_hops_and_keeps_room_for_the_waiting_samples(hop):
+    st0, h0, n0 = _plan()
+    st, h, n = _plan(hop=hop)
+    assert st0 == 0 and st == 0, pk.lib().ps_last_error()
+    extra = 0 if hop in (0, 1024) else 2 * (1024 - hop) * 2 * 2 // 8  # two halves of N - hop two-bit samples, 2 streams
+    assert n - n0 >= extra
+    sb = C.c_size_t()
+    assert pk.lib().ps_state_bytes(h, 0, C.byref(sb)) == 0
+    sb0 = C.c_size_t()
+    assert pk.lib().ps_state_bytes(h0, 0, C.byref(sb0)) == 0
+    assert sb.value - sb0.value == extra // 2
+    pk.lib().ps_destroy(h)
+    pk.lib().ps_destroy(h0)
+
+
+@pytest.mark.parametrize("window", ["hamming", "blackman"])
+def test_plan_accepts_apodisation_windows(window):
+    st, h, n = _plan(window=window)
+    assert st == 0, pk.lib().ps_last_error()
+    pk.lib().ps_destroy(h)
+    st, h, n = _plan(window=window, fft_len=1 << 16, precision="fp16", accum="kahan32")
+    assert st == 0, pk.lib().ps_last_error()
+    pk.lib().ps_destroy(h)

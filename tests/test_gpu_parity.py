@@ -347,3 +347,20 @@ def test_circular_feeds(pk, torch_dev, psi):
     with pytest.raises(pk.PolarisError) as ex:
         plan.stokes(feed=5)
     assert ex.value.code == "PS_ERR_ARG"
+
+
+@pytest.mark.parametrize("mode,F", [("8MHz", 16), ("4MHz", 32)])
+def test_table1_modes(pk, torch_dev, mode, F):
+    """Table 1's sampler modes with their four IFs: 8 MHz (16 Msps, 4-bit, 2^18 points) and 4 MHz (8 Msps,
+    8-bit, 2^17 points), pairs (X0, Y0), (X1, Y1)."""
+    torch, dev = torch_dev
+    say(f"Table 1 mode {mode} F={F}")
+    inst = synth.make_mode(mode, n_frames=F)
+    acc, nf, s2, _ = oracle.run_instance(inst)
+    ref = oracle.stokes(acc, nf, s2, psi=0.3)
+    spec, gnf, st = run_gpu(pk, torch, dev, inst, psi=0.3)
+    assert gnf == nf == F
+    e_spec = spectra_err(spec, acc)
+    e = stokes_err(st, ref)
+    say(f"  spectra err {e_spec.max()} stokes err {e.tolist()}")
+    assert np.all(e_spec < TOL) and np.all(e < TOL), (e_spec, e)
