@@ -456,6 +456,50 @@ def modes_form(pk, torch, dev, steps, ring_n):
     return res
 
 
+def post_form(pk, torch, dev, reps):
+    """The post-integration reductions at the paper's sizes (device time per call, events on the current
+    stream): channel averaging of one integration's Stokes spectra 131072 -> 4096 channels with a flagged
+    channel (Sec. 4); the bandpass table of 131072 channels (128-channel knots, 6 % edges) and the variation
+    of 30 integrations H^_k = H_k / (G_k H), averaged over 256 channels, with mean and SD (Sec. 3.3.2); the
+    TAV (Eq. 3) of every channel over 1800 1-s integrations and the SAV (Eq. 4) of 30 spectra, 8 lags each."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(1412)
+    C = 131072
+    stokes = 1 + 0.01 * torch.randn((1, 4, C), generator=g, device=dev)
+    flags = torch.zeros(C, dtype=torch.uint8, device=dev)
+    flags[C // 2] = 1
+    hk = 1 + 0.01 * torch.randn((30, C), generator=g, device=dev)
+    gain = torch.linspace(1.0, 1.03, 30, device=dev, dtype=torch.float64)
+    series = 1 + 0.01 * torch.randn((1800, C), generator=g, device=dev)
+    lags = [1, 2, 4, 8, 16, 64, 256, 512]
+    smooth = pk.bandpass_fit(hk[0])
+    hat = pk.bandpass_correct(hk, smooth, gain)
+    binned = pk.channel_average(hat, 256)[0]
+    calls = {
+        "channel_average_stokes_32": lambda: pk.channel_average(stokes, 32, flags),
+        "bandpass_fit_131072": lambda: pk.bandpass_fit(hk[0], 128, 0.06),
+        "bandpass_correct_30x131072": lambda: pk.bandpass_correct(hk, smooth, gain),
+        "channel_average_30x131072_256": lambda: pk.channel_average(hat, 256),
+        "band_stats_30x512": lambda: pk.band_stats(binned),
+        "tav_1800x131072_8lags": lambda: pk.allan(series, lags, spacing=1.0, normalize=True, axis=0),
+        "sav_30x131072_8lags": lambda: pk.allan(hat, lags, spacing=SAMPLE_RATE / 2 ** 18, axis=1),
+    }
+    res = {}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize(dev)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        res[f"{name}_us"] = a.elapsed_time(b) / reps * 1e3
+    res["tav_input_GBps"] = series.numel() * 4 / (res["tav_1800x131072_8lags_us"] * 1e-6) / 1e9
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -579,6 +623,7 @@ def main():
     out["total_power"] = power_form(pk, torch, dev, inst, packed, max(5, args.steps // 4))
     out["overlap_form"] = overlap_form(pk, torch, dev, inst, ring, max(8, args.steps // 2))
     out["table1_modes"] = modes_form(pk, torch, dev, max(8, args.steps // 2), args.ring)
+    out["post_reduction"] = post_form(pk, torch, dev, 10)
     if not args.no_batching:
         out["batching_form"] = batching_form(pk, torch, dev, max(3, args.steps // 10))
     if not args.no_precision:

@@ -248,6 +248,54 @@ ps_status ps_state_import(ps_plan_t plan, int32_t inst, const void* src_dev, int
 ps_status ps_unpack(const void* packed_dev, int32_t bits, int32_t n_streams, int64_t n_time, float* out_dev,
                     void* hip_stream);
 
+/*
+ * Post-integration reductions on integrated spectra (device buffers; each call is enqueued on hip_stream and
+ * allocates nothing).  Sums are FP64 in a fixed order: results are identical from run to run.  Non-finite
+ * values (e.g. channels outside a fitted band) are left out like flagged channels.
+ *
+ * Channel averaging (Sec. 4: 131072 channels averaged to 1.95-kHz resolution after flagging a spurious
+ * channel).  in [n_spec][n_chan] float; flags [n_chan] uint8, nonzero = flagged, or NULL; factor divides
+ * n_chan (else PS_ERR_SIZE); n_spec <= 65535.  out [n_spec][n_chan/factor]: the mean of the bin's unflagged
+ * finite channels, NaN when there are none; counts [n_spec][n_chan/factor] (may be NULL).
+ */
+ps_status ps_channel_average(const float* in_dev, int64_t n_spec, int64_t n_chan, int32_t factor,
+                             const uint8_t* flags_dev, float* out_dev, int32_t* counts_dev, void* hip_stream);
+
+/*
+ * Smoothed bandpass table H (Sec. 3.3.2: a long integration smoothed by a spline 128 channels wide, 6 % of
+ * the band left out at each end): the least-squares cubic spline with uniform knots every knot_spacing
+ * channels from c0 = floor(edge_frac n_chan), fitted to channels [c0, n_chan - c0) of h [n_chan] float;
+ * smooth [n_chan] float holds the spline there and NaN outside.  The range must hold at least four knot
+ * intervals (PS_ERR_SIZE) and give at most 3072 spline coefficients (PS_ERR_UNSUPPORTED).  work: a 256-byte
+ * aligned device buffer of ps_bandpass_work_bytes bytes, owned by the caller.
+ */
+ps_status ps_bandpass_work_bytes(int64_t n_chan, int32_t knot_spacing, double edge_frac, size_t* bytes);
+ps_status ps_bandpass_fit(const float* h_dev, int64_t n_chan, int32_t knot_spacing, double edge_frac,
+                          void* work_dev, size_t work_bytes, float* smooth_dev, void* hip_stream);
+
+/* Bandpass variation (Sec. 3.3.2): out[k][c] = hk[k][c] / (gain[k] smooth[c]) for spectra k < n_spec
+ * (<= 65535) of n_chan channels; gain [n_spec] double (the total-power gain G_k of each integration) or NULL
+ * (= 1).  FP64 arithmetic, FP32 output. */
+ps_status ps_bandpass_correct(const float* hk_dev, int64_t n_spec, int64_t n_chan, const float* smooth_dev,
+                              const double* gain_dev, float* out_dev, void* hip_stream);
+
+/* Band statistics (Sec. 3.3.3): mean_sd[k] = (mean, sqrt(<x^2> - <x>^2)) of spectrum k's finite channels
+ * (NaN, NaN when none), as double [n_spec][2]. */
+ps_status ps_band_stats(const float* x_dev, int64_t n_spec, int64_t n_chan, double* mean_sd_dev, void* hip_stream);
+
+/*
+ * Allan variance of a second difference: Eq. 3 (time-based, TAV: a series of integrations at one channel)
+ * and Eq. 4 (spectral, SAV: the channels of one spectrum).  Series s has n_points samples
+ * x[s * series_stride + t * point_stride] (float, strides in elements).  For each of the n_lags (1..64) lags
+ * L (host int32, >= 1): out[s][l] = mean over t of (x[t+L] - 2 x[t] + x[t-L])^2 / (2 (L spacing)^2), t with
+ * all three samples finite, NaN when there is none (2 L >= n_points); spacing is the sample interval (s for
+ * TAV, Hz for SAV).  normalize != 0 divides each series by the mean of its finite samples first.  out:
+ * double [n_series][n_lags].
+ */
+ps_status ps_allan(const float* x_dev, int64_t n_points, int64_t point_stride, int64_t n_series,
+                   int64_t series_stride, const int32_t* lags, int32_t n_lags, double spacing, int32_t normalize,
+                   double* out_dev, void* hip_stream);
+
 /* Free a plan's host metadata (never the caller's device memory). NULL is accepted. */
 ps_status ps_destroy(ps_plan_t plan);
 

@@ -119,6 +119,12 @@ def lib():
             "ps_graph_begin": [vp],
             "ps_graph_end": [vp, i32],
             "ps_graph_launch": [vp],
+            "ps_channel_average": [vp, i64, i64, i32, vp, vp, vp, vp],
+            "ps_bandpass_work_bytes": [i64, i32, C.c_double, C.POINTER(sz)],
+            "ps_bandpass_fit": [vp, i64, i32, C.c_double, vp, sz, vp, vp],
+            "ps_bandpass_correct": [vp, i64, i64, vp, vp, vp, vp],
+            "ps_band_stats": [vp, i64, i64, vp, vp],
+            "ps_allan": [vp, i64, i64, i64, i64, C.POINTER(i32), i32, C.c_double, i32, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -418,4 +424,89 @@ def unpack(packed, bits: int, n_streams: int, n_time: int, stream=None):
     out = torch.empty((n_streams, n_time), dtype=torch.float32, device=packed.device)
     s = stream if stream is not None else torch.cuda.current_stream(packed.device)
     _check(lib().ps_unpack(_ptr(packed), bits, n_streams, n_time, _ptr(out), C.c_void_p(s.cuda_stream)))
+    return out
+
+
+# ------------------------------------------------------------------------------------------------
+# post-integration reductions (device tensors in, device tensors out; enqueued on the current stream)
+
+def _stream(t, stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(t.device)
+    return C.c_void_p(s.cuda_stream)
+
+
+def _f32_2d(x):
+    x = x.contiguous()
+    if x.dtype != __import__("torch").float32:
+        raise TypeError("float32 spectra expected")
+    return x if x.dim() == 2 else x.reshape(-1, x.shape[-1])
+
+
+def channel_average(spectra, factor: int, flags=None, stream=None):
+    """Bins of `factor` channels along the last axis, flagged (uint8 [C], nonzero) and non-finite channels
+    left out: (mean [..., C/factor] float32, counts [..., C/factor] int32)."""
+    import torch
+    x = _f32_2d(spectra)
+    n_spec, n_chan = x.shape
+    out = torch.empty((n_spec, n_chan // max(1, factor)), dtype=torch.float32, device=x.device)
+    cnt = torch.empty(out.shape, dtype=torch.int32, device=x.device)
+    fl = None if flags is None else flags.to(torch.uint8).contiguous()
+    _check(lib().ps_channel_average(_ptr(x), n_spec, n_chan, factor, _ptr(fl), _ptr(out), _ptr(cnt),
+                                    _stream(x, stream)))
+    shape = tuple(spectra.shape[:-1]) + (out.shape[-1],)
+    return out.reshape(shape), cnt.reshape(shape)
+
+
+def bandpass_fit(h, knot_spacing: int = 128, edge_frac: float = 0.06, stream=None):
+    """Smoothed bandpass: least-squares cubic spline with knots every knot_spacing channels, fitted without
+    edge_frac of the band at each end (NaN there); float32 [C]."""
+    import torch
+    h = h.contiguous().to(torch.float32)
+    n = C.c_size_t()
+    _check(lib().ps_bandpass_work_bytes(h.numel(), knot_spacing, edge_frac, C.byref(n)))
+    work = torch.empty(n.value + 256, dtype=torch.uint8, device=h.device)
+    off = (-work.data_ptr()) % 256
+    w = work[off:off + n.value]
+    out = torch.empty_like(h)
+    _check(lib().ps_bandpass_fit(_ptr(h), h.numel(), knot_spacing, edge_frac, _ptr(w), n.value, _ptr(out),
+                                 _stream(h, stream)))
+    out._work_keepalive = work
+    return out
+
+
+def bandpass_correct(hk, smooth, gain=None, stream=None):
+    """H^_k = H_k / (G_k H): hk [n][C] float32, smooth [C] float32, gain [n] float64 or None."""
+    import torch
+    x = _f32_2d(hk)
+    g = None if gain is None else gain.to(torch.float64).contiguous()
+    out = torch.empty_like(x)
+    _check(lib().ps_bandpass_correct(_ptr(x), x.shape[0], x.shape[1], _ptr(smooth.contiguous()), _ptr(g), _ptr(out),
+                                     _stream(x, stream)))
+    return out.reshape(hk.shape)
+
+
+def band_stats(x, stream=None):
+    """[n][2] float64: mean and standard deviation of each spectrum's finite channels."""
+    import torch
+    v = _f32_2d(x)
+    out = torch.empty((v.shape[0], 2), dtype=torch.float64, device=v.device)
+    _check(lib().ps_band_stats(_ptr(v), v.shape[0], v.shape[1], _ptr(out), _stream(v, stream)))
+    return out
+
+
+def allan(x, lags, spacing: float = 1.0, normalize: bool = False, axis: int = -1, stream=None):
+    """Eq. 3 / Eq. 4 along `axis` of a 2-D float32 tensor (the other axis indexes the series): float64
+    [n_series][len(lags)]."""
+    import torch
+    if x.dim() != 2:
+        raise ValueError("a 2-D tensor expected")
+    v = x.contiguous().to(torch.float32)
+    axis = axis % 2
+    n_points, n_series = v.shape[axis], v.shape[1 - axis]
+    point_stride, series_stride = (1, n_points) if axis == 1 else (n_series, 1)
+    lg = (C.c_int32 * len(lags))(*[int(L) for L in lags])
+    out = torch.empty((n_series, len(lags)), dtype=torch.float64, device=v.device)
+    _check(lib().ps_allan(_ptr(v), n_points, point_stride, n_series, series_stride, lg, len(lags), spacing,
+                          1 if normalize else 0, _ptr(out), _stream(v, stream)))
     return out

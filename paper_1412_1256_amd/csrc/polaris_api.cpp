@@ -16,6 +16,7 @@
 
 #include "../../include/polaris.h"
 #include "polaris_internal.h"
+#include "polaris_post.h"
 
 namespace {
 
@@ -1340,6 +1341,127 @@ ps_status ps_profile_read(ps_plan_t plan, double* ms_total, int64_t* launches) {
 
 ps_status ps_destroy(ps_plan_t plan) {
   delete plan;
+  return PS_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// post-integration reductions
+
+ps_status ps_channel_average(const float* in_dev, int64_t n_spec, int64_t n_chan, int32_t factor,
+                             const uint8_t* flags_dev, float* out_dev, int32_t* counts_dev, void* hip_stream) {
+  if (!in_dev || !out_dev) return fail(PS_ERR_ARG, "null spectra or output");
+  if (n_spec < 0 || n_spec > 65535) return fail(PS_ERR_ARG, "n_spec %lld not in 0..65535", (long long)n_spec);
+  if (n_chan < 1 || factor < 1 || n_chan % factor)
+    return fail(PS_ERR_SIZE, "factor %d does not divide n_chan %lld", factor, (long long)n_chan);
+  if (n_chan / factor > (int64_t(1) << 31) - 1) return fail(PS_ERR_SIZE, "too many bins");
+  if (n_spec == 0) return PS_OK;
+  ps::ChanAvgArgs a{in_dev, n_spec, n_chan, factor, flags_dev, out_dev, counts_dev};
+  hipError_t e = ps::launch_channel_average(a, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "channel average launch");
+  return PS_OK;
+}
+
+static ps_status spline_args(int64_t n_chan, int32_t knot_spacing, double edge_frac, ps::SplineArgs* a) {
+  if (knot_spacing < 4) return fail(PS_ERR_ARG, "knot spacing %d below 4 channels", knot_spacing);
+  if (!(edge_frac >= 0.0 && edge_frac < 0.5)) return fail(PS_ERR_ARG, "edge fraction %g not in [0, 0.5)", edge_frac);
+  if (n_chan < 1 || n_chan > (int64_t(1) << 31)) return fail(PS_ERR_ARG, "n_chan %lld out of range", (long long)n_chan);
+  a->n_chan = n_chan;
+  a->c0 = (int64_t)std::floor(edge_frac * (double)n_chan);
+  a->c1 = n_chan - a->c0;
+  a->K = knot_spacing;
+  if (a->c1 - a->c0 < 4 * (int64_t)knot_spacing)
+    return fail(PS_ERR_SIZE, "the fit range of %lld channels holds fewer than four knot intervals",
+                (long long)(a->c1 - a->c0));
+  a->n_int = (a->c1 - a->c0 + knot_spacing - 1) / knot_spacing;
+  a->n_coef = a->n_int + 3;
+  if (a->n_coef > ps::kMaxSplineCoef)
+    return fail(PS_ERR_UNSUPPORTED, "%lld spline coefficients exceed the %lld of one solve", (long long)a->n_coef,
+                (long long)ps::kMaxSplineCoef);
+  return PS_OK;
+}
+
+static size_t spline_work_bytes(const ps::SplineArgs& a) {
+  return align_up((size_t)a.n_int * 14 * 8) + align_up((size_t)a.n_coef * 8) + align_up((size_t)a.n_coef * 32);
+}
+
+ps_status ps_bandpass_work_bytes(int64_t n_chan, int32_t knot_spacing, double edge_frac, size_t* bytes) {
+  if (!bytes) return fail(PS_ERR_ARG, "null bytes");
+  ps::SplineArgs a{};
+  ps_status st = spline_args(n_chan, knot_spacing, edge_frac, &a);
+  if (st != PS_OK) return st;
+  *bytes = spline_work_bytes(a);
+  return PS_OK;
+}
+
+ps_status ps_bandpass_fit(const float* h_dev, int64_t n_chan, int32_t knot_spacing, double edge_frac,
+                          void* work_dev, size_t work_bytes, float* smooth_dev, void* hip_stream) {
+  if (!h_dev || !smooth_dev) return fail(PS_ERR_ARG, "null spectrum or output");
+  ps::SplineArgs a{};
+  ps_status st = spline_args(n_chan, knot_spacing, edge_frac, &a);
+  if (st != PS_OK) return st;
+  if (!work_dev || reinterpret_cast<uintptr_t>(work_dev) % kAlign)
+    return fail(PS_ERR_WORKSPACE, "null or misaligned work buffer");
+  if (work_bytes < spline_work_bytes(a))
+    return fail(PS_ERR_WORKSPACE, "work buffer of %zu bytes is smaller than the %zu needed", work_bytes,
+                spline_work_bytes(a));
+  char* w = static_cast<char*>(work_dev);
+  a.h = h_dev;
+  a.partial = reinterpret_cast<double*>(w);
+  a.coef = reinterpret_cast<double*>(w + align_up((size_t)a.n_int * 14 * 8));
+  a.lower = reinterpret_cast<double*>(w + align_up((size_t)a.n_int * 14 * 8) + align_up((size_t)a.n_coef * 8));
+  a.smooth = smooth_dev;
+  hipError_t e = ps::launch_bandpass_fit(a, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "bandpass fit launch");
+  return PS_OK;
+}
+
+ps_status ps_bandpass_correct(const float* hk_dev, int64_t n_spec, int64_t n_chan, const float* smooth_dev,
+                              const double* gain_dev, float* out_dev, void* hip_stream) {
+  if (!hk_dev || !smooth_dev || !out_dev) return fail(PS_ERR_ARG, "null spectra, bandpass or output");
+  if (n_spec < 0 || n_spec > 65535) return fail(PS_ERR_ARG, "n_spec %lld not in 0..65535", (long long)n_spec);
+  if (n_chan < 1 || n_chan > (int64_t(1) << 31)) return fail(PS_ERR_ARG, "n_chan %lld out of range", (long long)n_chan);
+  if (n_spec == 0) return PS_OK;
+  hipError_t e = ps::launch_bandpass_correct(hk_dev, n_spec, n_chan, smooth_dev, gain_dev, out_dev,
+                                             static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "bandpass correction launch");
+  return PS_OK;
+}
+
+ps_status ps_band_stats(const float* x_dev, int64_t n_spec, int64_t n_chan, double* mean_sd_dev, void* hip_stream) {
+  if (!x_dev || !mean_sd_dev) return fail(PS_ERR_ARG, "null spectra or output");
+  if (n_spec < 0 || n_spec > (int64_t(1) << 31) - 1 || n_chan < 1)
+    return fail(PS_ERR_ARG, "n_spec %lld or n_chan %lld out of range", (long long)n_spec, (long long)n_chan);
+  if (n_spec == 0) return PS_OK;
+  hipError_t e = ps::launch_band_stats(x_dev, n_spec, n_chan, mean_sd_dev, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "band statistics launch");
+  return PS_OK;
+}
+
+ps_status ps_allan(const float* x_dev, int64_t n_points, int64_t point_stride, int64_t n_series,
+                   int64_t series_stride, const int32_t* lags, int32_t n_lags, double spacing, int32_t normalize,
+                   double* out_dev, void* hip_stream) {
+  if (!x_dev || !lags || !out_dev) return fail(PS_ERR_ARG, "null series, lags or output");
+  if (n_lags < 1 || n_lags > ps::kMaxAllanLags) return fail(PS_ERR_ARG, "n_lags %d not in 1..%d", n_lags, ps::kMaxAllanLags);
+  if (n_points < 0 || n_series < 0 || n_series > (int64_t(1) << 31) - 1 || point_stride < 0 || series_stride < 0)
+    return fail(PS_ERR_ARG, "negative size or stride, or too many series");
+  if (!(spacing > 0.0)) return fail(PS_ERR_ARG, "spacing must be positive");
+  ps::AllanArgs a{};
+  for (int i = 0; i < n_lags; ++i) {
+    if (lags[i] < 1) return fail(PS_ERR_ARG, "lag %d is %d (must be >= 1)", i, lags[i]);
+    a.lags[i] = lags[i];
+  }
+  if (n_series == 0) return PS_OK;
+  a.x = x_dev;
+  a.n_points = n_points;
+  a.point_stride = point_stride;
+  a.n_series = n_series;
+  a.series_stride = series_stride;
+  a.n_lags = n_lags;
+  a.normalize = normalize ? 1 : 0;
+  a.spacing = spacing;
+  a.out = out_dev;
+  hipError_t e = ps::launch_allan(a, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "Allan variance launch");
   return PS_OK;
 }
 

@@ -1,0 +1,49 @@
+// Post-integration reductions: launch arguments and launchers (device code in polaris_post.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ps {
+
+constexpr int kMaxAllanLags = 64;
+constexpr int64_t kMaxSplineCoef = 3072;  // basis functions of one bandpass fit (LDS of the solve)
+
+struct ChanAvgArgs {
+  const float* in;          // [n_spec][n_chan]
+  int64_t n_spec, n_chan;
+  int32_t factor;           // channels per bin
+  const uint8_t* flags;     // [n_chan], nonzero = flagged, or nullptr
+  float* out;               // [n_spec][n_chan / factor]
+  int32_t* counts;          // [n_spec][n_chan / factor] or nullptr
+};
+
+struct SplineArgs {
+  const float* h;           // [n_chan]
+  int64_t n_chan, c0, c1;   // fit channels [c0, c1)
+  int32_t K;                // knot spacing (channels)
+  int64_t n_int, n_coef;    // intervals, basis functions (n_int + 3)
+  double* partial;          // [n_int][14]: Gram entries (q <= p) and right-hand sides of each interval
+  double* coef;             // [n_coef]
+  double* lower;            // [n_coef][4]: Cholesky factor, row i holds L[i][i-3 .. i]
+  float* smooth;            // [n_chan]
+};
+
+struct AllanArgs {
+  const float* x;
+  int64_t n_points, point_stride, n_series, series_stride;
+  int32_t n_lags;
+  int32_t normalize;
+  int32_t lags[kMaxAllanLags];
+  double spacing;
+  double* out;              // [n_series][n_lags]
+};
+
+hipError_t launch_channel_average(const ChanAvgArgs& a, hipStream_t s);
+hipError_t launch_bandpass_fit(const SplineArgs& a, hipStream_t s);
+hipError_t launch_bandpass_correct(const float* hk, int64_t n_spec, int64_t n_chan, const float* smooth,
+                                   const double* gain, float* out, hipStream_t s);
+hipError_t launch_band_stats(const float* x, int64_t n_spec, int64_t n_chan, double* mean_sd, hipStream_t s);
+hipError_t launch_allan(const AllanArgs& a, hipStream_t s);
+
+}  // namespace ps

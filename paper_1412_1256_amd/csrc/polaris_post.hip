@@ -1,0 +1,390 @@
+// Post-integration reductions on integrated spectra: channel averaging with flags (Sec. 4), the smoothed
+// bandpass and the bandpass variation (Sec. 3.3.2), band moments and the Allan variances of Eq. 3 / Eq. 4
+// (Sec. 3.3.1, 3.3.3).  These run once per integration or per series on data of a few MB, so they are
+// latency-bound; sums are FP64 in a fixed order (run-to-run identical results).
+#include "polaris_post.h"
+
+#include <math.h>
+
+namespace ps {
+
+namespace {
+
+constexpr int kNT = 256;  // threads per workgroup
+
+// Sum of v over the workgroup in a fixed order: wave butterflies, then wave partials in order.  Every thread
+// gets the result.  sh: kNT / 64 doubles of LDS.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();  // earlier readers of sh are done
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < kNT / 64; ++w) r += sh[w];
+  return r;
+}
+
+__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
+
+// ------------------------------------------------------------------------------------------------
+// channel averaging: bins of `factor` channels, flagged and non-finite channels left out
+
+// factor <= kSpan: a workgroup stages the span of nb = kSpan / factor whole bins of one spectrum in LDS
+// (coalesced loads), then each of its threads sums one bin in channel order.
+constexpr int kSpan = 2048;
+
+__global__ void __launch_bounds__(kNT) k_chan_avg_span(ChanAvgArgs a) {
+  __shared__ float v[kSpan];
+  __shared__ uint8_t ok[kSpan];
+  const int64_t s = blockIdx.y;
+  const int F = a.factor;
+  const int nb = kSpan / F;
+  const int64_t n_bins = a.n_chan / F;
+  const int64_t b0 = (int64_t)blockIdx.x * nb;
+  const int nbl = (int)((n_bins - b0) < nb ? (n_bins - b0) : nb);
+  const int span = nbl * F;
+  const float* row = a.in + s * a.n_chan + b0 * F;
+  for (int i = (int)threadIdx.x; i < span; i += kNT) {
+    const float x = row[i];
+    const bool use = isfinite(x) && !(a.flags && a.flags[b0 * F + i]);
+    v[i] = use ? x : 0.0f;
+    ok[i] = use ? 1 : 0;
+  }
+  __syncthreads();
+  for (int b = (int)threadIdx.x; b < nbl; b += kNT) {
+    double sum = 0.0;
+    int n = 0;
+    for (int i = 0; i < F; ++i) {
+      sum += (double)v[b * F + i];
+      n += ok[b * F + i];
+    }
+    const int64_t o = s * n_bins + b0 + b;
+    a.out[o] = n ? (float)(sum / n) : NAN;
+    if (a.counts) a.counts[o] = n;
+  }
+}
+
+// factor > kSpan: one workgroup per (spectrum, bin)
+__global__ void __launch_bounds__(kNT) k_chan_avg_wide(ChanAvgArgs a) {
+  __shared__ double sh[kNT / 64];
+  const int64_t s = blockIdx.y, b = blockIdx.x;
+  const int64_t n_bins = a.n_chan / a.factor;
+  const int64_t c0 = b * a.factor;
+  double sum = 0.0, n = 0.0;
+  for (int64_t i = threadIdx.x; i < a.factor; i += kNT) {
+    const float x = a.in[s * a.n_chan + c0 + i];
+    if (isfinite(x) && !(a.flags && a.flags[c0 + i])) {
+      sum += (double)x;
+      n += 1.0;
+    }
+  }
+  sum = block_sum(sum, sh);
+  n = block_sum(n, sh);
+  if (threadIdx.x == 0) {
+    a.out[s * n_bins + b] = n > 0.0 ? (float)(sum / n) : NAN;
+    if (a.counts) a.counts[s * n_bins + b] = (int32_t)n;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// smoothed bandpass: least-squares cubic spline, uniform knots every K channels from c0
+
+// the four uniform cubic B-spline pieces at local position u of an interval
+__device__ __forceinline__ void bspline4(double u, double (&b)[4]) {
+  const double u2 = u * u, u3 = u2 * u, v = 1.0 - u;
+  b[0] = v * v * v / 6.0;
+  b[1] = (3.0 * u3 - 6.0 * u2 + 4.0) / 6.0;
+  b[2] = (-3.0 * u3 + 3.0 * u2 + 3.0 * u + 1.0) / 6.0;
+  b[3] = u3 / 6.0;
+}
+
+// one workgroup per knot interval j: the interval's contributions to the normal equations, Gram entries
+// G[q][p] (q <= p, ten of them) of basis functions j + q, j + p and right-hand sides r[q]
+__global__ void __launch_bounds__(kNT) k_spline_gram(SplineArgs a) {
+  __shared__ double sh[kNT / 64];
+  const int64_t j = blockIdx.x;
+  const int64_t lo = a.c0 + j * a.K;
+  const int64_t hi = (lo + a.K) < a.c1 ? (lo + a.K) : a.c1;
+  double g[14];
+#pragma unroll
+  for (int q = 0; q < 14; ++q) g[q] = 0.0;
+  for (int64_t c = lo + threadIdx.x; c < hi; c += kNT) {
+    double b[4];
+    bspline4((double)(c - lo) / (double)a.K, b);
+    const double h = (double)a.h[c];
+    int k = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int p = q; p < 4; ++p) g[k++] += b[q] * b[p];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g[10 + q] += b[q] * h;
+  }
+#pragma unroll
+  for (int q = 0; q < 14; ++q) {
+    const double t = block_sum(g[q], sh);
+    if (threadIdx.x == 0) a.partial[j * 14 + q] = t;
+  }
+}
+
+// index of G[q][p] (q <= p) in an interval's ten Gram entries
+__device__ __forceinline__ int gidx(int q, int p) {
+  constexpr int start[4] = {0, 4, 7, 9};
+  return start[q] + (p - q);
+}
+
+// One workgroup: the threads assemble the banded normal matrix (row i: A[i][i-3 .. i]) and the right-hand
+// side in LDS from the interval partials; one thread then factors A = L L^T (banded Cholesky, keeping the
+// last three rows of L in registers), solves L y = r on the way, and solves L^T a = y backwards.
+__global__ void __launch_bounds__(kNT) k_spline_solve(SplineArgs a) {
+  __shared__ double lds[5 * kMaxSplineCoef];
+  double* A = lds;                  // [n_coef][4], A[i][3 - d] = A(i, i - d)
+  double* r = lds + 4 * a.n_coef;   // [n_coef]
+  const int64_t n = a.n_coef;
+  for (int64_t i = threadIdx.x; i < n; i += kNT) {
+    double row[4] = {0.0, 0.0, 0.0, 0.0}, rhs = 0.0;
+    // intervals j = i - 3 .. i touch basis function i (as j + q, q = i - j)
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = i - q;
+      if (j < 0 || j >= a.n_int) continue;
+      const double* G = a.partial + j * 14;
+      rhs += G[10 + q];
+      for (int p = 0; p <= q; ++p) row[3 - (q - p)] += G[gidx(p, q)];  // A(i, j + p), j + p = i - (q - p)
+    }
+    for (int d = 0; d < 4; ++d) A[i * 4 + d] = row[d];
+    r[i] = rhs;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  // L rows i-3, i-2, i-1 (each as L(k, k-3 .. k)) and y
+  double Lm[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};  // Lm[0] = row i-1, Lm[1] = i-2, Lm[2] = i-3
+  double ym[3] = {0, 0, 0};
+  for (int64_t i = 0; i < n; ++i) {
+    double Li[4];
+    // L(i, i-d) for d = 3, 2, 1, then the diagonal
+    for (int d = 3; d >= 1; --d) {
+      if (i - d < 0) {
+        Li[3 - d] = 0.0;
+        continue;
+      }
+      // sum over k = i-3 .. i-d-1 of L(i, k) L(i-d, k); row i-d is Lm[d-1], its entry L(i-d, k) at 3-(i-d-k)
+      double s = A[i * 4 + 3 - d];
+      for (int e = 3; e > d; --e) {  // k = i - e
+        const double lik = Li[3 - e];
+        const double ldk = Lm[d - 1][3 - (e - d)];
+        s -= lik * ldk;
+      }
+      Li[3 - d] = s / Lm[d - 1][3];
+    }
+    double dg = A[i * 4 + 3];
+    for (int e = 1; e <= 3; ++e) dg -= Li[3 - e] * Li[3 - e];
+    Li[3] = sqrt(dg);
+    double y = r[i];
+    for (int e = 1; e <= 3; ++e) y -= Li[3 - e] * ym[e - 1];
+    y /= Li[3];
+    for (int q = 0; q < 4; ++q) a.lower[i * 4 + q] = Li[q];
+    r[i] = y;
+    for (int q = 0; q < 4; ++q) {
+      Lm[2][q] = Lm[1][q];
+      Lm[1][q] = Lm[0][q];
+      Lm[0][q] = Li[q];
+    }
+    ym[2] = ym[1];
+    ym[1] = ym[0];
+    ym[0] = y;
+  }
+  // L^T a = y: a_i = (y_i - sum_{e=1..3} L(i+e, i) a_{i+e}) / L(i, i)
+  double am[3] = {0, 0, 0};  // a_{i+1}, a_{i+2}, a_{i+3}
+  for (int64_t i = n - 1; i >= 0; --i) {
+    double s = r[i];
+    for (int e = 1; e <= 3; ++e)
+      if (i + e < n) s -= a.lower[(i + e) * 4 + 3 - e] * am[e - 1];
+    const double ai = s / a.lower[i * 4 + 3];
+    a.coef[i] = ai;
+    am[2] = am[1];
+    am[1] = am[0];
+    am[0] = ai;
+  }
+}
+
+__global__ void __launch_bounds__(kNT) k_spline_eval(SplineArgs a) {
+  const int64_t c = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (c >= a.n_chan) return;
+  if (c < a.c0 || c >= a.c1) {
+    a.smooth[c] = NAN;
+    return;
+  }
+  const int64_t j = (c - a.c0) / a.K;
+  double b[4];
+  bspline4((double)(c - a.c0 - j * a.K) / (double)a.K, b);
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v += a.coef[j + q] * b[q];
+  a.smooth[c] = (float)v;
+}
+
+// ------------------------------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kNT) k_bandpass_correct(const float* __restrict__ hk, int64_t n_chan,
+                                                          const float* __restrict__ smooth,
+                                                          const double* __restrict__ gain,
+                                                          float* __restrict__ out) {
+  const int64_t s = blockIdx.y;
+  const int64_t c = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (c >= n_chan) return;
+  const double g = gain ? gain[s] : 1.0;
+  out[s * n_chan + c] = (float)((double)hk[s * n_chan + c] / (g * (double)smooth[c]));
+}
+
+// one workgroup per spectrum: mean of the finite channels, then the root mean square deviation from it
+__global__ void __launch_bounds__(kNT) k_band_stats(const float* __restrict__ x, int64_t n_chan,
+                                                    double* __restrict__ mean_sd) {
+  __shared__ double sh[kNT / 64];
+  const float* row = x + (int64_t)blockIdx.x * n_chan;
+  double s = 0.0, n = 0.0;
+  for (int64_t c = threadIdx.x; c < n_chan; c += kNT) {
+    const float v = row[c];
+    if (isfinite(v)) {
+      s += (double)v;
+      n += 1.0;
+    }
+  }
+  s = block_sum(s, sh);
+  n = block_sum(n, sh);
+  const double m = n > 0.0 ? s / n : NAN;
+  double q = 0.0;
+  for (int64_t c = threadIdx.x; c < n_chan; c += kNT) {
+    const float v = row[c];
+    if (isfinite(v)) q += ((double)v - m) * ((double)v - m);
+  }
+  q = block_sum(q, sh);
+  if (threadIdx.x == 0) {
+    mean_sd[2 * blockIdx.x] = m;
+    mean_sd[2 * blockIdx.x + 1] = n > 0.0 ? sqrt(q / n) : NAN;
+  }
+}
+
+// Eq. 3 / Eq. 4: one workgroup per series; per lag L the mean over t of the squared second difference
+// (t - L, t, t + L all finite), over 2 (L spacing)^2, divided by the squared series mean when normalised.
+__global__ void __launch_bounds__(kNT) k_allan(AllanArgs a) {
+  __shared__ double sh[kNT / 64];
+  const float* x = a.x + (int64_t)blockIdx.x * a.series_stride;
+  const int64_t P = a.n_points, st = a.point_stride;
+  double mean2 = 1.0;
+  if (a.normalize) {
+    double s = 0.0, n = 0.0;
+    for (int64_t t = threadIdx.x; t < P; t += kNT) {
+      const float v = x[t * st];
+      if (isfinite(v)) {
+        s += (double)v;
+        n += 1.0;
+      }
+    }
+    s = block_sum(s, sh);
+    n = block_sum(n, sh);
+    const double m = s / n;
+    mean2 = m * m;
+  }
+  for (int l = 0; l < a.n_lags; ++l) {
+    const int64_t L = a.lags[l];
+    double s = 0.0, n = 0.0;
+    if (L >= 1 && 2 * L < P) {
+      for (int64_t t = L + threadIdx.x; t < P - L; t += kNT) {
+        const double d = (double)x[(t + L) * st] - 2.0 * (double)x[t * st] + (double)x[(t - L) * st];
+        if (finite(d)) {
+          s += d * d;
+          n += 1.0;
+        }
+      }
+    }
+    s = block_sum(s, sh);
+    n = block_sum(n, sh);
+    if (threadIdx.x == 0) {
+      const double tau = (double)L * a.spacing;
+      a.out[(int64_t)blockIdx.x * a.n_lags + l] = n > 0.0 ? s / n / (2.0 * tau * tau) / mean2 : NAN;
+    }
+  }
+}
+
+// The same for series stored side by side (series_stride 1, e.g. one series per channel of a run of
+// integrations [t][channel]): one thread per series, so a wave's loads are consecutive addresses; sums in
+// t order.
+__global__ void __launch_bounds__(kNT) k_allan_cols(AllanArgs a) {
+  const int64_t s = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (s >= a.n_series) return;
+  const float* x = a.x + s;
+  const int64_t P = a.n_points, st = a.point_stride;
+  double mean2 = 1.0;
+  if (a.normalize) {
+    double sum = 0.0, n = 0.0;
+    for (int64_t t = 0; t < P; ++t) {
+      const float v = x[t * st];
+      if (isfinite(v)) {
+        sum += (double)v;
+        n += 1.0;
+      }
+    }
+    const double m = sum / n;
+    mean2 = m * m;
+  }
+  for (int l = 0; l < a.n_lags; ++l) {
+    const int64_t L = a.lags[l];
+    double sum = 0.0, n = 0.0;
+    if (L >= 1 && 2 * L < P) {
+      for (int64_t t = L; t < P - L; ++t) {
+        const double d = (double)x[(t + L) * st] - 2.0 * (double)x[t * st] + (double)x[(t - L) * st];
+        if (finite(d)) {
+          sum += d * d;
+          n += 1.0;
+        }
+      }
+    }
+    const double tau = (double)L * a.spacing;
+    a.out[s * a.n_lags + l] = n > 0.0 ? sum / n / (2.0 * tau * tau) / mean2 : NAN;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_channel_average(const ChanAvgArgs& a, hipStream_t s) {
+  const int64_t n_bins = a.n_chan / a.factor;
+  if (a.factor <= kSpan) {
+    const int nb = kSpan / a.factor;
+    const dim3 grid((unsigned)((n_bins + nb - 1) / nb), (unsigned)a.n_spec);
+    hipLaunchKernelGGL(k_chan_avg_span, grid, dim3(kNT), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_chan_avg_wide, dim3((unsigned)n_bins, (unsigned)a.n_spec), dim3(kNT), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bandpass_fit(const SplineArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_spline_gram, dim3((unsigned)a.n_int), dim3(kNT), 0, s, a);
+  hipLaunchKernelGGL(k_spline_solve, dim3(1), dim3(kNT), 0, s, a);
+  hipLaunchKernelGGL(k_spline_eval, dim3((unsigned)((a.n_chan + kNT - 1) / kNT)), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bandpass_correct(const float* hk, int64_t n_spec, int64_t n_chan, const float* smooth,
+                                   const double* gain, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_bandpass_correct, dim3((unsigned)((n_chan + kNT - 1) / kNT), (unsigned)n_spec), dim3(kNT), 0,
+                     s, hk, n_chan, smooth, gain, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_stats(const float* x, int64_t n_spec, int64_t n_chan, double* mean_sd, hipStream_t s) {
+  hipLaunchKernelGGL(k_band_stats, dim3((unsigned)n_spec), dim3(kNT), 0, s, x, n_chan, mean_sd);
+  return hipGetLastError();
+}
+
+hipError_t launch_allan(const AllanArgs& a, hipStream_t s) {
+  if (a.series_stride == 1 && a.point_stride >= a.n_series && a.n_series >= 64)
+    hipLaunchKernelGGL(k_allan_cols, dim3((unsigned)((a.n_series + kNT - 1) / kNT)), dim3(kNT), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_allan, dim3((unsigned)a.n_series), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace ps

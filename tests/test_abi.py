@@ -182,3 +182,28 @@ def test_plan_accepts_apodisation_windows(window):
     st, h, n = _plan(window=window, fft_len=1 << 16, precision="fp16", accum="kahan32")
     assert st == 0, pk.lib().ps_last_error()
     pk.lib().ps_destroy(h)
+
+
+def test_post_reduction_argument_errors():
+    """Validation happens before any launch (dummy device addresses are never touched)."""
+    L = pk.lib()
+    p = C.c_void_p(1 << 20)
+    assert pk.STATUS[L.ps_channel_average(p, 4, 1000, 3, None, p, None, None)] == "PS_ERR_SIZE"
+    assert pk.STATUS[L.ps_channel_average(None, 4, 1024, 4, None, p, None, None)] == "PS_ERR_ARG"
+    assert pk.STATUS[L.ps_channel_average(p, 70000, 1024, 4, None, p, None, None)] == "PS_ERR_ARG"
+    assert L.ps_channel_average(p, 0, 1024, 4, None, p, None, None) == 0  # nothing to do
+    n = C.c_size_t()
+    assert L.ps_bandpass_work_bytes(131072, 128, 0.06, C.byref(n)) == 0
+    n_int = -(-(131072 - 2 * 7864) // 128)
+    assert n.value >= (n_int * 14 + (n_int + 3) * 5) * 8
+    assert pk.STATUS[L.ps_bandpass_work_bytes(131072, 16, 0.0, C.byref(n))] == "PS_ERR_UNSUPPORTED"
+    assert pk.STATUS[L.ps_bandpass_work_bytes(500, 128, 0.06, C.byref(n))] == "PS_ERR_SIZE"  # 440 < 4 x 128
+    assert pk.STATUS[L.ps_bandpass_work_bytes(131072, 2, 0.06, C.byref(n))] == "PS_ERR_ARG"
+    assert pk.STATUS[L.ps_bandpass_work_bytes(131072, 128, 0.5, C.byref(n))] == "PS_ERR_ARG"
+    assert pk.STATUS[L.ps_bandpass_fit(p, 131072, 128, 0.06, p, 16, p, None)] == "PS_ERR_WORKSPACE"
+    lags = (C.c_int32 * 2)(1, 0)
+    assert pk.STATUS[L.ps_allan(p, 100, 1, 1, 100, lags, 2, 1.0, 0, p, None)] == "PS_ERR_ARG"
+    assert pk.STATUS[L.ps_allan(p, 100, 1, 1, 100, lags, 0, 1.0, 0, p, None)] == "PS_ERR_ARG"
+    lags = (C.c_int32 * 1)(1)
+    assert pk.STATUS[L.ps_allan(p, 100, 1, 1, 100, lags, 1, 0.0, 0, p, None)] == "PS_ERR_ARG"
+    assert pk.STATUS[L.ps_band_stats(p, 1, 0, p, None)] == "PS_ERR_ARG"
