@@ -456,6 +456,44 @@ def modes_form(pk, torch, dev, steps, ring_n):
     return res
 
 
+def short_form(pk, torch, dev, steps):
+    """Short transforms (two int8 streams, 2^24 samples per stream per integration, streamed from a ring of
+    HBM-resident buffers): the single pass (whole frames in LDS, up to 2^12 points) against the four-step
+    passes, whole integrations including Stokes."""
+    import synth
+    res = {}
+    for m in (8, 10, 12, 14):
+        N = 1 << m
+        d = synth.make_correlated_noise(8, 0.3, N, (1 << 24) // N, seed_extra=m)
+        packed = torch.from_numpy(d["packed"]).to(dev)
+        ring = [packed] + [packed.clone() for _ in range(23)]
+        r = {}
+        for name, sched in (("single_pass", pk.Schedule(single_pass=1)), ("four_step", pk.Schedule(single_pass=2))):
+            if name == "single_pass" and m > 12:
+                continue
+            side = torch.cuda.Stream(dev)
+            with torch.cuda.stream(side):
+                plan = pk.Plan([pk.Instance.from_synth(d)], device=dev, stream=side, schedules=[sched])
+                out = torch.empty((1, 4, N // 2), dtype=torch.float32, device=dev)
+            pos = [0]
+
+            def step():
+                plan.reset()
+                plan.accumulate(ring[pos[0] % len(ring)])
+                pos[0] += 1
+                plan.stokes(out=out)
+
+            with torch.cuda.stream(side):
+                t = time_steps(torch, dev, step, steps, 3)
+            r[f"{name}_us"] = t * 1e6
+            r[f"{name}_Gsamples_per_s"] = d["n_samples"] * 2 / t / 1e9
+        if "single_pass_us" in r:
+            r["speedup"] = r["four_step_us"] / r["single_pass_us"]
+        res[f"2^{m}"] = r
+        del ring, packed
+    return res
+
+
 def post_form(pk, torch, dev, reps):
     """The post-integration reductions at the paper's sizes (device time per call, events on the current
     stream): channel averaging of one integration's Stokes spectra 131072 -> 4096 channels with a flagged
@@ -624,6 +662,7 @@ def main():
     out["overlap_form"] = overlap_form(pk, torch, dev, inst, ring, max(8, args.steps // 2))
     out["table1_modes"] = modes_form(pk, torch, dev, max(8, args.steps // 2), args.ring)
     out["post_reduction"] = post_form(pk, torch, dev, 10)
+    out["short_transforms"] = short_form(pk, torch, dev, max(5, args.steps // 4))
     if not args.no_batching:
         out["batching_form"] = batching_form(pk, torch, dev, max(3, args.steps // 10))
     if not args.no_precision:

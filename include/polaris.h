@@ -142,9 +142,15 @@ ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_
  *   colpass_cols    columns per column-pass workgroup (its LDS tile width and workgroup size);
  *   rowpass_frames  frames per row-pass workgroup batch (its workgroup size);
  *   col_wg_per_cu   column-pass workgroups per CU that the frame grouping aims at (1 .. 8);
- *   rowpass_slots   accumulator slots G (a power of two, 1 .. 64): frame a of the integration goes to slot
- *                   a mod G, so G frame groups run the row pass in parallel; readers sum the slots in
- *                   order.  Default: enough for about 256 row-pass workgroups (1 for 16-bit passes).
+ *   rowpass_slots   accumulator slots G (a power of two, 1 .. 64; 1 .. 8192 in a single pass): frame a of
+ *                   the integration goes to slot a mod G, so G frame groups run in parallel; readers sum the
+ *                   slots in order.  Default: enough for about 256 row-pass workgroups (1 for 16-bit
+ *                   passes; 2^21 / (N n_pairs) rounded down to a power of two, at most 8192, in a
+ *                   single pass).
+ *   single_pass     0: the default (a single pass for FP32 transforms of 2^8 .. 2^12 points, else the
+ *                   four-step passes); 1: a single pass (each workgroup transforms whole frames in LDS
+ *                   and accumulates their products; 2^8 .. 2^12 points, FP32; only log2_n1 and
+ *                   rowpass_slots apply); 2: the four-step column and row passes.
  * The results of every schedule agree within rounding; only speed differs.
  */
 typedef struct {
@@ -153,6 +159,7 @@ typedef struct {
   int32_t rowpass_frames;
   int32_t col_wg_per_cu;
   int32_t rowpass_slots;
+  int32_t single_pass;
 } ps_schedule;
 
 /* ps_plan with one schedule per instance (sched may be NULL).  PS_ERR_UNSUPPORTED for a schedule that has

@@ -52,7 +52,7 @@ class _CalGrad(C.Structure):
 
 class _Schedule(C.Structure):
     _fields_ = [("log2_n1", C.c_int32), ("colpass_cols", C.c_int32), ("rowpass_frames", C.c_int32),
-                ("col_wg_per_cu", C.c_int32), ("rowpass_slots", C.c_int32)]
+                ("col_wg_per_cu", C.c_int32), ("rowpass_slots", C.c_int32), ("single_pass", C.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -63,10 +63,11 @@ class Schedule:
     rowpass_frames: int = 0
     col_wg_per_cu: int = 0
     rowpass_slots: int = 0
+    single_pass: int = 0  # 0 default, 1 whole frames in LDS (2^8 .. 2^12 points, FP32), 2 four-step passes
 
     def to_c(self) -> _Schedule:
         return _Schedule(self.log2_n1, self.colpass_cols, self.rowpass_frames, self.col_wg_per_cu,
-                         self.rowpass_slots)
+                         self.rowpass_slots, self.single_pass)
 
 
 def schedule_candidates(instance) -> list:
@@ -76,7 +77,7 @@ def schedule_candidates(instance) -> list:
     _check(lib().ps_schedule_candidates(C.byref(c), None, 0, C.byref(n)))
     arr = (_Schedule * max(1, n.value))()
     _check(lib().ps_schedule_candidates(C.byref(c), arr, n.value, C.byref(n)))
-    return [Schedule(a.log2_n1, a.colpass_cols, a.rowpass_frames, a.col_wg_per_cu, a.rowpass_slots)
+    return [Schedule(a.log2_n1, a.colpass_cols, a.rowpass_frames, a.col_wg_per_cu, a.rowpass_slots, a.single_pass)
             for a in arr[:n.value]]
 
 

@@ -14,7 +14,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for every device pass
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"--offload-arch={ARCH}"]
-SOURCES = ["polaris_kernels.hip", "polaris_backward.hip", "polaris_mfma.hip", "polaris_post.hip", "polaris_api.cpp"]
+SOURCES = ["polaris_kernels.hip", "polaris_backward.hip", "polaris_mfma.hip", "polaris_post.hip", "polaris_fused.hip", "polaris_api.cpp"]
 
 
 def build(verbose: bool = False) -> str:

@@ -17,6 +17,7 @@
 #include "../../include/polaris.h"
 #include "polaris_internal.h"
 #include "polaris_post.h"
+#include "polaris_fused.h"
 
 namespace {
 
@@ -75,6 +76,10 @@ struct Inst {
   // column-pass workgroups per CU aimed at by the frame grouping
   int cols = 0, fb = 0, col_wgs = 1;
   int G = 1;  // accumulator slots (row-pass frame groups)
+  // single pass: whole frames transformed in LDS (short FP32 transforms), with the table W_N^m, m < N
+  bool fused = false;
+  size_t off_tw_full = 0;
+  std::vector<float> tw_full;
   // level histograms (total power): counted by the column pass while on; zeroed by the first accumulate
   // after a reset
   bool hist_on = false, hist_zeroed = false;
@@ -100,6 +105,9 @@ struct Inst {
   size_t slot_doubles() const { return (size_t)cfg.n_pairs * (size_t)(N1 / 2) * 4 * (size_t)N2; }
   size_t acc_bytes() const { return (size_t)G * slot_doubles() * sizeof(double); }
   int slots_used() const { return (int)std::min<int64_t>(G, n_frames); }
+  // readers of more than kDirectSlots slots take their sum from a reduction into one slot
+  size_t off_sumacc = 0, off_sumpart = 0;
+  bool use_reduced() const { return slots_used() > ps::kDirectSlots; }
 };
 
 }  // namespace
@@ -257,6 +265,7 @@ void build_tables(Inst& I) {
     stage_twiddles(I.tws_col, I.N1);
     stage_twiddles(I.tws_row, I.N2);
   }
+  if (I.fused) twiddle_table(I.tw_full, I.N, I.N);  // W_N^m, m < N
   twiddle_table(I.tw_col, I.N1, I.N1);
   twiddle_table(I.tw_row, I.N2, I.N2);
   twiddle_table(I.tw_lo, I.N, I.N2);  // W_N^m, m < N2; W_N^(q*N2) = W_N1^q reuses tw_col
@@ -279,6 +288,7 @@ void build_tables(Inst& I) {
     s = (double)I.N;
   } else {
     s = (double)I.N;
+    if (I.fused) I.win.assign((size_t)I.N, 1.0f);  // the single pass always reads a window table
   }
   I.sumw2 = s;
 }
@@ -325,6 +335,26 @@ ps_status upload(ps_plan_t plan, size_t off, const void* src, size_t bytes) {
 
 // Accumulator slots: enough row-pass frame groups that units x pairs x slots reach about 256 workgroups
 // (1 for the 16-bit passes, whose row pass spreads frames over its waves).
+// the single pass runs FP32 transforms of 2^8 .. 2^14 points
+bool fused_eligible(const ps_instance& c) {
+  const int m = ilog2_exact(c.fft_len);
+  return c.precision == PS_PREC_FP32 && m >= ps::kFusedMinLog2 && m <= ps::kFusedMaxLog2;
+}
+
+bool uses_fused(const ps_instance& c, const ps_schedule* s) {
+  if (!fused_eligible(c)) return false;
+  return !s || s->single_pass != 2;
+}
+
+// N/8-thread workgroups, one per slot and pair: about 2^21 / N of them (some 4000 waves) fill the device,
+// and the slots then hold 32 MiB whatever N is
+int default_slots_fused(const ps_instance& c) {
+  const int64_t target = (int64_t(1) << 21) / c.fft_len;
+  int G = 1;
+  while (2 * G * c.n_pairs <= target && 2 * G <= 8192) G *= 2;
+  return G;
+}
+
 int default_slots(const ps_instance& c, int N1, int N2) {
   if (c.precision != PS_PREC_FP32) return 1;
   const int tiles = N1 / 2 / ps::rowpass_units_per_tile(N2) * c.n_pairs;
@@ -339,6 +369,30 @@ const char* schedule_error(const ps_instance& c, const ps_schedule& s, char* why
   char* w = why ? why : buf;
   const int m = ilog2_exact(c.fft_len);
   const int m1 = s.log2_n1 ? s.log2_n1 : m / 2, m2 = m - m1;
+  if (s.single_pass < 0 || s.single_pass > 2) {
+    snprintf(w, 160, "single_pass %d not in 0..2", s.single_pass);
+    return w;
+  }
+  if (s.single_pass == 1 && !fused_eligible(c)) {
+    snprintf(w, 160, "the single pass runs FP32 transforms of 2^%d .. 2^%d points", ps::kFusedMinLog2,
+             ps::kFusedMaxLog2);
+    return w;
+  }
+  if (uses_fused(c, &s)) {
+    if (s.colpass_cols || s.rowpass_frames || s.col_wg_per_cu) {
+      snprintf(w, 160, "a single pass takes only log2_n1 and rowpass_slots");
+      return w;
+    }
+    if (m1 < 4 || m2 < 4) {
+      snprintf(w, 160, "split 2^%d x 2^%d: both factors at least 2^4", m1, m2);
+      return w;
+    }
+    if (s.rowpass_slots < 0 || s.rowpass_slots > 8192 || (s.rowpass_slots & (s.rowpass_slots - 1))) {
+      snprintf(w, 160, "rowpass_slots %d is not a power of two in 1..8192", s.rowpass_slots);
+      return w;
+    }
+    return nullptr;
+  }
   if (c.precision != PS_PREC_FP32) {
     if (m1 != m / 2 || s.colpass_cols || s.rowpass_frames || s.col_wg_per_cu > 1 || s.rowpass_slots > 1) {
       snprintf(w, 160, "16-bit passes run with the default schedule only");
@@ -469,7 +523,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
   int64_t rounds = 0;
   for (size_t i = 0; i < plan->inst.size(); ++i) {
     const Inst& I = plan->inst[i];
-    if (I.mx() || I.hist_on) continue;
+    if (I.mx() || I.hist_on || I.fused) continue;
     const int64_t F = I.frames_in(n_samples[i]);
     rounds = std::max(rounds, (F + I.chunk - 1) / I.chunk);
   }
@@ -498,7 +552,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
     std::vector<std::pair<std::vector<int>, std::vector<Member>>> classes;
     for (size_t i = 0; i < plan->inst.size(); ++i) {
       const Inst& I = plan->inst[i];
-      if (I.mx() || I.hist_on) continue;
+      if (I.mx() || I.hist_on || I.fused) continue;
       const int64_t F = I.frames_in(n_samples[i]), f0 = r * I.chunk;
       if (f0 >= F) continue;
       const int nf = (int)std::min<int64_t>(I.chunk, F - f0);
@@ -571,7 +625,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
   }
   for (size_t i = 0; i < plan->inst.size(); ++i) {
     Inst& I = plan->inst[i];
-    if (I.mx() || I.hist_on) continue;
+    if (I.mx() || I.hist_on || I.fused) continue;
     done[i] = 1;
     const int64_t F = I.frames_in(n_samples[i]);
     if (F > 0) {
@@ -630,6 +684,36 @@ ps_status accumulate_mx(ps_plan_t plan, Inst& I, const ps::ColArgs& ca) {
 // Frames 0 .. F-1 of the buffer at base (frame f at sample f * hop) in chunks of the instance's chunk size:
 // the column and row passes (or their 16-bit forms) of each chunk, frames in order.
 ps_status run_frames(ps_plan_t plan, Inst& I, const uint8_t* base, int64_t F) {
+  if (I.fused && !I.hist_on) {
+    // single pass: no inter-pass buffer, so one launch takes up to 2^28 frames
+    constexpr int64_t kMaxFused = int64_t(1) << 28;
+    for (int64_t f0 = 0; f0 < F; f0 += kMaxFused) {
+      const int nf = (int)std::min<int64_t>(kMaxFused, F - f0);
+      ps::FusedArgs fa{};
+      fa.in = base + f0 * I.hop * I.bits_per_sample() / 8;
+      fa.hop = I.hop;
+      fa.S = I.cfg.n_streams;
+      fa.P = I.cfg.n_pairs;
+      for (int p = 0; p < 4; ++p) {
+        fa.px[p] = I.cfg.pair_x[p];
+        fa.py[p] = I.cfg.pair_y[p];
+      }
+      fa.n_frames = nf;
+      fa.win = ws_ptr<float>(plan, I.off_win);  // a table of ones for the rectangular window
+      fa.tw = ws_ptr<float2>(plan, I.off_tw_full);
+      fa.acc = ws_ptr<double>(plan, I.off_acc);
+      fa.G = I.G;
+      fa.N1 = (int32_t)I.N1;
+      fa.N2 = (int32_t)I.N2;
+      fa.F0 = I.n_frames;
+      fa.slot_stride = (int64_t)I.slot_doubles();
+      hipError_t e = timed(plan, PS_KERNEL_COLPASS, [&](const ps::Launch& l) { return ps::launch_fused((int)I.N, I.cfg.bits, fa, l); });
+      if (e != hipSuccess) return hip_fail(e, "single-pass launch");
+      I.first = false;
+      I.n_frames += nf;
+    }
+    return PS_OK;
+  }
   for (int64_t f0 = 0; f0 < F; f0 += I.chunk) {
     const int nf = (int)((F - f0) < I.chunk ? (F - f0) : I.chunk);
     int mode = 0;
@@ -688,8 +772,12 @@ ps_status ps_schedule_candidates(const ps_instance* inst, ps_schedule* out, int3
   std::vector<ps_schedule> v;
   const int m = ilog2_exact(inst->fft_len);
   if (inst->precision != PS_PREC_FP32) {
-    v.push_back(ps_schedule{m / 2, 0, 0, 0, 1});
+    v.push_back(ps_schedule{m / 2, 0, 0, 0, 1, 0});
   } else {
+    if (fused_eligible(*inst)) {
+      const int G0 = default_slots_fused(*inst);
+      for (int G = std::max(1, G0 / 4); G <= std::min(8192, 2 * G0); G *= 2) v.push_back(ps_schedule{m / 2, 0, 0, 0, G, 1});
+    }
     for (int m1 = m / 2 - 1; m1 <= m / 2 + 1; ++m1) {
       const int N1 = 1 << m1, N2 = 1 << (m - m1);
       if (m1 < 4 || m - m1 < 4 || m1 > 11 || m - m1 > 11) continue;
@@ -698,7 +786,7 @@ ps_status ps_schedule_candidates(const ps_instance* inst, ps_schedule* out, int3
         for (int fb = 2; fb <= 8; fb *= 2)
           for (int wg = 1; wg <= 4; wg *= 2)
             for (int G = std::max(1, G0 / 2); G <= std::min(64, 2 * G0); G *= 2) {
-              const ps_schedule c{m1, cols, fb, wg, G};
+              const ps_schedule c{m1, cols, fb, wg, G, fused_eligible(*inst) ? 2 : 0};
               if (schedule_error(*inst, c, nullptr) == nullptr) v.push_back(c);
             }
     }
@@ -740,7 +828,9 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
     I.cols = (sched && sched[i].colpass_cols) ? sched[i].colpass_cols : ps::colpass_cols((int)I.N1);
     I.fb = (sched && sched[i].rowpass_frames) ? sched[i].rowpass_frames : ps::rowpass_frames((int)I.N2);
     I.col_wgs = (sched && sched[i].col_wg_per_cu) ? sched[i].col_wg_per_cu : 1;
-    I.G = (sched && sched[i].rowpass_slots) ? sched[i].rowpass_slots : default_slots(I.cfg, (int)I.N1, (int)I.N2);
+    I.fused = uses_fused(I.cfg, sched ? &sched[i] : nullptr);
+    I.G = (sched && sched[i].rowpass_slots) ? sched[i].rowpass_slots
+                                             : (I.fused ? default_slots_fused(I.cfg) : default_slots(I.cfg, (int)I.N1, (int)I.N2));
     // short transforms take more frames per pass (inter-pass buffer of at most 32 MiB per pair)
     I.chunk = inst[i].chunk_frames ? inst[i].chunk_frames : (int64_t)std::max<int64_t>(64, (int64_t(1) << 22) / I.N);
     // word loads of the column pass: 2-, 4- and 8-bit codes of two streams correlated as (0, 1), or of four
@@ -764,9 +854,14 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
       I.off_tws_row = off; off = align_up(off + I.tws_row.size() * 4);
     }
     I.off_hist = off; off = align_up(off + (size_t)I.cfg.n_pairs * 2 * (size_t)I.hist_bins() * 8);
+    I.off_tw_full = off; off = align_up(off + I.tw_full.size() * 4);
     I.off_stage = off; off = align_up(off + 2 * I.tail_bytes());
     I.off_T = off; off = align_up(off + (size_t)I.chunk * (size_t)I.cfg.n_pairs * (size_t)I.N * 8);
     I.off_acc = off; off = align_up(off + I.acc_bytes());
+    if (I.G > ps::kDirectSlots) {
+      I.off_sumacc = off; off = align_up(off + I.slot_doubles() * 8);
+      I.off_sumpart = off; off = align_up(off + (size_t)ps::slot_reduce_chunks(I.G) * I.slot_doubles() * 8);
+    }
     const size_t U = (size_t)(I.N1 / 2), P = (size_t)I.cfg.n_pairs;
     I.off_red = off; off = align_up(off + P * U * 5 * sizeof(double));
     I.off_norm = off; off = align_up(off + P * sizeof(double));
@@ -818,6 +913,7 @@ ps_status ps_bind(ps_plan_t plan, void* workspace_dev, size_t bytes, void* hip_s
     if ((st = upload(plan, I.off_tw_lo, I.tw_lo.data(), I.tw_lo.size() * 4)) != PS_OK) return st;
     if ((st = upload(plan, I.off_win, I.win.data(), I.win.size() * 4)) != PS_OK) return st;
     if ((st = upload(plan, I.off_sumw2, &I.sumw2, 8)) != PS_OK) return st;
+    if ((st = upload(plan, I.off_tw_full, I.tw_full.data(), I.tw_full.size() * 4)) != PS_OK) return st;
     if (I.mx()) {
       if ((st = upload(plan, I.off_mx16, I.mx16.data(), I.mx16.size() * 4)) != PS_OK) return st;
       if ((st = upload(plan, I.off_mx32, I.mx32.data(), I.mx32.size() * 4)) != PS_OK) return st;
@@ -920,10 +1016,22 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
   return PS_OK;
 }
 
+// Sum the slots of an instance that uses many of them into one (readers then see a single slot).
+static ps_status reduce_slots(ps_plan_t plan, const Inst& I) {
+  if (!I.use_reduced()) return PS_OK;
+  hipError_t e = timed(plan, PS_KERNEL_OTHER, [&](const ps::Launch& l) {
+    return ps::launch_slot_reduce(ws_ptr<double>(plan, I.off_acc), (int64_t)I.slot_doubles(), I.slots_used(),
+                                  (int64_t)I.slot_doubles(), ws_ptr<double>(plan, I.off_sumpart),
+                                  ws_ptr<double>(plan, I.off_sumacc), l);
+  });
+  if (e != hipSuccess) return hip_fail(e, "slot reduction launch");
+  return PS_OK;
+}
+
 static ps::OutArgs out_args(ps_plan_t plan, const Inst& I) {
   ps::OutArgs o{};
-  o.acc = ws_ptr<double>(plan, I.off_acc);
-  o.slots = I.slots_used();
+  o.acc = ws_ptr<double>(plan, I.use_reduced() ? I.off_sumacc : I.off_acc);
+  o.slots = I.use_reduced() ? 1 : I.slots_used();
   o.slot_stride = (int64_t)I.slot_doubles();
   o.N1 = (int32_t)I.N1;
   o.N2 = (int32_t)I.N2;
@@ -939,6 +1047,7 @@ ps_status ps_spectra(ps_plan_t plan, int32_t inst, double* out_dev, int64_t* n_f
   const Inst& I = plan->inst[(size_t)inst];
   if (!out_dev) return fail(PS_ERR_ARG, "null output");
   if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %d has no accumulated frames", inst);
+  if ((st = reduce_slots(plan, I)) != PS_OK) return st;
   ps::OutArgs o = out_args(plan, I);
   o.spectra = out_dev;
   hipError_t e = timed(plan, PS_KERNEL_SPECTRA, [&](const ps::Launch& l) { return ps::launch_spectra(o, l); });
@@ -954,6 +1063,9 @@ ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv
   const Inst& I = plan->inst[(size_t)inst];
   if (!iquv_dev) return fail(PS_ERR_ARG, "null output");
   if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %d has no accumulated frames", inst);
+  if (cal && cal->feed != PS_FEED_LINEAR && cal->feed != PS_FEED_CIRCULAR)
+    return fail(PS_ERR_ARG, "unknown feed %d", cal->feed);
+  if ((st = reduce_slots(plan, I)) != PS_OK) return st;
   ps::OutArgs o = out_args(plan, I);
   o.n_frames = (double)I.n_frames;
   o.sumw2_dev = ws_ptr<double>(plan, I.off_sumw2);
@@ -961,8 +1073,6 @@ ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv
   const double psi = cal ? cal->psi : 0.0;
   o.cos2psi = std::cos(2.0 * psi);
   o.sin2psi = std::sin(2.0 * psi);
-  if (cal && cal->feed != PS_FEED_LINEAR && cal->feed != PS_FEED_CIRCULAR)
-    return fail(PS_ERR_ARG, "unknown feed %d", cal->feed);
   o.circular = (cal && cal->feed == PS_FEED_CIRCULAR) ? 1 : 0;
   if (cal) {
     o.gain_x = cal->gain_x;
@@ -1007,6 +1117,8 @@ ps_status ps_stokes_all(ps_plan_t plan, const ps_cal* cal, float* const* iquv_de
     ends.push_back(total);
   }
   if (outs.empty()) return PS_OK;
+  for (size_t i = 0; i < plan->inst.size(); ++i)
+    if (iquv_dev[i] && (st = reduce_slots(plan, plan->inst[i])) != PS_OK) return st;
   std::vector<unsigned char> img;
   append_bytes(img, outs.data(), outs.size());
   const size_t ends_at = img.size();
@@ -1136,9 +1248,10 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
                   (long long)I.frames_in(n_samples), (long long)I.n_frames);
   }
   if (I.N2 > 512) return fail(PS_ERR_UNSUPPORTED, "the adjoint is built for fft_len <= 2^18");
+  if ((st = reduce_slots(plan, I)) != PS_OK) return st;
   ps::BwChanArgs ca{};
-  ca.acc = ws_ptr<double>(plan, I.off_acc);
-  ca.slots = I.slots_used();
+  ca.acc = ws_ptr<double>(plan, I.use_reduced() ? I.off_sumacc : I.off_acc);
+  ca.slots = I.use_reduced() ? 1 : I.slots_used();
   ca.slot_stride = (int64_t)I.slot_doubles();
   ca.N1 = (int32_t)I.N1;
   ca.P = I.cfg.n_pairs;

@@ -139,8 +139,13 @@ def test_schedule_candidates_and_scheduled_plans():
     # 16-bit passes: default schedule only
     assert pk.schedule_candidates(pk.Instance(fft_len=1 << 18, precision="fp16")) == [pk.Schedule(9, 0, 0, 0, 1)]
     # accumulator slots around the default (which targets about 256 row-pass workgroups)
-    small = {c.rowpass_slots for c in pk.schedule_candidates(pk.Instance(fft_len=1 << 12)) if c.log2_n1 == 6}
+    small = {c.rowpass_slots for c in pk.schedule_candidates(pk.Instance(fft_len=1 << 12))
+             if c.log2_n1 == 6 and c.single_pass == 2}
     assert small == {16, 32, 64}
+    # short transforms also list the single pass, with slots around 512 / n_pairs
+    single = {c for c in pk.schedule_candidates(pk.Instance(fft_len=1 << 12)) if c.single_pass == 1}
+    assert single == {pk.Schedule(6, 0, 0, 0, G, 1) for G in (128, 256, 512, 1024)}  # default 2^21 / 2^12 = 512
+    assert not any(c.single_pass == 1 for c in pk.schedule_candidates(pk.Instance(fft_len=1 << 13)))
     # tiny transform: only the split that keeps both passes >= 16 points
     assert {c.log2_n1 for c in pk.schedule_candidates(pk.Instance(fft_len=256))} == {4}
 
@@ -207,3 +212,25 @@ def test_post_reduction_argument_errors():
     lags = (C.c_int32 * 1)(1)
     assert pk.STATUS[L.ps_allan(p, 100, 1, 1, 100, lags, 1, 0.0, 0, p, None)] == "PS_ERR_ARG"
     assert pk.STATUS[L.ps_band_stats(p, 1, 0, p, None)] == "PS_ERR_ARG"
+
+
+@pytest.mark.parametrize("n,sched,ok", [
+    (1 << 12, pk.Schedule(0, 0, 0, 0, 0, 1), True),
+    (1 << 12, pk.Schedule(0, 0, 0, 0, 4096, 1), True),
+    (1 << 12, pk.Schedule(0, 0, 0, 0, 8192, 1), True),
+    (1 << 12, pk.Schedule(0, 0, 0, 0, 16384, 1), False),
+    (1 << 12, pk.Schedule(0, 16, 0, 0, 0, 1), False),    # the single pass has no column tiles
+    (1 << 12, pk.Schedule(0, 16, 0, 0, 0, 0), False),    # default for 2^12 is the single pass
+    (1 << 12, pk.Schedule(0, 16, 0, 0, 0, 2), True),
+    (1 << 13, pk.Schedule(0, 0, 0, 0, 0, 1), False),     # above 2^12
+    (1 << 12, pk.Schedule(0, 0, 0, 0, 0, 3), False),
+])
+def test_single_pass_schedules(n, sched, ok):
+    arr = (pk._Instance * 1)(pk.Instance(fft_len=n, bits=8).to_c())
+    sarr = (pk._Schedule * 1)(sched.to_c())
+    h = C.c_void_p()
+    nb = C.c_size_t()
+    st = pk.lib().ps_plan_scheduled(arr, sarr, 1, C.byref(h), C.byref(nb))
+    assert (st == 0) == ok, pk.lib().ps_last_error()
+    if h.value:
+        pk.lib().ps_destroy(h)

@@ -55,9 +55,14 @@ def test_two_streams(env, bits, log2n, F):
         assert np.allclose(power[..., 1], pref[..., 1], rtol=1e-12, atol=0)
     else:
         assert np.all(np.isnan(power[..., 1]))
-    # counting does not change the spectra
+    # counting does not change the spectra: bitwise where both runs take the four-step passes; transforms of
+    # 2^12 points or less run the single pass when not counting, equal within FP32 rounding
     spec_off = run(env, d, calls=2 if F > 3 else 1, hist=False)[0]
-    assert np.array_equal(spec, spec_off)
+    if log2n > 12:
+        assert np.array_equal(spec, spec_off)
+    else:
+        scale = np.mean(spec_off[:, 0:1, :], axis=2, keepdims=True)
+        assert np.max(np.abs(spec - spec_off) / scale) < 2e-6
 
 
 def test_four_streams_two_pairs(env):

@@ -82,7 +82,7 @@ def test_tuner_cache(env, tmp_path, monkeypatch):
     key = autotune.cache_key(inst, dev)
     assert d[key]["schedule"] == {"log2_n1": best.log2_n1, "colpass_cols": best.colpass_cols,
                                   "rowpass_frames": best.rowpass_frames, "col_wg_per_cu": best.col_wg_per_cu,
-                                  "rowpass_slots": best.rowpass_slots}
+                                  "rowpass_slots": best.rowpass_slots, "single_pass": best.single_pass}
     assert d[key]["ms"] == min(timings.values())
 
     def boom(*a, **k):
