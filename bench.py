@@ -46,6 +46,8 @@ def parse():
                     help="only the headline workload (for profiler runs): no other sections, no CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time (whole integrations)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--only", choices=["short_transforms", "post_reduction", "table1_modes", "overlap_form"],
+                    help="run one further section alone and print it (for profiler runs)")
     return ap.parse_args()
 
 
@@ -555,6 +557,12 @@ def main():
 
     pk.lib()  # fail loudly when the HIP library is missing
     dev = torch.device("cuda:0")
+    if args.only in ("short_transforms", "post_reduction", "table1_modes"):
+        fn = {"short_transforms": lambda: short_form(pk, torch, dev, args.steps),
+              "post_reduction": lambda: post_form(pk, torch, dev, args.steps),
+              "table1_modes": lambda: modes_form(pk, torch, dev, args.steps, args.ring)}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        return
     inst = synth.make_paper()
     N, S, F = inst["fft_len"], inst["n_streams"], inst["n_frames"]
     samples = F * N * S
@@ -567,6 +575,9 @@ def main():
         outs = [torch.empty((1, 4, N // 2), dtype=torch.float32, device=dev) for _ in ring]
         plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev, stream=side)
     side.synchronize()
+    if args.only == "overlap_form":
+        print(json.dumps({"overlap_form": overlap_form(pk, torch, dev, inst, ring, args.steps)}), flush=True)
+        return
     pos = {"i": 0}
 
     def step():

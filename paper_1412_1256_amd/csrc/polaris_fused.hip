@@ -196,7 +196,8 @@ __global__ void __launch_bounds__(256) k_slot_chunks(const double* __restrict__ 
   if (e >= elems) return;
   const int g1 = min(slots, (c + 1) * kReduceChunk);
   double s = 0.0;
-  for (int g = c * kReduceChunk; g < g1; ++g) s += acc[(int64_t)g * slot_stride + e];
+#pragma unroll 8
+  for (int g = c * kReduceChunk; g < g1; ++g) s += acc[(int64_t)g * slot_stride + e];  // loads issue 8 at a time
   part[(int64_t)c * elems + e] = s;
 }
 
@@ -205,6 +206,7 @@ __global__ void __launch_bounds__(256) k_slot_total(const double* __restrict__ p
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= elems) return;
   double s = 0.0;
+#pragma unroll 8
   for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * elems + e];
   out[e] = s;
 }

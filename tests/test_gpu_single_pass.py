@@ -191,3 +191,37 @@ def test_state_graph_and_grouped_plans(env):
         side.synchronize()
         for o, e in zip(outs, eager):
             assert torch.equal(o, e), r
+
+
+def test_backward_reads_reduced_slots(env):
+    """More than 64 slots in use: Stokes and the adjoint read the reduced slot sum (learnable window)."""
+    torch, pk, dev = env
+    N, F = 1024, 200
+    rng = np.random.default_rng(8)
+    inst = synth.make_correlated_noise(8, 0.3, N, F, seed_extra=8, window="taps")
+    taps = (1 + 0.1 * rng.standard_normal(64)).astype(np.float32)
+    g = rng.standard_normal((1, 4, N // 2)).astype(np.float32)
+    say("single pass backward with 200 slots in use")
+    w, s2 = oracle.window("taps", N, taps=taps.astype(np.float64))
+    acc, nf = oracle.accumulate(inst["packed"], 8, 2, inst["n_samples"], N, w, inst["pairs"])
+    ref = oracle.stokes(acc, nf, s2)
+    gr = oracle.calibrate_backward(inst["packed"], 8, 2, inst["n_samples"], N, w, inst["pairs"], acc, nf, s2,
+                                   g.astype(np.float64), taps=taps.astype(np.float64))
+    plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev)
+    packed = torch.from_numpy(inst["packed"]).to(dev)
+    plan.set_window_taps(torch.from_numpy(taps).to(dev))
+    plan.reset()
+    plan.accumulate(packed)
+    st = plan.stokes().cpu().numpy().astype(np.float64)
+    grads = plan.calibrate_backward(packed, torch.from_numpy(g).to(dev))
+    torch.cuda.synchronize(dev)
+    assert np.all(stokes_err(st, ref) < TOL)
+    for name, key in (("gain_x", "d_gain_x"), ("gain_y", "d_gain_y")):
+        got = grads[name].cpu().numpy().astype(np.float64)
+        got = got[..., 0] + 1j * got[..., 1]
+        rel = np.max(np.abs(got - gr[key])) / np.max(np.abs(gr[key]))
+        assert rel < 1e-5, (name, rel)
+    dt = grads["taps"].cpu().numpy().astype(np.float64)
+    rel = np.max(np.abs(dt - gr["d_taps"])) / np.max(np.abs(gr["d_taps"]))
+    say(f"  taps rel err {rel}")
+    assert rel < 1e-4
