@@ -297,11 +297,14 @@ ps_status ps_band_stats(const float* x_dev, int64_t n_spec, int64_t n_chan, doub
  * L (host int32, >= 1): out[s][l] = mean over t of (x[t+L] - 2 x[t] + x[t-L])^2 / (2 (L spacing)^2), t with
  * all three samples finite, NaN when there is none (2 L >= n_points); spacing is the sample interval (s for
  * TAV, Hz for SAV).  normalize != 0 divides each series by the mean of its finite samples first.  out:
- * double [n_series][n_lags].
+ * double [n_series][n_lags].  work: a device buffer of ps_allan_work_bytes bytes owned by the caller (partial
+ * sums per chunk of 4096 points; 0 bytes, and NULL allowed, when the series lie side by side, series_stride 1).
  */
+ps_status ps_allan_work_bytes(int64_t n_points, int64_t point_stride, int64_t n_series, int64_t series_stride,
+                              int32_t n_lags, size_t* bytes);
 ps_status ps_allan(const float* x_dev, int64_t n_points, int64_t point_stride, int64_t n_series,
                    int64_t series_stride, const int32_t* lags, int32_t n_lags, double spacing, int32_t normalize,
-                   double* out_dev, void* hip_stream);
+                   void* work_dev, size_t work_bytes, double* out_dev, void* hip_stream);
 
 /* Free a plan's host metadata (never the caller's device memory). NULL is accepted. */
 ps_status ps_destroy(ps_plan_t plan);

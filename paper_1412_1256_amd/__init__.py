@@ -125,7 +125,8 @@ def lib():
             "ps_bandpass_fit": [vp, i64, i32, C.c_double, vp, sz, vp, vp],
             "ps_bandpass_correct": [vp, i64, i64, vp, vp, vp, vp],
             "ps_band_stats": [vp, i64, i64, vp, vp],
-            "ps_allan": [vp, i64, i64, i64, i64, C.POINTER(i32), i32, C.c_double, i32, vp, vp],
+            "ps_allan_work_bytes": [i64, i64, i64, i64, i32, C.POINTER(sz)],
+            "ps_allan": [vp, i64, i64, i64, i64, C.POINTER(i32), i32, C.c_double, i32, vp, sz, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -508,6 +509,10 @@ def allan(x, lags, spacing: float = 1.0, normalize: bool = False, axis: int = -1
     point_stride, series_stride = (1, n_points) if axis == 1 else (n_series, 1)
     lg = (C.c_int32 * len(lags))(*[int(L) for L in lags])
     out = torch.empty((n_series, len(lags)), dtype=torch.float64, device=v.device)
+    nb = C.c_size_t()
+    _check(lib().ps_allan_work_bytes(n_points, point_stride, n_series, series_stride, len(lags), C.byref(nb)))
+    work = torch.empty(max(8, nb.value), dtype=torch.uint8, device=v.device)
     _check(lib().ps_allan(_ptr(v), n_points, point_stride, n_series, series_stride, lg, len(lags), spacing,
-                          1 if normalize else 0, _ptr(out), _stream(v, stream)))
+                          1 if normalize else 0, _ptr(work), nb.value, _ptr(out), _stream(v, stream)))
+    out._work_keepalive = work
     return out

@@ -1494,7 +1494,7 @@ static ps_status spline_args(int64_t n_chan, int32_t knot_spacing, double edge_f
 }
 
 static size_t spline_work_bytes(const ps::SplineArgs& a) {
-  return align_up((size_t)a.n_int * 14 * 8) + align_up((size_t)a.n_coef * 8) + align_up((size_t)a.n_coef * 32);
+  return align_up((size_t)a.n_int * 14 * 8) + align_up((size_t)a.n_coef * 8);
 }
 
 ps_status ps_bandpass_work_bytes(int64_t n_chan, int32_t knot_spacing, double edge_frac, size_t* bytes) {
@@ -1521,7 +1521,6 @@ ps_status ps_bandpass_fit(const float* h_dev, int64_t n_chan, int32_t knot_spaci
   a.h = h_dev;
   a.partial = reinterpret_cast<double*>(w);
   a.coef = reinterpret_cast<double*>(w + align_up((size_t)a.n_int * 14 * 8));
-  a.lower = reinterpret_cast<double*>(w + align_up((size_t)a.n_int * 14 * 8) + align_up((size_t)a.n_coef * 8));
   a.smooth = smooth_dev;
   hipError_t e = ps::launch_bandpass_fit(a, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "bandpass fit launch");
@@ -1550,13 +1549,27 @@ ps_status ps_band_stats(const float* x_dev, int64_t n_spec, int64_t n_chan, doub
   return PS_OK;
 }
 
-ps_status ps_allan(const float* x_dev, int64_t n_points, int64_t point_stride, int64_t n_series,
-                   int64_t series_stride, const int32_t* lags, int32_t n_lags, double spacing, int32_t normalize,
-                   double* out_dev, void* hip_stream) {
-  if (!x_dev || !lags || !out_dev) return fail(PS_ERR_ARG, "null series, lags or output");
+ps_status ps_allan_work_bytes(int64_t n_points, int64_t point_stride, int64_t n_series, int64_t series_stride,
+                              int32_t n_lags, size_t* bytes) {
+  if (!bytes) return fail(PS_ERR_ARG, "null bytes");
   if (n_lags < 1 || n_lags > ps::kMaxAllanLags) return fail(PS_ERR_ARG, "n_lags %d not in 1..%d", n_lags, ps::kMaxAllanLags);
   if (n_points < 0 || n_series < 0 || n_series > (int64_t(1) << 31) - 1 || point_stride < 0 || series_stride < 0)
     return fail(PS_ERR_ARG, "negative size or stride, or too many series");
+  *bytes = (size_t)ps::allan_part_doubles(n_points, n_series, point_stride, series_stride, n_lags) * 8;
+  return PS_OK;
+}
+
+ps_status ps_allan(const float* x_dev, int64_t n_points, int64_t point_stride, int64_t n_series,
+                   int64_t series_stride, const int32_t* lags, int32_t n_lags, double spacing, int32_t normalize,
+                   void* work_dev, size_t work_bytes, double* out_dev, void* hip_stream) {
+  if (!x_dev || !lags || !out_dev) return fail(PS_ERR_ARG, "null series, lags or output");
+  size_t need = 0;
+  ps_status st = ps_allan_work_bytes(n_points, point_stride, n_series, series_stride, n_lags, &need);
+  if (st != PS_OK) return st;
+  if ((int64_t)(n_points > 0 ? (n_points + ps::kAllanChunk - 1) / ps::kAllanChunk : 1) > 65535)
+    return fail(PS_ERR_SIZE, "%lld points per series exceed the block form's 65535 chunks", (long long)n_points);
+  if (need && (!work_dev || work_bytes < need))
+    return fail(PS_ERR_WORKSPACE, "work buffer of %zu bytes is smaller than the %zu needed", work_bytes, need);
   if (!(spacing > 0.0)) return fail(PS_ERR_ARG, "spacing must be positive");
   ps::AllanArgs a{};
   for (int i = 0; i < n_lags; ++i) {
@@ -1573,6 +1586,7 @@ ps_status ps_allan(const float* x_dev, int64_t n_points, int64_t point_stride, i
   a.normalize = normalize ? 1 : 0;
   a.spacing = spacing;
   a.out = out_dev;
+  a.part = static_cast<double*>(work_dev);
   hipError_t e = ps::launch_allan(a, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "Allan variance launch");
   return PS_OK;

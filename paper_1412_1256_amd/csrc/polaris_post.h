@@ -7,6 +7,7 @@
 namespace ps {
 
 constexpr int kMaxAllanLags = 64;
+constexpr int64_t kAllanChunk = 4096;  // points per workgroup of a series (block form)
 constexpr int64_t kMaxSplineCoef = 3072;  // basis functions of one bandpass fit (LDS of the solve)
 
 struct ChanAvgArgs {
@@ -25,7 +26,6 @@ struct SplineArgs {
   int64_t n_int, n_coef;    // intervals, basis functions (n_int + 3)
   double* partial;          // [n_int][14]: Gram entries (q <= p) and right-hand sides of each interval
   double* coef;             // [n_coef]
-  double* lower;            // [n_coef][4]: Cholesky factor, row i holds L[i][i-3 .. i]
   float* smooth;            // [n_chan]
 };
 
@@ -37,7 +37,11 @@ struct AllanArgs {
   int32_t lags[kMaxAllanLags];
   double spacing;
   double* out;              // [n_series][n_lags]
+  double* part;             // [n_series][chunks][n_lags + 1][2]: per chunk sums and counts (block form)
 };
+
+// block form (series not side by side): partial sums per chunk of points; 0 for the side-by-side form
+int64_t allan_part_doubles(int64_t n_points, int64_t n_series, int64_t point_stride, int64_t series_stride, int n_lags);
 
 hipError_t launch_channel_average(const ChanAvgArgs& a, hipStream_t s);
 hipError_t launch_bandpass_fit(const SplineArgs& a, hipStream_t s);

@@ -137,7 +137,9 @@ __device__ __forceinline__ int gidx(int q, int p) {
 
 // One workgroup: the threads assemble the banded normal matrix (row i: A[i][i-3 .. i]) and the right-hand
 // side in LDS from the interval partials; one thread then factors A = L L^T (banded Cholesky, keeping the
-// last three rows of L in registers), solves L y = r on the way, and solves L^T a = y backwards.
+// last three rows of L in registers and each finished row of L in place of A's, the diagonal as its
+// reciprocal so that the recurrence has one division and one square root per row), solves L y = r on the
+// way, and solves L^T a = y backwards from LDS.
 __global__ void __launch_bounds__(kNT) k_spline_solve(SplineArgs a) {
   __shared__ double lds[5 * kMaxSplineCoef];
   double* A = lds;                  // [n_coef][4], A[i][3 - d] = A(i, i - d)
@@ -158,7 +160,7 @@ __global__ void __launch_bounds__(kNT) k_spline_solve(SplineArgs a) {
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  // L rows i-3, i-2, i-1 (each as L(k, k-3 .. k)) and y
+  // L rows i-3, i-2, i-1 (each as L(k, k-3 .. k-1) and 1 / L(k, k)) and y
   double Lm[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};  // Lm[0] = row i-1, Lm[1] = i-2, Lm[2] = i-3
   double ym[3] = {0, 0, 0};
   for (int64_t i = 0; i < n; ++i) {
@@ -176,15 +178,15 @@ __global__ void __launch_bounds__(kNT) k_spline_solve(SplineArgs a) {
         const double ldk = Lm[d - 1][3 - (e - d)];
         s -= lik * ldk;
       }
-      Li[3 - d] = s / Lm[d - 1][3];
+      Li[3 - d] = s * Lm[d - 1][3];
     }
     double dg = A[i * 4 + 3];
     for (int e = 1; e <= 3; ++e) dg -= Li[3 - e] * Li[3 - e];
-    Li[3] = sqrt(dg);
+    Li[3] = 1.0 / sqrt(dg);
     double y = r[i];
     for (int e = 1; e <= 3; ++e) y -= Li[3 - e] * ym[e - 1];
-    y /= Li[3];
-    for (int q = 0; q < 4; ++q) a.lower[i * 4 + q] = Li[q];
+    y *= Li[3];
+    for (int q = 0; q < 4; ++q) A[i * 4 + q] = Li[q];  // row i of A is no longer needed
     r[i] = y;
     for (int q = 0; q < 4; ++q) {
       Lm[2][q] = Lm[1][q];
@@ -195,13 +197,13 @@ __global__ void __launch_bounds__(kNT) k_spline_solve(SplineArgs a) {
     ym[1] = ym[0];
     ym[0] = y;
   }
-  // L^T a = y: a_i = (y_i - sum_{e=1..3} L(i+e, i) a_{i+e}) / L(i, i)
+  // L^T a = y: a_i = (y_i - sum_{e=1..3} L(i+e, i) a_{i+e}) / L(i, i)  (A[i][3] holds 1 / L(i, i))
   double am[3] = {0, 0, 0};  // a_{i+1}, a_{i+2}, a_{i+3}
   for (int64_t i = n - 1; i >= 0; --i) {
     double s = r[i];
     for (int e = 1; e <= 3; ++e)
-      if (i + e < n) s -= a.lower[(i + e) * 4 + 3 - e] * am[e - 1];
-    const double ai = s / a.lower[i * 4 + 3];
+      if (i + e < n) s -= A[(i + e) * 4 + 3 - e] * am[e - 1];
+    const double ai = s * A[i * 4 + 3];
     a.coef[i] = ai;
     am[2] = am[1];
     am[1] = am[0];
@@ -266,16 +268,20 @@ __global__ void __launch_bounds__(kNT) k_band_stats(const float* __restrict__ x,
   }
 }
 
-// Eq. 3 / Eq. 4: one workgroup per series; per lag L the mean over t of the squared second difference
-// (t - L, t, t + L all finite), over 2 (L spacing)^2, divided by the squared series mean when normalised.
-__global__ void __launch_bounds__(kNT) k_allan(AllanArgs a) {
+// Eq. 3 / Eq. 4, block form: workgroup (chunk c, series s) covers the points t of chunk c and writes, per lag
+// L, the sum of squared second differences (x[t+L] - 2 x[t] + x[t-L])^2 over its t with all three samples
+// finite and their count, and (normalised) the sum and count of its finite points; a second kernel adds
+// the chunks of each series in order.
+__global__ void __launch_bounds__(kNT) k_allan_part(AllanArgs a, int64_t chunks) {
   __shared__ double sh[kNT / 64];
-  const float* x = a.x + (int64_t)blockIdx.x * a.series_stride;
+  const int64_t s_ = blockIdx.x, c = blockIdx.y;
+  const float* x = a.x + s_ * a.series_stride;
   const int64_t P = a.n_points, st = a.point_stride;
-  double mean2 = 1.0;
+  const int64_t t0 = c * kAllanChunk, t1 = (t0 + kAllanChunk) < P ? (t0 + kAllanChunk) : P;
+  double* out = a.part + (s_ * chunks + c) * (a.n_lags + 1) * 2;
   if (a.normalize) {
     double s = 0.0, n = 0.0;
-    for (int64_t t = threadIdx.x; t < P; t += kNT) {
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kNT) {
       const float v = x[t * st];
       if (isfinite(v)) {
         s += (double)v;
@@ -284,27 +290,53 @@ __global__ void __launch_bounds__(kNT) k_allan(AllanArgs a) {
     }
     s = block_sum(s, sh);
     n = block_sum(n, sh);
-    const double m = s / n;
-    mean2 = m * m;
+    if (threadIdx.x == 0) {
+      out[2 * a.n_lags] = s;
+      out[2 * a.n_lags + 1] = n;
+    }
   }
   for (int l = 0; l < a.n_lags; ++l) {
     const int64_t L = a.lags[l];
     double s = 0.0, n = 0.0;
-    if (L >= 1 && 2 * L < P) {
-      for (int64_t t = L + threadIdx.x; t < P - L; t += kNT) {
-        const double d = (double)x[(t + L) * st] - 2.0 * (double)x[t * st] + (double)x[(t - L) * st];
-        if (finite(d)) {
-          s += d * d;
-          n += 1.0;
-        }
+    const int64_t lo = t0 > L ? t0 : L, hi = t1 < P - L ? t1 : P - L;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += kNT) {
+      const double d = (double)x[(t + L) * st] - 2.0 * (double)x[t * st] + (double)x[(t - L) * st];
+      if (finite(d)) {
+        s += d * d;
+        n += 1.0;
       }
     }
     s = block_sum(s, sh);
     n = block_sum(n, sh);
     if (threadIdx.x == 0) {
-      const double tau = (double)L * a.spacing;
-      a.out[(int64_t)blockIdx.x * a.n_lags + l] = n > 0.0 ? s / n / (2.0 * tau * tau) / mean2 : NAN;
+      out[2 * l] = s;
+      out[2 * l + 1] = n;
     }
+  }
+}
+
+__global__ void __launch_bounds__(kNT) k_allan_total(AllanArgs a, int64_t chunks) {
+  const int64_t s_ = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (s_ >= a.n_series) return;
+  const double* part = a.part + s_ * chunks * (a.n_lags + 1) * 2;
+  double mean2 = 1.0;
+  if (a.normalize) {
+    double s = 0.0, n = 0.0;
+    for (int64_t c = 0; c < chunks; ++c) {
+      s += part[(c * (a.n_lags + 1) + a.n_lags) * 2];
+      n += part[(c * (a.n_lags + 1) + a.n_lags) * 2 + 1];
+    }
+    const double m = s / n;
+    mean2 = m * m;
+  }
+  for (int l = 0; l < a.n_lags; ++l) {
+    double s = 0.0, n = 0.0;
+    for (int64_t c = 0; c < chunks; ++c) {
+      s += part[(c * (a.n_lags + 1) + l) * 2];
+      n += part[(c * (a.n_lags + 1) + l) * 2 + 1];
+    }
+    const double tau = (double)a.lags[l] * a.spacing;
+    a.out[s_ * a.n_lags + l] = n > 0.0 ? s / n / (2.0 * tau * tau) / mean2 : NAN;
   }
 }
 
@@ -379,11 +411,25 @@ hipError_t launch_band_stats(const float* x, int64_t n_spec, int64_t n_chan, dou
   return hipGetLastError();
 }
 
+static bool allan_cols(int64_t n_series, int64_t point_stride, int64_t series_stride) {
+  return series_stride == 1 && point_stride >= n_series && n_series >= 64;
+}
+
+int64_t allan_part_doubles(int64_t n_points, int64_t n_series, int64_t point_stride, int64_t series_stride,
+                           int n_lags) {
+  if (allan_cols(n_series, point_stride, series_stride)) return 0;
+  const int64_t chunks = n_points > 0 ? (n_points + kAllanChunk - 1) / kAllanChunk : 1;
+  return n_series * chunks * (n_lags + 1) * 2;
+}
+
 hipError_t launch_allan(const AllanArgs& a, hipStream_t s) {
-  if (a.series_stride == 1 && a.point_stride >= a.n_series && a.n_series >= 64)
+  if (allan_cols(a.n_series, a.point_stride, a.series_stride)) {
     hipLaunchKernelGGL(k_allan_cols, dim3((unsigned)((a.n_series + kNT - 1) / kNT)), dim3(kNT), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_allan, dim3((unsigned)a.n_series), dim3(kNT), 0, s, a);
+  } else {
+    const int64_t chunks = a.n_points > 0 ? (a.n_points + kAllanChunk - 1) / kAllanChunk : 1;
+    hipLaunchKernelGGL(k_allan_part, dim3((unsigned)a.n_series, (unsigned)chunks), dim3(kNT), 0, s, a, chunks);
+    hipLaunchKernelGGL(k_allan_total, dim3((unsigned)((a.n_series + kNT - 1) / kNT)), dim3(kNT), 0, s, a, chunks);
+  }
   return hipGetLastError();
 }
 

@@ -200,18 +200,23 @@ def test_post_reduction_argument_errors():
     n = C.c_size_t()
     assert L.ps_bandpass_work_bytes(131072, 128, 0.06, C.byref(n)) == 0
     n_int = -(-(131072 - 2 * 7864) // 128)
-    assert n.value >= (n_int * 14 + (n_int + 3) * 5) * 8
+    assert n.value >= (n_int * 14 + (n_int + 3)) * 8
     assert pk.STATUS[L.ps_bandpass_work_bytes(131072, 16, 0.0, C.byref(n))] == "PS_ERR_UNSUPPORTED"
     assert pk.STATUS[L.ps_bandpass_work_bytes(500, 128, 0.06, C.byref(n))] == "PS_ERR_SIZE"  # 440 < 4 x 128
     assert pk.STATUS[L.ps_bandpass_work_bytes(131072, 2, 0.06, C.byref(n))] == "PS_ERR_ARG"
     assert pk.STATUS[L.ps_bandpass_work_bytes(131072, 128, 0.5, C.byref(n))] == "PS_ERR_ARG"
     assert pk.STATUS[L.ps_bandpass_fit(p, 131072, 128, 0.06, p, 16, p, None)] == "PS_ERR_WORKSPACE"
-    lags = (C.c_int32 * 2)(1, 0)
-    assert pk.STATUS[L.ps_allan(p, 100, 1, 1, 100, lags, 2, 1.0, 0, p, None)] == "PS_ERR_ARG"
-    assert pk.STATUS[L.ps_allan(p, 100, 1, 1, 100, lags, 0, 1.0, 0, p, None)] == "PS_ERR_ARG"
-    lags = (C.c_int32 * 1)(1)
-    assert pk.STATUS[L.ps_allan(p, 100, 1, 1, 100, lags, 1, 0.0, 0, p, None)] == "PS_ERR_ARG"
+
     assert pk.STATUS[L.ps_band_stats(p, 1, 0, p, None)] == "PS_ERR_ARG"
+    lags = (C.c_int32 * 2)(1, 0)
+    assert pk.STATUS[L.ps_allan(p, 100, 1, 1, 100, lags, 2, 1.0, 0, p, 1 << 20, p, None)] == "PS_ERR_ARG"
+    assert pk.STATUS[L.ps_allan(p, 100, 1, 1, 100, lags, 0, 1.0, 0, p, 1 << 20, p, None)] == "PS_ERR_ARG"
+    lags = (C.c_int32 * 1)(1)
+    assert pk.STATUS[L.ps_allan(p, 100, 1, 1, 100, lags, 1, 0.0, 0, p, 1 << 20, p, None)] == "PS_ERR_ARG"
+    nb = C.c_size_t()
+    assert L.ps_allan_work_bytes(131072, 1, 30, 131072, 8, C.byref(nb)) == 0 and nb.value == 30 * 32 * 9 * 2 * 8
+    assert L.ps_allan_work_bytes(1800, 4096, 4096, 1, 8, C.byref(nb)) == 0 and nb.value == 0  # side by side
+    assert pk.STATUS[L.ps_allan(p, 131072, 1, 30, 131072, lags, 1, 1.0, 0, p, 16, p, None)] == "PS_ERR_WORKSPACE"
 
 
 @pytest.mark.parametrize("n,sched,ok", [

@@ -167,6 +167,10 @@ def test_spectral_allan_variance(env):
     got = pk.allan(torch.from_numpy(x).to(dev), lags, spacing=61.03515625, axis=1).cpu().numpy()
     ref = post.allan(x, lags, spacing=61.03515625)
     rel_close(got, ref, 1e-10)
+    # normalised, and a series length that is not a whole number of 4096-point chunks
+    y = torch.from_numpy(x[:, :100000].copy()).to(dev)
+    got = pk.allan(y, lags, spacing=61.03515625, normalize=True, axis=1).cpu().numpy()
+    rel_close(got, post.allan(x[:, :100000], lags, spacing=61.03515625, normalize=True), 1e-10)
 
 
 def test_post_reductions_are_deterministic(env):
