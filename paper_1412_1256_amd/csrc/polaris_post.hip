@@ -341,8 +341,9 @@ __global__ void __launch_bounds__(kNT) k_allan_total(AllanArgs a, int64_t chunks
 }
 
 // The same for series stored side by side (series_stride 1, e.g. one series per channel of a run of
-// integrations [t][channel]): one thread per series, so a wave's loads are consecutive addresses; sums in
-// t order.
+// integrations [t][channel]): one thread per series, so a wave's loads are consecutive addresses.  One sweep
+// over t serves up to 8 lags (their sums in registers), so the rows t - L, t, t + L of nearby lags are
+// reused from cache; each lag still adds its terms in t order.
 __global__ void __launch_bounds__(kNT) k_allan_cols(AllanArgs a) {
   const int64_t s = (int64_t)blockIdx.x * kNT + threadIdx.x;
   if (s >= a.n_series) return;
@@ -361,20 +362,34 @@ __global__ void __launch_bounds__(kNT) k_allan_cols(AllanArgs a) {
     const double m = sum / n;
     mean2 = m * m;
   }
-  for (int l = 0; l < a.n_lags; ++l) {
-    const int64_t L = a.lags[l];
-    double sum = 0.0, n = 0.0;
-    if (L >= 1 && 2 * L < P) {
-      for (int64_t t = L; t < P - L; ++t) {
-        const double d = (double)x[(t + L) * st] - 2.0 * (double)x[t * st] + (double)x[(t - L) * st];
-        if (finite(d)) {
-          sum += d * d;
-          n += 1.0;
+  constexpr int LG = 8;
+  for (int l0 = 0; l0 < a.n_lags; l0 += LG) {
+    int64_t L[LG];
+    double sum[LG], n[LG];
+#pragma unroll
+    for (int l = 0; l < LG; ++l) {
+      L[l] = l0 + l < a.n_lags ? a.lags[l0 + l] : 0;  // 0: not a lag of this group
+      sum[l] = n[l] = 0.0;
+    }
+    for (int64_t t = 0; t < P; ++t) {
+      const double xt = (double)x[t * st];
+#pragma unroll
+      for (int l = 0; l < LG; ++l) {
+        if (L[l] >= 1 && t >= L[l] && t < P - L[l]) {  // the same for every lane
+          const double d = (double)x[(t + L[l]) * st] - 2.0 * xt + (double)x[(t - L[l]) * st];
+          if (finite(d)) {
+            sum[l] += d * d;
+            n[l] += 1.0;
+          }
         }
       }
     }
-    const double tau = (double)L * a.spacing;
-    a.out[s * a.n_lags + l] = n > 0.0 ? sum / n / (2.0 * tau * tau) / mean2 : NAN;
+#pragma unroll
+    for (int l = 0; l < LG; ++l) {
+      if (l0 + l >= a.n_lags) break;
+      const double tau = (double)L[l] * a.spacing;
+      a.out[s * a.n_lags + l0 + l] = n[l] > 0.0 && L[l] >= 1 && 2 * L[l] < P ? sum[l] / n[l] / (2.0 * tau * tau) / mean2 : NAN;
+    }
   }
 }
 
