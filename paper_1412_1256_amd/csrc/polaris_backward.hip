@@ -181,7 +181,8 @@ __global__ void __launch_bounds__(64) k_bw_reduce(BwChanArgs a) {
   const int U = a.N1 / 2, p = (int)blockIdx.x;
   if (threadIdx.x < kBwRed) {
     double v = 0.0;
-    for (int u = 0; u < U; ++u) v += a.red[((int64_t)p * U + u) * kBwRed + threadIdx.x];
+#pragma unroll 8
+    for (int u = 0; u < U; ++u) v += a.red[((int64_t)p * U + u) * kBwRed + threadIdx.x];  // loads 8 at a time
     if (threadIdx.x < 4) {
       if (a.d_dterms) a.d_dterms[4 * p + threadIdx.x] = (float)v;
     } else {
@@ -199,7 +200,12 @@ __global__ void __launch_bounds__(64) k_bw_reduce(BwChanArgs a) {
 // ------------------------------------------------------------------------------------------------
 
 template <int L, int UB, int FB>
-__global__ void __launch_bounds__(UB * FB * L / 4) k_bw_rowpass(BwRowArgs a) {
+__global__ void __launch_bounds__(UB * FB * L / 4) k_bw_rowpass(BwRowArgs a, int fpg) {
+  // frames [blockIdx.z fpg, +fpg) of the launch: frames are independent here, so groups of them run in
+  // parallel workgroups
+  const int fz0 = (int)blockIdx.z * fpg;
+  const int n_frames = min(fpg, a.n_frames - fz0);
+  if (n_frames <= 0) return;
   constexpr int NT = UB * FB * L / 4;
   constexpr int TPS = L / 8;
   constexpr int NCH = UB * L;  // channel slots, one per owning thread
@@ -248,10 +254,10 @@ __global__ void __launch_bounds__(UB * FB * L / 4) k_bw_rowpass(BwRowArgs a) {
   const int onyq = (ubc * FB * 2 + 0) * L + swz(L / 2);
 
   const int64_t fstride = (int64_t)a.P * a.N1 * L;
-  float2* const tb = a.T + ((int64_t)p * a.N1 + row) * (int64_t)L;
+  float2* const tb = a.T + (int64_t)fz0 * fstride + ((int64_t)p * a.N1 + row) * (int64_t)L;
   const float2* src = tb + ts;
   auto fetch = [&](float2 (&d)[1][8], int f0) {
-    const float2* pj = src + (int64_t)min(f0 + fs, a.n_frames - 1) * fstride;
+    const float2* pj = src + (int64_t)min(f0 + fs, n_frames - 1) * fstride;
 #pragma unroll
     for (int i = 0; i < 8 / R0; ++i)
 #pragma unroll
@@ -260,7 +266,7 @@ __global__ void __launch_bounds__(UB * FB * L / 4) k_bw_rowpass(BwRowArgs a) {
   auto batch = [&](float2 (&v)[1][8], int f0) {
     row_chain<L, 1, 0>(v, ts, tw, seq);
     __syncthreads();
-    const int nf = min(FB, a.n_frames - f0);
+    const int nf = min(FB, n_frames - f0);
     if (owner) {
       for (int g = 0; g < nf; ++g) {
         float2* fr = buf + g * 2 * L;
@@ -292,7 +298,7 @@ __global__ void __launch_bounds__(UB * FB * L / 4) k_bw_rowpass(BwRowArgs a) {
     exchange_sync<L>();
     row_chain<L, 1, 0>(w, ts, tw, seq);
     exchange_sync<L>();
-    if (f0 + fs < a.n_frames) {
+    if (f0 + fs < n_frames) {
       float2* dst = tb + (int64_t)(f0 + fs) * fstride;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -304,12 +310,12 @@ __global__ void __launch_bounds__(UB * FB * L / 4) k_bw_rowpass(BwRowArgs a) {
   };
   float2 va[1][8], vb[1][8];
   fetch(va, 0);
-  for (int f0 = 0; f0 < a.n_frames; f0 += 2 * FB) {
-    const bool second = f0 + FB < a.n_frames;
+  for (int f0 = 0; f0 < n_frames; f0 += 2 * FB) {
+    const bool second = f0 + FB < n_frames;
     if (second) fetch(vb, f0 + FB);
     batch(va, f0);
     if (!second) break;
-    if (f0 + 2 * FB < a.n_frames) fetch(va, f0 + 2 * FB);
+    if (f0 + 2 * FB < n_frames) fetch(va, f0 + 2 * FB);
     batch(vb, f0 + FB);
   }
 }
@@ -393,6 +399,17 @@ __global__ void __launch_bounds__(L * COLS / 16) k_bw_colpass(BwColArgs a) {
 
 constexpr int kTapThreads = 256;
 
+// the groups' partial dL/dw of each sample, added in group order into group 0's row (the order the tap
+// kernel used to add them in, so the result is unchanged); one thread per sample
+__global__ void __launch_bounds__(256) k_bw_dw_sum(double* __restrict__ dw, int groups, int64_t N) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  double s = 0.0;
+#pragma unroll 8
+  for (int g = 0; g < groups; ++g) s += dw[(int64_t)g * N + n];
+  dw[n] = s;
+}
+
 __global__ void __launch_bounds__(kTapThreads) k_bw_taps(BwTapArgs a) {
   __shared__ double red[kTapThreads];
   const int j = (int)blockIdx.x;
@@ -470,7 +487,14 @@ hipError_t launch_bw_channel(int N2, const BwChanArgs& a, const Launch& l) {
 
 template <int L, int UB, int FB>
 static hipError_t bw_rowpass_launch(const BwRowArgs& a, const Launch& l) {
-  PS_LAUNCH((k_bw_rowpass<L, UB, FB>), dim3((unsigned)(a.N1 / 2 / UB), (unsigned)a.P), dim3(UB * FB * L / 4), l, a);
+  // enough frame groups for about 256 workgroups
+  const int units = a.N1 / 2 / UB * a.P;
+  int groups = (256 + units - 1) / units;
+  if (groups > a.n_frames) groups = a.n_frames > 0 ? a.n_frames : 1;
+  const int fpg = (a.n_frames + groups - 1) / groups;
+  groups = (a.n_frames + fpg - 1) / fpg;
+  PS_LAUNCH((k_bw_rowpass<L, UB, FB>), dim3((unsigned)(a.N1 / 2 / UB), (unsigned)a.P, (unsigned)groups),
+            dim3(UB * FB * L / 4), l, a, fpg);
   return hipGetLastError();
 }
 
@@ -517,7 +541,11 @@ hipError_t launch_bw_colpass(int N1, int bits, bool fast, const BwColArgs& a, co
 }
 
 hipError_t launch_bw_taps(const BwTapArgs& a, const Launch& l) {
-  PS_LAUNCH(k_bw_taps, dim3((unsigned)a.n_taps), dim3(kTapThreads), l, a);
+  hipExtLaunchKernelGGL(k_bw_dw_sum, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, l.stream, l.start, nullptr, 0,
+                        const_cast<double*>(a.dw), a.groups, a.N);  // the plan's workspace
+  BwTapArgs b = a;
+  b.groups = 1;  // summed into group 0
+  hipExtLaunchKernelGGL(k_bw_taps, dim3((unsigned)a.n_taps), dim3(kTapThreads), 0, l.stream, nullptr, l.stop, 0, b);
   return hipGetLastError();
 }
 
