@@ -46,7 +46,8 @@ def parse():
                     help="only the headline workload (for profiler runs): no other sections, no CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time (whole integrations)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
-    ap.add_argument("--only", choices=["short_transforms", "post_reduction", "table1_modes", "overlap_form", "fwd_bwd"],
+    ap.add_argument("--only", choices=["short_transforms", "post_reduction", "table1_modes", "overlap_form", "fwd_bwd",
+                                       "precision_form"],
                     help="run one further section alone and print it (for profiler runs)")
     return ap.parse_args()
 
@@ -557,11 +558,12 @@ def main():
 
     pk.lib()  # fail loudly when the HIP library is missing
     dev = torch.device("cuda:0")
-    if args.only in ("short_transforms", "post_reduction", "table1_modes", "fwd_bwd"):
+    if args.only in ("short_transforms", "post_reduction", "table1_modes", "fwd_bwd", "precision_form"):
         fn = {"short_transforms": lambda: short_form(pk, torch, dev, args.steps),
               "post_reduction": lambda: post_form(pk, torch, dev, args.steps),
               "table1_modes": lambda: modes_form(pk, torch, dev, args.steps, args.ring),
-              "fwd_bwd": lambda: differentiation_form(pk, torch, dev, args.steps, 2)}[args.only]
+              "fwd_bwd": lambda: differentiation_form(pk, torch, dev, args.steps, 2),
+              "precision_form": lambda: precision_form(pk, torch, dev, args.steps, 1, with_oracle=False)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     inst = synth.make_paper()
