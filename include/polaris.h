@@ -138,7 +138,8 @@ ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_
 
 /*
  * Schedule of one instance's passes (what the autotuner chooses; every field 0 = the default):
- *   log2_n1         the split N = N1 x N2 of the four-step transform (default floor(log2 N / 2));
+ *   log2_n1         the split N = N1 x N2 of the four-step transform (default floor(log2 N / 2), but 10 for
+ *                   2^19 and 9 for 2^20 points with FP32 passes);
  *   colpass_cols    columns per column-pass workgroup (its LDS tile width and workgroup size);
  *   rowpass_frames  frames per row-pass workgroup batch (its workgroup size);
  *   col_wg_per_cu   column-pass workgroups per CU that the frame grouping aims at (1 .. 8);

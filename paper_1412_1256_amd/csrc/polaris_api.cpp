@@ -333,9 +333,17 @@ ps_status upload(ps_plan_t plan, size_t off, const void* src, size_t bytes) {
   return PS_OK;
 }
 
-// Accumulator slots: enough row-pass frame groups that units x pairs x slots reach about 256 workgroups
-// (1 for the 16-bit passes, whose row pass spreads frames over its waves).
-// the single pass runs FP32 transforms of 2^8 .. 2^14 points
+// Default split N = N1 x N2 (log2 N1) of the four-step passes: N1 = 2^floor(m/2), except where timing on the
+// device favours another: 2^19 as 1024 x 512 (rows of 512 points stay wave-local) and 2^20 as 512 x 2048.
+int default_log2_n1(const ps_instance& c) {
+  const int m = ilog2_exact(c.fft_len);
+  if (c.precision != PS_PREC_FP32) return m / 2;
+  if (m == 19) return 10;
+  if (m == 20) return 9;
+  return m / 2;
+}
+
+// the single pass runs FP32 transforms of 2^8 .. 2^12 points
 bool fused_eligible(const ps_instance& c) {
   const int m = ilog2_exact(c.fft_len);
   return c.precision == PS_PREC_FP32 && m >= ps::kFusedMinLog2 && m <= ps::kFusedMaxLog2;
@@ -355,6 +363,8 @@ int default_slots_fused(const ps_instance& c) {
   return G;
 }
 
+// Accumulator slots: enough row-pass frame groups that units x pairs x slots reach about 256 workgroups
+// (1 for the 16-bit passes, whose row pass spreads frames over its waves).
 int default_slots(const ps_instance& c, int N1, int N2) {
   if (c.precision != PS_PREC_FP32) return 1;
   const int tiles = N1 / 2 / ps::rowpass_units_per_tile(N2) * c.n_pairs;
@@ -368,7 +378,7 @@ const char* schedule_error(const ps_instance& c, const ps_schedule& s, char* why
   static thread_local char buf[160];
   char* w = why ? why : buf;
   const int m = ilog2_exact(c.fft_len);
-  const int m1 = s.log2_n1 ? s.log2_n1 : m / 2, m2 = m - m1;
+  const int m1 = s.log2_n1 ? s.log2_n1 : default_log2_n1(c), m2 = m - m1;
   if (s.single_pass < 0 || s.single_pass > 2) {
     snprintf(w, 160, "single_pass %d not in 0..2", s.single_pass);
     return w;
@@ -404,8 +414,8 @@ const char* schedule_error(const ps_instance& c, const ps_schedule& s, char* why
     snprintf(w, 160, "split 2^%d x 2^%d outside 2^4 .. 2^11 per pass", m1, m2);
     return w;
   }
-  if (c.window == PS_WIN_TAPS && (m2 > 9 || m1 > 11)) {
-    snprintf(w, 160, "the learnable window's backward needs rows of at most 2^9 points");
+  if (c.window == PS_WIN_TAPS && (m2 > 9 || m1 > 9)) {
+    snprintf(w, 160, "the learnable window's backward needs both passes of at most 2^9 points");
     return w;
   }
   const int N1 = 1 << m1, N2 = 1 << m2;
@@ -819,7 +829,7 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
     I.cfg = inst[i];
     I.N = inst[i].fft_len;
     I.m = ilog2_exact(I.N);
-    I.m1 = (sched && sched[i].log2_n1) ? sched[i].log2_n1 : I.m / 2;
+    I.m1 = (sched && sched[i].log2_n1) ? sched[i].log2_n1 : default_log2_n1(I.cfg);
     I.m2 = I.m - I.m1;
     I.N1 = int64_t(1) << I.m1;
     I.N2 = int64_t(1) << I.m2;
@@ -1240,14 +1250,16 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
   const bool want_taps = grad->d_taps != nullptr;
   if (want_taps) {
     if (!I.taps()) return fail(PS_ERR_ARG, "d_taps requested for an instance without a PS_WIN_TAPS window");
-    if (I.N2 > 512) return fail(PS_ERR_UNSUPPORTED, "the window adjoint is built for fft_len <= 2^18");
+    if (I.N1 > 512 || I.N2 > 512)
+      return fail(PS_ERR_UNSUPPORTED, "the window adjoint is built for passes of at most 512 points (fft_len <= 2^18)");
     if (!packed_dev) return fail(PS_ERR_ARG, "null packed input");
     if (n_samples < 0 || n_samples % I.N) return fail(PS_ERR_SIZE, "n_samples is not a multiple of fft_len");
     if (I.frames_in(n_samples) != I.n_frames)
       return fail(PS_ERR_STATE, "the input has %lld frames but the integration has %lld",
                   (long long)I.frames_in(n_samples), (long long)I.n_frames);
   }
-  if (I.N2 > 512) return fail(PS_ERR_UNSUPPORTED, "the adjoint is built for fft_len <= 2^18");
+  if (I.N1 > 512 || I.N2 > 512)
+    return fail(PS_ERR_UNSUPPORTED, "the adjoint is built for passes of at most 512 points (fft_len <= 2^18)");
   if ((st = reduce_slots(plan, I)) != PS_OK) return st;
   ps::BwChanArgs ca{};
   ca.acc = ws_ptr<double>(plan, I.use_reduced() ? I.off_sumacc : I.off_acc);

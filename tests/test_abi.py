@@ -239,3 +239,18 @@ def test_single_pass_schedules(n, sched, ok):
     assert (st == 0) == ok, pk.lib().ps_last_error()
     if h.value:
         pk.lib().ps_destroy(h)
+
+
+def test_learnable_window_needs_short_passes():
+    """The adjoint's passes are built up to 512 points: a learnable-window instance may not take a split with
+    a longer pass (2^18 as 1024 x 256 or 256 x 1024 is rejected, 512 x 512 accepted)."""
+    inst = pk.Instance(fft_len=1 << 18, bits=8, window="taps", n_taps=64)
+    for sched, ok in ((pk.Schedule(9), True), (pk.Schedule(10), False), (pk.Schedule(8), False)):
+        arr = (pk._Instance * 1)(inst.to_c())
+        sarr = (pk._Schedule * 1)(sched.to_c())
+        h = C.c_void_p()
+        n = C.c_size_t()
+        st = pk.lib().ps_plan_scheduled(arr, sarr, 1, C.byref(h), C.byref(n))
+        assert (st == 0) == ok, (sched, pk.lib().ps_last_error())
+        if h.value:
+            pk.lib().ps_destroy(h)
