@@ -78,7 +78,7 @@ typedef struct ps_plan_s* ps_plan_t;
  *   accum       PS_ACC_FP64 (any precision), or PS_ACC_KAHAN32 (16-bit passes only): the products of
  *               the frames of one pass launch are summed per channel in registers, in FP64 or in
  *               compensated FP32, then added to FP64 accumulators.
- *   chunk_frames  frames processed per internal pass pair (0 = max(64, 2^22 / N)); bounds the workspace.
+ *   chunk_frames  frames processed per internal pass pair (0 = max(64, 2^24 / N)); bounds the workspace.
  *   sample_rate_hz  metadata only (channel width = sample_rate_hz / N).
  *   hop         segmentation (Sec. 3.1, 50 % overlap): frame f of the stream starts at sample f * hop;
  *               0 or N = contiguous frames, N/2 = 50 % overlap, N/4 or N/8 = 75 or 87.5 %.  An integration
@@ -138,14 +138,16 @@ ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_
 
 /*
  * Schedule of one instance's passes (what the autotuner chooses; every field 0 = the default):
- *   log2_n1         the split N = N1 x N2 of the four-step transform (default floor(log2 N / 2), but 10 for
- *                   2^19 and 9 for 2^20 points with FP32 passes);
+ *   log2_n1         the split N = N1 x N2 of the four-step transform (default floor(log2 N / 2); with FP32
+ *                   passes 7, 8, 7, 8, 9 for 2^13 .. 2^17 points, 10 for 2^19 and 9 for 2^20);
  *   colpass_cols    columns per column-pass workgroup (its LDS tile width and workgroup size);
  *   rowpass_frames  frames per row-pass workgroup batch (its workgroup size);
- *   col_wg_per_cu   column-pass workgroups per CU that the frame grouping aims at (1 .. 8);
+ *   col_wg_per_cu   column-pass workgroups per CU that the frame grouping aims at (1 .. 8; default 4 for
+ *                   2^13, 2 for 2^14 .. 2^16 points with FP32 passes, else 1);
  *   rowpass_slots   accumulator slots G (a power of two, 1 .. 64; 1 .. 8192 in a single pass): frame a of
  *                   the integration goes to slot a mod G, so G frame groups run in parallel; readers sum the
- *                   slots in order.  Default: enough for about 256 row-pass workgroups (1 for 16-bit
+ *                   slots in order.  Default: enough for about 256 row-pass workgroups (512 up to 2^17
+ *                   points; 1 for 16-bit
  *                   passes; 2^21 / (N n_pairs) rounded down to a power of two, at most 8192, in a
  *                   single pass).
  *   single_pass     0: the default (a single pass for FP32 transforms of 2^8 .. 2^12 points, else the

@@ -335,12 +335,29 @@ ps_status upload(ps_plan_t plan, size_t off, const void* src, size_t bytes) {
 
 // Default split N = N1 x N2 (log2 N1) of the four-step passes: N1 = 2^floor(m/2), except where timing on the
 // device favours another: 2^19 as 1024 x 512 (rows of 512 points stay wave-local) and 2^20 as 512 x 2048.
+// Default FP32 schedules of the four-step passes, from whole-integration timings on the device (2^25 samples
+// per stream and integration, int8 and 2-bit): 2^13 .. 2^17 run with the longer column pass first and 2 or 4
+// column-pass workgroups per CU; 2^19 as 1024 x 512, 2^20 as 512 x 2048.
 int default_log2_n1(const ps_instance& c) {
   const int m = ilog2_exact(c.fft_len);
   if (c.precision != PS_PREC_FP32) return m / 2;
-  if (m == 19) return 10;
-  if (m == 20) return 9;
-  return m / 2;
+  switch (m) {
+    case 13: return 7;
+    case 14: return 8;
+    case 15: return 7;
+    case 16: return 8;
+    case 17: return 9;
+    case 19: return 10;
+    case 20: return 9;
+    default: return m / 2;
+  }
+}
+
+int default_col_wgs(const ps_instance& c) {
+  const int m = ilog2_exact(c.fft_len);
+  if (c.precision != PS_PREC_FP32) return 1;
+  if (m == 13) return 4;
+  return (m >= 14 && m <= 16) ? 2 : 1;
 }
 
 // the single pass runs FP32 transforms of 2^8 .. 2^12 points
@@ -363,13 +380,15 @@ int default_slots_fused(const ps_instance& c) {
   return G;
 }
 
-// Accumulator slots: enough row-pass frame groups that units x pairs x slots reach about 256 workgroups
-// (1 for the 16-bit passes, whose row pass spreads frames over its waves).
+// Accumulator slots: enough row-pass frame groups that units x pairs x slots reach about 256 workgroups,
+// 512 for frames of at most 2^17 points (shorter row passes; twice the slots measured faster there), and 1
+// for the 16-bit passes, whose row pass spreads frames over its waves.
 int default_slots(const ps_instance& c, int N1, int N2) {
   if (c.precision != PS_PREC_FP32) return 1;
   const int tiles = N1 / 2 / ps::rowpass_units_per_tile(N2) * c.n_pairs;
+  const int target = c.fft_len <= (1 << 17) ? 512 : 256;
   int G = 1;
-  while (G < 64 && G * tiles < 256) G *= 2;
+  while (G < 64 && G * tiles < target) G *= 2;
   return G;
 }
 
@@ -837,12 +856,13 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
     I.hop = inst[i].hop ? inst[i].hop : I.N;
     I.cols = (sched && sched[i].colpass_cols) ? sched[i].colpass_cols : ps::colpass_cols((int)I.N1);
     I.fb = (sched && sched[i].rowpass_frames) ? sched[i].rowpass_frames : ps::rowpass_frames((int)I.N2);
-    I.col_wgs = (sched && sched[i].col_wg_per_cu) ? sched[i].col_wg_per_cu : 1;
+    I.col_wgs = (sched && sched[i].col_wg_per_cu) ? sched[i].col_wg_per_cu : default_col_wgs(inst[i]);
     I.fused = uses_fused(I.cfg, sched ? &sched[i] : nullptr);
     I.G = (sched && sched[i].rowpass_slots) ? sched[i].rowpass_slots
                                              : (I.fused ? default_slots_fused(I.cfg) : default_slots(I.cfg, (int)I.N1, (int)I.N2));
-    // short transforms take more frames per pass (inter-pass buffer of at most 32 MiB per pair)
-    I.chunk = inst[i].chunk_frames ? inst[i].chunk_frames : (int64_t)std::max<int64_t>(64, (int64_t(1) << 22) / I.N);
+    // short transforms take more frames per pass: 2^24 points (a 128 MiB inter-pass buffer per pair), so the
+    // fixed cost of a pass pair (first loads, last stores, setup) is spread over as many frames as at 2^18
+    I.chunk = inst[i].chunk_frames ? inst[i].chunk_frames : (int64_t)std::max<int64_t>(64, (int64_t(1) << 24) / I.N);
     // word loads of the column pass: 2-, 4- and 8-bit codes of two streams correlated as (0, 1), or of four
     // streams (any pairs)
     if (inst[i].bits <= 8 && inst[i].n_streams == 2 && inst[i].n_pairs == 1 && inst[i].pair_x[0] == 0 &&
