@@ -148,7 +148,7 @@ ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_
  *                   the integration goes to slot a mod G, so G frame groups run in parallel; readers sum the
  *                   slots in order.  Default: enough for about 256 row-pass workgroups (512 up to 2^17
  *                   points; 1 for 16-bit
- *                   passes; 2^21 / (N n_pairs) rounded down to a power of two, at most 8192, in a
+ *                   passes; 2^20 / (N n_pairs) rounded down to a power of two, at most 8192, in a
  *                   single pass).
  *   single_pass     0: the default (a single pass for FP32 transforms of 2^8 .. 2^12 points, else the
  *                   four-step passes); 1: a single pass (each workgroup transforms whole frames in LDS

@@ -371,10 +371,11 @@ bool uses_fused(const ps_instance& c, const ps_schedule* s) {
   return !s || s->single_pass != 2;
 }
 
-// N/8-thread workgroups, one per slot and pair: about 2^21 / N of them (some 4000 waves) fill the device,
-// and the slots then hold 32 MiB whatever N is
+// N/8-thread workgroups, one per slot and pair: about 2^20 / N of them (some 2000 waves, each then walking
+// twice as many frames as with 2^21 / N, which measured 7-17 % slower at 2^10 .. 2^12), and the slots hold
+// 16 MiB whatever N is
 int default_slots_fused(const ps_instance& c) {
-  const int64_t target = (int64_t(1) << 21) / c.fft_len;
+  const int64_t target = (int64_t(1) << 20) / c.fft_len;
   int G = 1;
   while (2 * G * c.n_pairs <= target && 2 * G <= 8192) G *= 2;
   return G;

@@ -145,7 +145,7 @@ def test_schedule_candidates_and_scheduled_plans():
     assert small == {32, 64}
     # short transforms also list the single pass, with slots around 512 / n_pairs
     single = {c for c in pk.schedule_candidates(pk.Instance(fft_len=1 << 12)) if c.single_pass == 1}
-    assert single == {pk.Schedule(6, 0, 0, 0, G, 1) for G in (128, 256, 512, 1024)}  # default 2^21 / 2^12 = 512
+    assert single == {pk.Schedule(6, 0, 0, 0, G, 1) for G in (64, 128, 256, 512)}  # default 2^20 / 2^12 = 256
     assert not any(c.single_pass == 1 for c in pk.schedule_candidates(pk.Instance(fft_len=1 << 13)))
     # tiny transform: only the split that keeps both passes >= 16 points
     assert {c.log2_n1 for c in pk.schedule_candidates(pk.Instance(fft_len=256))} == {4}
