@@ -116,6 +116,35 @@ def test_fft_lengths_float_input(pk, torch_dev, logn):
     assert np.all(e < TOL), e
 
 
+@pytest.mark.parametrize("logn,F", [(13, 300), (14, 150), (15, 80), (16, 48), (17, 40)])
+def test_default_schedules_many_frames(pk, torch_dev, logn, F):
+    """2-bit pair, Hann window, the default schedules of 2^13 .. 2^17 points (longer column pass first,
+    several column-pass workgroups per CU, row-pass slots aimed at 512 workgroups) over enough frames that
+    every frame group and slot is used; one call against the oracle, three calls bitwise equal to one."""
+    torch, dev = torch_dev
+    N = 1 << logn
+    say(f"default schedule 2^{logn}, {F} frames")
+    inst = synth.make_correlated_noise(2, 0.35, N, F, seed_extra=500 + logn, window="hann")
+    acc, nf, s2, _ = oracle.run_instance(inst)
+    ref = oracle.stokes(acc, nf, s2, psi=0.3)
+    spec, gnf, st = run_gpu(pk, torch, dev, inst, psi=0.3)
+    assert gnf == nf == F
+    es, e = spectra_err(spec, acc), stokes_err(st, ref)
+    say(f"  spectra {es.max()} stokes {e.ravel().tolist()}")
+    assert np.all(es < TOL) and np.all(e < TOL), (es, e)
+    plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev)
+    packed = torch.from_numpy(inst["packed"]).to(dev)
+    per = N * 2 * 2 // 8
+    cuts = [0, (F // 3) * per, (2 * F // 3 + 1) * per, F * per]
+    plan.reset()
+    for c in range(3):
+        plan.accumulate(packed[cuts[c]:cuts[c + 1]])
+    split, nf2 = plan.spectra()
+    torch.cuda.synchronize(dev)
+    assert nf2 == F
+    assert np.array_equal(split.cpu().numpy(), spec)
+
+
 @pytest.mark.parametrize("logn", [21, 22])
 def test_largest_lengths(pk, torch_dev, logn):
     torch, dev = torch_dev
