@@ -381,16 +381,29 @@ int default_slots_fused(const ps_instance& c) {
   return G;
 }
 
-// Accumulator slots: enough row-pass frame groups that units x pairs x slots reach about 256 workgroups,
-// 512 for frames of at most 2^17 points (shorter row passes; twice the slots measured faster there), and 1
-// for the 16-bit passes, whose row pass spreads frames over its waves.
+// Accumulator slots: enough row-pass frame groups that units x pairs x slots reach about 512 workgroups for
+// frames of at most 2^18 points and 256 beyond (twice the slots measured faster up to 2^18), and 1 for the
+// 16-bit passes, whose row pass spreads frames over its waves.
+int rowpass_tiles(const ps_instance& c, int N1, int N2) {
+  return N1 / 2 / ps::rowpass_units_per_tile(N2) * c.n_pairs;
+}
+
 int default_slots(const ps_instance& c, int N1, int N2) {
   if (c.precision != PS_PREC_FP32) return 1;
-  const int tiles = N1 / 2 / ps::rowpass_units_per_tile(N2) * c.n_pairs;
-  const int target = c.fft_len <= (1 << 17) ? 512 : 256;
+  const int tiles = rowpass_tiles(c, N1, N2);
+  const int target = c.fft_len <= (1 << 18) ? 512 : 256;
   int G = 1;
   while (G < 64 && G * tiles < target) G *= 2;
   return G;
+}
+
+// Row-pass frames per batch: 512-point rows of frames of at most 2^18 points in batches of 4 (512-thread
+// workgroups, two per CU) once there are at least 512 row-pass workgroups (2^18, one pair: 73.0 vs 74.7 us
+// per integration; batches of 4 with half the workgroups, or of 8 with twice the slots, were slower).
+int default_rowpass_frames(const ps_instance& c, int N1, int N2, int G) {
+  if (c.precision == PS_PREC_FP32 && N2 == 512 && c.fft_len <= (1 << 18) && rowpass_tiles(c, N1, N2) * G >= 512)
+    return 4;
+  return ps::rowpass_frames(N2);
 }
 
 // Why a schedule cannot run an instance (nullptr when it can).  why: optional message buffer (160 bytes).
@@ -856,11 +869,12 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
     I.C = I.N / 2;
     I.hop = inst[i].hop ? inst[i].hop : I.N;
     I.cols = (sched && sched[i].colpass_cols) ? sched[i].colpass_cols : ps::colpass_cols((int)I.N1);
-    I.fb = (sched && sched[i].rowpass_frames) ? sched[i].rowpass_frames : ps::rowpass_frames((int)I.N2);
     I.col_wgs = (sched && sched[i].col_wg_per_cu) ? sched[i].col_wg_per_cu : default_col_wgs(inst[i]);
     I.fused = uses_fused(I.cfg, sched ? &sched[i] : nullptr);
     I.G = (sched && sched[i].rowpass_slots) ? sched[i].rowpass_slots
                                              : (I.fused ? default_slots_fused(I.cfg) : default_slots(I.cfg, (int)I.N1, (int)I.N2));
+    I.fb = (sched && sched[i].rowpass_frames) ? sched[i].rowpass_frames
+                                              : default_rowpass_frames(I.cfg, (int)I.N1, (int)I.N2, (int)I.G);
     // short transforms take more frames per pass: 2^24 points (a 128 MiB inter-pass buffer per pair), so the
     // fixed cost of a pass pair (first loads, last stores, setup) is spread over as many frames as at 2^18
     I.chunk = inst[i].chunk_frames ? inst[i].chunk_frames : (int64_t)std::max<int64_t>(64, (int64_t(1) << 24) / I.N);
