@@ -75,10 +75,11 @@ def _input_ring(instance: Instance, frames: int, device) -> list:
 
 
 def time_schedule(instance: Instance, sched: Schedule, device, frames: int, reps: int = 5, warmup: int = 2,
-                  ring: list | None = None) -> float:
-    """Median time (ms) of one whole integration: reset, accumulate `frames` frames from the next buffer of
-    the input ring, Stokes (the Stokes pass sums the accumulator slots, so its cost depends on the schedule
-    too)."""
+                  ring: list | None = None, inner: int = 8) -> float:
+    """Time (ms) of one whole integration: reset, accumulate `frames` frames from the next buffer of the input
+    ring, Stokes (the Stokes pass sums the accumulator slots, so its cost depends on the schedule too).  Each
+    of the `reps` samples times `inner` consecutive integrations (single integrations of some 70 us are too
+    short to rank schedules a few percent apart); the median sample is returned."""
     import torch
     plan = Plan([instance], device=device, schedules=[sched])
     ring = ring if ring is not None else _input_ring(instance, frames, device)
@@ -99,10 +100,11 @@ def time_schedule(instance: Instance, sched: Schedule, device, frames: int, reps
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(plan.stream)
-        step()
+        for _ in range(inner):
+            step()
         b.record(plan.stream)
         b.synchronize()
-        times.append(a.elapsed_time(b))
+        times.append(a.elapsed_time(b) / inner)
     times.sort()
     return times[len(times) // 2]
 
@@ -124,6 +126,9 @@ def tune(instance: Instance, device=None, frames: int | None = None, reps: int =
         return Schedule(**d[key]["schedule"]), d[key].get("timings_ms", {})
     frames = frames or default_frames(instance)
     ring = _input_ring(instance, frames, device)
+    # the first hundred or so integrations after start-up run several percent slow (clocks, first touches of
+    # the input ring): run them before the first candidate is timed
+    time_schedule(instance, Schedule(), device, frames, reps=1, warmup=0, ring=ring, inner=max(32, 2 * len(ring)))
     timings = {}
     best, best_ms = None, float("inf")
     for s in schedule_candidates(instance):
