@@ -142,8 +142,8 @@ ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_
  *                   passes 7, 8, 7, 8, 9 for 2^13 .. 2^17 points, 10 for 2^19 and 9 for 2^20);
  *   colpass_cols    columns per column-pass workgroup (its LDS tile width and workgroup size);
  *   rowpass_frames  frames per row-pass workgroup batch (its workgroup size; default 8, 4 for 1024-point
- *                   rows, 2 for 2048, and 4 for 512-point rows of frames of at most 2^18 points once the
- *                   row pass has 512 or more workgroups);
+ *                   rows, 2 for 2048, and 4 for 512-point rows once the row pass has 512 or more
+ *                   workgroups);
  *   col_wg_per_cu   column-pass workgroups per CU that the frame grouping aims at (1 .. 8; default 4 for
  *                   2^13, 2 for 2^14 .. 2^16 points with FP32 passes, else 1);
  *   rowpass_slots   accumulator slots G (a power of two, 1 .. 64; 1 .. 8192 in a single pass): frame a of

@@ -397,12 +397,11 @@ int default_slots(const ps_instance& c, int N1, int N2) {
   return G;
 }
 
-// Row-pass frames per batch: 512-point rows of frames of at most 2^18 points in batches of 4 (512-thread
-// workgroups, two per CU) once there are at least 512 row-pass workgroups (2^18, one pair: 73.0 vs 74.7 us
-// per integration; batches of 4 with half the workgroups, or of 8 with twice the slots, were slower).
+// Row-pass frames per batch: 512-point rows in batches of 4 (512-thread workgroups, two per CU) once there
+// are at least 512 row-pass workgroups (2^18, one pair: 73.0 vs 74.7 us per integration, where batches of 4
+// with half the workgroups, or of 8 with twice the slots, were slower; 2^19: 6 % faster).
 int default_rowpass_frames(const ps_instance& c, int N1, int N2, int G) {
-  if (c.precision == PS_PREC_FP32 && N2 == 512 && c.fft_len <= (1 << 18) && rowpass_tiles(c, N1, N2) * G >= 512)
-    return 4;
+  if (c.precision == PS_PREC_FP32 && N2 == 512 && rowpass_tiles(c, N1, N2) * G >= 512) return 4;
   return ps::rowpass_frames(N2);
 }
 
