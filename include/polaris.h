@@ -19,7 +19,7 @@
  *     except ps_bind itself and the descriptor upload described next.  ps_reset, ps_accumulate,
  *     ps_spectra, ps_stokes, ps_stokes_all, ps_set_window_taps and ps_calibrate_backward enqueue kernels
  *     only (no allocation or memset), so they can be captured into a hipGraph (ps_graph_begin).
- *   - Plans of several instances run each pass as grouped persistent launches (the batching form), whose
+ *   - Plans of several instances run each pass as grouped launches (the batching form), whose
  *     per-instance launch descriptors live in the workspace.  ps_accumulate and ps_stokes_all upload them
  *     (waiting for the stream, then one copy from pinned host memory) only when they differ from the
  *     previous call's, e.g. new buffers or frame counts; during a capture they must be unchanged.
@@ -194,8 +194,8 @@ ps_status ps_reset(ps_plan_t plan);
  * Frames are added in order; with FP32 passes, splitting one input over several calls gives bitwise the
  * same sums (with 16-bit passes the same up to the rounding of the per-launch sums).
  * In a plan of several instances, the FP32 instances of a call run together: per chunk round, instances of
- * one shape class (split, sample format, schedule) share a persistent column-pass launch and a row-pass
- * launch that walk the tiles of all of them, in sub-batches of at most 128 MB of inter-pass data, each row
+ * one shape class (split, sample format, schedule) share a column-pass launch and a row-pass launch with
+ * one workgroup per tile of all of them, in sub-batches of at most 128 MB of inter-pass data, each row
  * pass right after its column pass (up to 8 chunk rounds per call; beyond that instance by instance). */
 ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples);
 
@@ -209,7 +209,7 @@ ps_status ps_spectra(ps_plan_t plan, int32_t inst, double* out_dev, int64_t* n_f
  * (unit gains, no leakage, psi = 0).  The integration is read, not consumed. */
 ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv_dev);
 
-/* Stokes spectra of every instance whose iquv_dev[i] is not NULL, in one persistent launch (the batching
+/* Stokes spectra of every instance whose iquv_dev[i] is not NULL, in one launch (the batching
  * form).  cal: NULL or an array of n_inst calibrations; iquv_dev: n_inst device pointers, each
  * [n_pairs][4][C] floats.  PS_ERR_STATE if a selected instance has no accumulated frame. */
 ps_status ps_stokes_all(ps_plan_t plan, const ps_cal* cal, float* const* iquv_dev);

@@ -559,7 +559,7 @@ void append_bytes(std::vector<unsigned char>& v, const T* p, size_t n) {
 }
 
 // Batching form: every FP32 instance of the call in one column-pass launch per (N1, format) and one row-pass
-// launch per N2, per chunk round; each launch is a persistent grid walking the tiles of all its instances.
+// launch per N2, per chunk round; each launch has one workgroup per tile of all its instances.
 ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples,
                              std::vector<char>& done) {
   int64_t rounds = 0;
@@ -652,7 +652,6 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
     ps::BatchArgs b{};
     b.n_tasks = (int32_t)l.n;
     b.total = l.total;
-    b.n_cu = plan->n_cu;
     hipError_t e;
     if (l.kind == 0) {
       b.tasks = dev + l.task0 * sizeof(ps::ColArgs);
@@ -1174,7 +1173,6 @@ ps_status ps_stokes_all(ps_plan_t plan, const ps_cal* cal, float* const* iquv_de
   b.tile_end = reinterpret_cast<const int32_t*>(dev + ends_at);
   b.n_tasks = (int32_t)outs.size();
   b.total = total;
-  b.n_cu = plan->n_cu;
   hipError_t e = timed(plan, PS_KERNEL_STOKES, [&](const ps::Launch& l) { return ps::launch_output_batch(true, b, l); });
   if (e != hipSuccess) return hip_fail(e, "grouped stokes launch");
   return PS_OK;

@@ -166,13 +166,12 @@ struct Launch {
   hipEvent_t stop;
 };
 
-// ---- batching form: one persistent launch per pass and shape over the tiles of many instances
+// ---- batching form: one launch per pass and shape over the tiles of many instances, a workgroup per tile
 struct BatchArgs {
   const void* tasks;        // device array of ColArgs / RowArgs / OutArgs, one per instance
   const int32_t* tile_end;  // device array: running total of tiles up to and including each task
   int32_t n_tasks;
-  int32_t total;            // tiles of all tasks
-  int32_t n_cu;             // compute units (the grid is the resident workgroups, at most `total`)
+  int32_t total;            // tiles of all tasks (the grid; at least 1)
 };
 
 hipError_t launch_colpass_batch(int N1, int cols, int bits, int mode, const BatchArgs& b, const Launch& l);

@@ -214,25 +214,28 @@ __global__ void __launch_bounds__(L * COLS / (8 * V)) k_colpass_hist(ColArgs a) 
   colpass_tile<L, COLS, V, BITS, FAST, true>(a, xcd_remap((int)blockIdx.x, (int)gridDim.x));
 }
 
-// Batched (persistent) column pass over the tiles of several instances of the same shape and format: each
-// workgroup walks the global tile list with a grid stride; tile_end holds the running tile totals.  The
-// task descriptors are read through the constant address space (scalar loads into SGPRs).
+// Grouped column pass over the tiles of several instances of the same shape and format: one workgroup per
+// tile (a loop over tiles in each workgroup cost 10-30 registers and often a wave per SIMD).  tile_end holds
+// the running tile totals; the task descriptors are read through the constant address space (scalar loads
+// into SGPRs).  The grid is the tile count, renumbered as the single-instance launch does so that
+// neighbouring column blocks run on one XCD.
+__device__ __forceinline__ int batch_task(const int32_t* __restrict__ tile_end, int n_tasks, int tile) {
+  int lo = 0, hi = n_tasks - 1;  // first task whose running total exceeds the tile
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (tile < tile_end[mid]) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
 template <int L, int COLS, int V, int BITS, int FAST>
 __global__ void __launch_bounds__(L * COLS / (8 * V))
     k_colpass_batch(const ColArgs* __restrict__ tasks, const int32_t* __restrict__ tile_end, int n_tasks) {
-  const int total = tile_end[n_tasks - 1];
-  int t = 0;
-  for (int slot = (int)blockIdx.x; slot < total; slot += (int)gridDim.x) {
-    // the grid is a multiple of 8 (or all tiles), so every slot of this workgroup runs on its XCD: renumber
-    // as the single-instance launch does, keeping neighbouring column blocks on one XCD (increasing per
-    // workgroup, so the task scan stays monotonic)
-    const int tile = xcd_remap(slot, total);
-    while (tile >= tile_end[t]) ++t;
-    const int begin = t ? tile_end[t - 1] : 0;
-    const ColArgs a = load_const(tasks + t);
-    colpass_tile<L, COLS, V, BITS, FAST>(a, tile - begin);
-    __syncthreads();  // the next tile reuses the LDS tile
-  }
+  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int t = batch_task(tile_end, n_tasks, tile);
+  const ColArgs a = load_const(tasks + t);
+  colpass_tile<L, COLS, V, BITS, FAST>(a, tile - (t ? tile_end[t - 1] : 0));
 }
 
 // one tile of the row pass: units bx*UB .. bx*UB+UB-1 of pair p, the launch's frames of accumulator slot g
@@ -356,16 +359,12 @@ __global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
 template <int L, int UB, int FB, int SQ>
 __global__ void __launch_bounds__(UB * FB * L / (4 * SQ))
     k_rowpass_batch(const RowArgs* __restrict__ tasks, const int32_t* __restrict__ tile_end, int n_tasks) {
-  const int total = tile_end[n_tasks - 1];
-  int t = 0;
-  for (int tile = (int)blockIdx.x; tile < total; tile += (int)gridDim.x) {
-    while (tile >= tile_end[t]) ++t;
-    const int local = tile - (t ? tile_end[t - 1] : 0);
-    const RowArgs a = load_const(tasks + t);
-    const int nbx = a.N1 / 2 / UB;
-    rowpass_tile<L, UB, FB, SQ>(a, local % nbx, (local / nbx) % a.P, local / (nbx * a.P));
-    __syncthreads();
-  }
+  const int tile = (int)blockIdx.x;
+  const int t = batch_task(tile_end, n_tasks, tile);
+  const int local = tile - (t ? tile_end[t - 1] : 0);
+  const RowArgs a = load_const(tasks + t);
+  const int nbx = a.N1 / 2 / UB;
+  rowpass_tile<L, UB, FB, SQ>(a, local % nbx, (local / nbx) % a.P, local / (nbx * a.P));
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -493,16 +492,12 @@ __host__ __device__ inline int output_tiles_y(int N2) { return N2 / 2 / (N2 / 2 
 template <bool STOKES>
 __global__ void __launch_bounds__(kOutThreads)
     k_output_batch(const OutArgs* __restrict__ tasks, const int32_t* __restrict__ tile_end, int n_tasks) {
-  const int total = tile_end[n_tasks - 1];
-  int t = 0;
-  for (int tile = (int)blockIdx.x; tile < total; tile += (int)gridDim.x) {
-    while (tile >= tile_end[t]) ++t;
-    const int local = tile - (t ? tile_end[t - 1] : 0);
-    const OutArgs a = load_const(tasks + t);
-    const int nx = output_tiles_x(a.N1), ny = output_tiles_y(a.N2);
-    output_tile<STOKES>(a, local % nx, (local / nx) % ny, local / (nx * ny));
-    __syncthreads();
-  }
+  const int tile = (int)blockIdx.x;
+  const int t = batch_task(tile_end, n_tasks, tile);
+  const int local = tile - (t ? tile_end[t - 1] : 0);
+  const OutArgs a = load_const(tasks + t);
+  const int nx = output_tiles_x(a.N1), ny = output_tiles_y(a.N2);
+  output_tile<STOKES>(a, local % nx, (local / nx) % ny, local / (nx * ny));
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -677,50 +672,22 @@ hipError_t launch_rowpass(int N2, int fb, const RowArgs& a, const Launch& s) {
   }
 }
 
-// ---- batched (persistent) launches: grid = min(tiles, workgroups resident on the device)
+// ---- grouped launches: one workgroup per tile of all the launch's instances
 
-// workgroups of a kernel resident on one CU, queried once per kernel (not a stream operation, so a launch
-// made during graph capture after a first eager launch needs no query)
-template <class K>
-static int resident_per_cu(K kernel, int block) {
-  static std::mutex mu;
-  static std::unordered_map<const void*, int> cache;
-  std::lock_guard<std::mutex> lock(mu);
-  const void* key = reinterpret_cast<const void*>(kernel);
-  auto it = cache.find(key);
-  if (it != cache.end()) return it->second;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-  cache[key] = per_cu;
-  return per_cu;
-}
-
-// all tiles, or the resident workgroups rounded down to a multiple of the 8 XCDs (dispatch is round-robin
-// over the XCDs, so a workgroup's grid-stride slots then all run on one XCD)
-template <class K>
-static unsigned persistent_grid(K kernel, int block, int total, int n_cu) {
-  long resident = (long)resident_per_cu(kernel, block) * n_cu;
-  if (resident >= 16) resident -= resident % 8;
-  return (unsigned)(total < resident ? total : resident);
-}
-
-#define PS_LAUNCH_BATCH(kernel, block, total, n_cu, l, ...)                                          \
-  do {                                                                                             \
-    const unsigned g_ = persistent_grid(kernel, block, total, n_cu);                               \
-    hipExtLaunchKernelGGL(kernel, dim3(g_), dim3(block), 0, (l).stream, (l).start, (l).stop, 0, __VA_ARGS__); \
-  } while (0)
+#define PS_LAUNCH_BATCH(kernel, block, total, l, ...)                                                   \
+  hipExtLaunchKernelGGL(kernel, dim3((unsigned)(total)), dim3(block), 0, (l).stream, (l).start, (l).stop, 0, __VA_ARGS__)
 
 template <int L, int COLS, int V, int BITS>
 static void colpass_batch_mode(int mode, const BatchArgs& b, const Launch& s) {
   constexpr int block = L * COLS / (8 * V);
   const ColArgs* t = static_cast<const ColArgs*>(b.tasks);
   if constexpr (BITS == 32) {
-    PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 32, 0>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+    PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, 32, 0>), block, b.total, s, t, b.tile_end, b.n_tasks);
     return;
   }
-  if (mode == 1) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, BITS, 1>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
-  else if (mode == 2) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, BITS, 2>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
-  else PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, BITS, 0>), block, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+  if (mode == 1) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, BITS, 1>), block, b.total, s, t, b.tile_end, b.n_tasks);
+  else if (mode == 2) PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, BITS, 2>), block, b.total, s, t, b.tile_end, b.n_tasks);
+  else PS_LAUNCH_BATCH((k_colpass_batch<L, COLS, V, BITS, 0>), block, b.total, s, t, b.tile_end, b.n_tasks);
 }
 
 template <int L, int COLS, int V>
@@ -758,7 +725,7 @@ hipError_t launch_colpass_batch(int N1, int cols, int bits, int mode, const Batc
 template <int L, int UB, int FB, int SQ>
 static hipError_t rowpass_batch_launch(const BatchArgs& b, const Launch& s) {
   constexpr int block = UB * FB * L / (4 * SQ);
-  PS_LAUNCH_BATCH((k_rowpass_batch<L, UB, FB, SQ>), block, b.total, b.n_cu, s,
+  PS_LAUNCH_BATCH((k_rowpass_batch<L, UB, FB, SQ>), block, b.total, s,
                   static_cast<const RowArgs*>(b.tasks), b.tile_end, b.n_tasks);
   return hipGetLastError();
 }
@@ -789,8 +756,8 @@ int output_tiles(int N1, int N2, int P) { return output_tiles_x(N1) * output_til
 
 hipError_t launch_output_batch(bool stokes, const BatchArgs& b, const Launch& s) {
   const OutArgs* t = static_cast<const OutArgs*>(b.tasks);
-  if (stokes) PS_LAUNCH_BATCH((k_output_batch<true>), kOutThreads, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
-  else PS_LAUNCH_BATCH((k_output_batch<false>), kOutThreads, b.total, b.n_cu, s, t, b.tile_end, b.n_tasks);
+  if (stokes) PS_LAUNCH_BATCH((k_output_batch<true>), kOutThreads, b.total, s, t, b.tile_end, b.n_tasks);
+  else PS_LAUNCH_BATCH((k_output_batch<false>), kOutThreads, b.total, s, t, b.tile_end, b.n_tasks);
   return hipGetLastError();
 }
 
