@@ -341,28 +341,46 @@ __global__ void __launch_bounds__(kNT) k_allan_total(AllanArgs a, int64_t chunks
 }
 
 // The same for series stored side by side (series_stride 1, e.g. one series per channel of a run of
-// integrations [t][channel]): one thread per series, so a wave's loads are consecutive addresses.  One sweep
-// over t serves up to 8 lags (their sums in registers), so the rows t - L, t, t + L of nearby lags are
-// reused from cache; each lag still adds its terms in t order.
-__global__ void __launch_bounds__(kNT) k_allan_cols(AllanArgs a) {
-  const int64_t s = (int64_t)blockIdx.x * kNT + threadIdx.x;
-  if (s >= a.n_series) return;
-  const float* x = a.x + s;
+// integrations [t][channel]): a wave holds 64 consecutive series, so its loads are consecutive addresses, and
+// the t range of each series is cut into kColsSlices slices handled by the workgroup's waves (one thread per
+// series and slice: a single thread sweeping all t paid one memory round trip per step).  One sweep serves
+// up to 8 lags (their sums in registers), so the rows t - L, t, t + L of nearby lags are reused from cache;
+// each slice adds its terms in t order and the slices' sums are added in slice order (a fixed order).
+constexpr int kColsSeries = 64, kColsSlices = 4;
+
+__global__ void __launch_bounds__(kColsSeries * kColsSlices) k_allan_cols(AllanArgs a) {
+  constexpr int LG = 8;
+  __shared__ double red[kColsSlices][LG][2][kColsSeries];
+  __shared__ double msum[kColsSlices][2][kColsSeries];
+  const int lane = (int)threadIdx.x % kColsSeries, slice = (int)threadIdx.x / kColsSeries;
+  const int64_t s = (int64_t)blockIdx.x * kColsSeries + lane;
+  const bool valid = s < a.n_series;  // every thread still takes part in the barriers
+  const float* x = a.x + (valid ? s : 0);
   const int64_t P = a.n_points, st = a.point_stride;
+  const int64_t t0 = P * slice / kColsSlices, t1 = P * (slice + 1) / kColsSlices;
   double mean2 = 1.0;
   if (a.normalize) {
     double sum = 0.0, n = 0.0;
-    for (int64_t t = 0; t < P; ++t) {
-      const float v = x[t * st];
-      if (isfinite(v)) {
-        sum += (double)v;
-        n += 1.0;
+    if (valid)
+      for (int64_t t = t0; t < t1; ++t) {
+        const float v = x[t * st];
+        if (isfinite(v)) {
+          sum += (double)v;
+          n += 1.0;
+        }
       }
+    msum[slice][0][lane] = sum;
+    msum[slice][1][lane] = n;
+    __syncthreads();
+    double S = 0.0, N = 0.0;
+#pragma unroll
+    for (int k = 0; k < kColsSlices; ++k) {
+      S += msum[k][0][lane];
+      N += msum[k][1][lane];
     }
-    const double m = sum / n;
+    const double m = S / N;
     mean2 = m * m;
   }
-  constexpr int LG = 8;
   for (int l0 = 0; l0 < a.n_lags; l0 += LG) {
     int64_t L[LG];
     double sum[LG], n[LG];
@@ -371,25 +389,41 @@ __global__ void __launch_bounds__(kNT) k_allan_cols(AllanArgs a) {
       L[l] = l0 + l < a.n_lags ? a.lags[l0 + l] : 0;  // 0: not a lag of this group
       sum[l] = n[l] = 0.0;
     }
-    for (int64_t t = 0; t < P; ++t) {
-      const double xt = (double)x[t * st];
+    if (valid)
+      for (int64_t t = t0; t < t1; ++t) {
+        const double xt = (double)x[t * st];
 #pragma unroll
-      for (int l = 0; l < LG; ++l) {
-        if (L[l] >= 1 && t >= L[l] && t < P - L[l]) {  // the same for every lane
-          const double d = (double)x[(t + L[l]) * st] - 2.0 * xt + (double)x[(t - L[l]) * st];
-          if (finite(d)) {
-            sum[l] += d * d;
-            n[l] += 1.0;
+        for (int l = 0; l < LG; ++l) {
+          if (L[l] >= 1 && t >= L[l] && t < P - L[l]) {  // the same for every lane
+            const double d = (double)x[(t + L[l]) * st] - 2.0 * xt + (double)x[(t - L[l]) * st];
+            if (isfinite(d)) {
+              sum[l] += d * d;
+              n[l] += 1.0;
+            }
           }
         }
       }
-    }
 #pragma unroll
     for (int l = 0; l < LG; ++l) {
-      if (l0 + l >= a.n_lags) break;
-      const double tau = (double)L[l] * a.spacing;
-      a.out[s * a.n_lags + l0 + l] = n[l] > 0.0 && L[l] >= 1 && 2 * L[l] < P ? sum[l] / n[l] / (2.0 * tau * tau) / mean2 : NAN;
+      red[slice][l][0][lane] = sum[l];
+      red[slice][l][1][lane] = n[l];
     }
+    __syncthreads();
+    if (slice == 0 && valid) {
+#pragma unroll
+      for (int l = 0; l < LG; ++l) {
+        if (l0 + l >= a.n_lags) break;
+        double S = 0.0, N = 0.0;
+#pragma unroll
+        for (int k = 0; k < kColsSlices; ++k) {
+          S += red[k][l][0][lane];
+          N += red[k][l][1][lane];
+        }
+        const double tau = (double)L[l] * a.spacing;
+        a.out[s * a.n_lags + l0 + l] = N > 0.0 && L[l] >= 1 && 2 * L[l] < P ? S / N / (2.0 * tau * tau) / mean2 : NAN;
+      }
+    }
+    __syncthreads();  // the next lag group reuses red
   }
 }
 
@@ -439,7 +473,8 @@ int64_t allan_part_doubles(int64_t n_points, int64_t n_series, int64_t point_str
 
 hipError_t launch_allan(const AllanArgs& a, hipStream_t s) {
   if (allan_cols(a.n_series, a.point_stride, a.series_stride)) {
-    hipLaunchKernelGGL(k_allan_cols, dim3((unsigned)((a.n_series + kNT - 1) / kNT)), dim3(kNT), 0, s, a);
+    hipLaunchKernelGGL(k_allan_cols, dim3((unsigned)((a.n_series + kColsSeries - 1) / kColsSeries)),
+                       dim3(kColsSeries * kColsSlices), 0, s, a);
   } else {
     const int64_t chunks = a.n_points > 0 ? (a.n_points + kAllanChunk - 1) / kAllanChunk : 1;
     hipLaunchKernelGGL(k_allan_part, dim3((unsigned)a.n_series, (unsigned)chunks), dim3(kNT), 0, s, a, chunks);

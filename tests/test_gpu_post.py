@@ -8,6 +8,8 @@ differences); FP64 outputs (moments, Allan variances) within 1e-10 relative.
 """
 import sys
 
+import warnings
+
 import numpy as np
 import pytest
 
@@ -157,6 +159,31 @@ def test_time_allan_variance_across_channels(env):
     ref = post.allan(x.T, lags, spacing=1.0, normalize=True)
     rel_close(got, ref, 1e-10)
     assert np.all(np.isnan(got[:, -1]))  # 2 L >= n_points
+
+
+def test_time_allan_variance_ragged_with_flags(env):
+    """TAV of side-by-side series: a channel count that is not a whole number of 64-series workgroups, a
+    series length that does not split evenly over the time slices, NaN (flagged) samples, both with and
+    without normalisation; run twice, bitwise equal."""
+    torch, pk, dev = env
+    T, C = 1001, 1000
+    rng = np.random.default_rng(9)
+    x = (2 + 0.02 * rng.standard_normal((T, C))).astype(np.float32)
+    x[rng.integers(0, T, 300), rng.integers(0, C, 300)] = np.nan
+    x[:, 7] = np.nan  # a channel with no finite sample
+    lags = [1, 3, 5, 17, 100, 250, 333, 499, 500, 501]
+    xd = torch.from_numpy(x).to(dev)
+    for normalize in (False, True):
+        got = pk.allan(xd, lags, spacing=2.0, normalize=normalize, axis=0).cpu().numpy()
+        again = pk.allan(xd, lags, spacing=2.0, normalize=normalize, axis=0).cpu().numpy()
+        with warnings.catch_warnings():  # the mean of the all-NaN channel is NaN by design
+            warnings.simplefilter("ignore", RuntimeWarning)
+            ref = post.allan(x.T, lags, spacing=2.0, normalize=normalize)
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        ok = ~np.isnan(ref)
+        rel_close(got[ok], ref[ok], 1e-10)
+        assert np.array_equal(np.nan_to_num(got), np.nan_to_num(again))
+        assert np.all(np.isnan(got[7])) and np.all(np.isnan(got[:, -1]))
 
 
 def test_spectral_allan_variance(env):
