@@ -119,6 +119,7 @@ struct ps_plan_s {
   hipStream_t stream = nullptr;
   bool bound = false;
   int n_cu = 256;  // compute units of the bound device
+  size_t off_T = 0, t_bytes = 0;  // the inter-pass buffer shared by every instance
   // per-kernel timing (measurement only)
   bool prof = false;
   std::vector<hipEvent_t> ev;       // pairs (start, stop)
@@ -620,11 +621,17 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
         L1 lc{0, key[0], key[2], key[3], key[4], cols.size(), e - m, 0};
         L1 lr{1, key[1], 0, 0, key[5], rows.size(), e - m, 0};
         int ct = 0, rt = 0;
+        size_t t_off = 0;  // the sub-batch's members take consecutive regions of the shared inter-pass buffer
         for (size_t q = m; q < e; ++q) {
-          cols.push_back(c.second[q].ca);
-          ct += col_tiles(c.second[q].ca);
+          ps::ColArgs ca = c.second[q].ca;
+          ps::RowArgs ra = c.second[q].ra;
+          ca.T = reinterpret_cast<float2*>(plan->ws + plan->off_T + t_off);
+          ra.T = ca.T;
+          t_off += (size_t)c.second[q].t_bytes;
+          if (t_off > plan->t_bytes) return fail(PS_ERR_STATE, "grouped sub-batch exceeds the inter-pass buffer");
+          cols.push_back(ca);
+          ct += col_tiles(ca);
           cend.push_back(ct);
-          const ps::RowArgs& ra = c.second[q].ra;
           rows.push_back(ra);
           rt += ra.N1 / 2 / ps::rowpass_units_per_tile(key[1]) * ra.P * ra.G;
           rend.push_back(rt);
@@ -853,7 +860,7 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
   }
   ps_plan_s* plan = new (std::nothrow) ps_plan_s;
   if (!plan) return fail(PS_ERR_ARG, "out of host memory");
-  size_t off = 0;
+  size_t off = 0, t_pool = 0;
   plan->inst.resize((size_t)n_inst);
   for (int i = 0; i < n_inst; ++i) {
     Inst& I = plan->inst[(size_t)i];
@@ -899,7 +906,7 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
     I.off_hist = off; off = align_up(off + (size_t)I.cfg.n_pairs * 2 * (size_t)I.hist_bins() * 8);
     I.off_tw_full = off; off = align_up(off + I.tw_full.size() * 4);
     I.off_stage = off; off = align_up(off + 2 * I.tail_bytes());
-    I.off_T = off; off = align_up(off + (size_t)I.chunk * (size_t)I.cfg.n_pairs * (size_t)I.N * 8);
+    t_pool = std::max(t_pool, (size_t)I.chunk * (size_t)I.cfg.n_pairs * (size_t)I.N * 8);
     I.off_acc = off; off = align_up(off + I.acc_bytes());
     if (I.G > ps::kDirectSlots) {
       I.off_sumacc = off; off = align_up(off + I.slot_doubles() * 8);
@@ -915,6 +922,14 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
     }
     I.end = off;
   }
+  // One inter-pass buffer for the whole plan: the passes of its instances run one after another on the
+  // plan's stream, and a grouped sub-batch holds at most kBatchT bytes of inter-pass data (or a single
+  // instance's chunk), so the largest chunk or kBatchT suffices (64 instances: 0.5 GB instead of 10 GB).
+  if (n_inst > 1) t_pool = std::max(t_pool, (size_t)kBatchT);
+  plan->off_T = off;
+  plan->t_bytes = t_pool;
+  off = align_up(off + t_pool);
+  for (Inst& I : plan->inst) I.off_T = plan->off_T;
   // descriptors of the grouped launches: up to kMaxRounds chunks per call, one task per instance and pass
   {
     const size_t n = (size_t)n_inst;
