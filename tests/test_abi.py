@@ -255,3 +255,18 @@ def test_learnable_window_needs_short_passes():
         assert (st == 0) == ok, (sched, pk.lib().ps_last_error())
         if h.value:
             pk.lib().ps_destroy(h)
+
+
+def test_instances_share_one_inter_pass_buffer():
+    """The inter-pass buffer is one region for the whole plan: the largest instance's chunk, and at least the
+    128 MiB of a grouped sub-batch when the plan has several instances (host-side sizing, no GPU)."""
+    paper = pk.Instance(fft_len=1 << 18, bits=8)
+    one = pk.plan_workspace_bytes([paper])
+    t18 = 64 * (1 << 18) * 8  # default chunk of 64 frames of 2^18 points, one pair: 128 MiB
+    assert one >= t18
+    many = pk.plan_workspace_bytes([paper] * 64)
+    per_inst = one - t18  # everything an instance owns besides the shared buffer (tables, accumulators, ...)
+    assert many < t18 + 64 * (per_inst + (1 << 20))  # one buffer, not 64 (which would be > 8 GiB)
+    mixed = pk.plan_workspace_bytes([paper, pk.Instance(fft_len=1 << 20, bits=2), pk.Instance(fft_len=1 << 12)])
+    t20 = 64 * (1 << 20) * 8  # 512 MiB: the largest chunk sets the buffer
+    assert t20 <= mixed < t20 + 3 * (per_inst + (64 << 20))
