@@ -262,7 +262,7 @@ def test_instances_share_one_inter_pass_buffer():
     128 MiB of a grouped sub-batch when the plan has several instances (host-side sizing, no GPU)."""
     paper = pk.Instance(fft_len=1 << 18, bits=8)
     one = pk.plan_workspace_bytes([paper])
-    t18 = 64 * (1 << 18) * 8  # default chunk of 64 frames of 2^18 points, one pair: 128 MiB
+    t18 = 128 * (1 << 18) * 8  # default chunk of 2^25 points (128 frames of 2^18), one pair: 256 MiB
     assert one >= t18
     many = pk.plan_workspace_bytes([paper] * 64)
     per_inst = one - t18  # everything an instance owns besides the shared buffer (tables, accumulators, ...)
