@@ -78,7 +78,9 @@ typedef struct ps_plan_s* ps_plan_t;
  *   accum       PS_ACC_FP64 (any precision), or PS_ACC_KAHAN32 (16-bit passes only): the products of
  *               the frames of one pass launch are summed per channel in registers, in FP64 or in
  *               compensated FP32, then added to FP64 accumulators.
- *   chunk_frames  frames processed per internal pass pair (0 = max(64, 2^25 / N)); bounds the workspace.
+ *   chunk_frames  frames processed per internal pass pair (0 = max(64, 2^25 / N)); bounds the workspace:
+ *                 a plan keeps one inter-pass buffer of the largest chunk_frames x n_pairs x N x 8 bytes
+ *                 of its instances (at least 128 MiB with several instances), shared by all of them.
  *   sample_rate_hz  metadata only (channel width = sample_rate_hz / N).
  *   hop         segmentation (Sec. 3.1, 50 % overlap): frame f of the stream starts at sample f * hop;
  *               0 or N = contiguous frames, N/2 = 50 % overlap, N/4 or N/8 = 75 or 87.5 %.  An integration
