@@ -116,11 +116,12 @@ def test_fft_lengths_float_input(pk, torch_dev, logn):
     assert np.all(e < TOL), e
 
 
-@pytest.mark.parametrize("logn,F", [(13, 300), (14, 150), (15, 80), (16, 48), (17, 40)])
+@pytest.mark.parametrize("logn,F", [(13, 300), (14, 150), (15, 80), (16, 48), (17, 40), (19, 40), (20, 32)])
 def test_default_schedules_many_frames(pk, torch_dev, logn, F):
     """2-bit pair, Hann window, the default schedules of 2^13 .. 2^17 points (longer column pass first,
-    several column-pass workgroups per CU, row-pass slots aimed at 512 workgroups) over enough frames that
-    every frame group and slot is used; one call against the oracle, three calls bitwise equal to one."""
+    several column-pass workgroups per CU, row-pass slots aimed at 512 workgroups), of 2^19 (1024 x 512,
+    4-frame row batches) and 2^20 (512 x 2048) over enough frames that every frame group and slot is used;
+    one call against the oracle, three calls bitwise equal to one."""
     torch, dev = torch_dev
     N = 1 << logn
     say(f"default schedule 2^{logn}, {F} frames")
