@@ -1,4 +1,4 @@
-"""Batching form on the GPU: grouped persistent launches over many uneven instances, and hipGraph replay.
+"""Batching form on the GPU: grouped launches over many uneven instances, and hipGraph replay.
 
 Parity: the grouped launches run the same per-tile code as single-instance plans, and the row pass adds the
 frames of each instance in order, so the spectra of a many-instance plan equal those of one plan per
@@ -68,6 +68,29 @@ def test_grouped_equals_separate(env, chunk):
     b = run(env, insts, chunk, separate=True)
     for i, (x, y) in enumerate(zip(a, b)):
         assert np.array_equal(x, y), f"instance {i}"
+
+
+def test_grouped_sub_batches_share_the_inter_pass_buffer(env):
+    """One member whose inter-pass data alone exceeds a 128 MiB grouped sub-batch (2^16 points x 300
+    frames = 157 MiB), three of one shape class that share a sub-batch (2^14 x 100 frames, 13 MiB each),
+    and a 2^18 instance: every sub-batch takes consecutive regions of the plan's one inter-pass buffer;
+    spectra bitwise equal to separate plans, and to a second integration of the same plan."""
+    torch, pk, dev = env
+    insts = [synth.make_correlated_noise(2, 0.3, 1 << 16, 300, seed_extra=900),
+             synth.make_correlated_noise(8, 0.2, 1 << 14, 100, seed_extra=901),
+             synth.make_correlated_noise(8, 0.4, 1 << 14, 100, seed_extra=902),
+             synth.make_correlated_noise(8, 0.1, 1 << 14, 100, seed_extra=903),
+             synth.make_correlated_noise(4, 0.3, 1 << 18, 12, seed_extra=904)]
+    say("grouped sub-batches in the shared inter-pass buffer")
+    a = run(env, insts)
+    b = run(env, insts, separate=True)
+    for i, (x, y) in enumerate(zip(a, b)):
+        assert np.array_equal(x, y), f"instance {i}"
+    c = run(env, insts)
+    for i, (x, y) in enumerate(zip(a, c)):
+        assert np.array_equal(x, y), f"instance {i} (second plan)"
+    acc, nf, _, _ = oracle.run_instance(insts[1])
+    assert np.max(np.abs(a[1] - acc) / np.mean(acc[:, 0:1, :], axis=2, keepdims=True)) < 1e-5
 
 
 def test_grouped_against_oracle(env):
