@@ -42,6 +42,12 @@ def parse():
     ap.add_argument("--no-batching", action="store_true", help="skip the 64-instance batching section")
     ap.add_argument("--ring", type=int, default=24, help="distinct input buffers cycled through by the steps")
     ap.add_argument("--no-graph", action="store_true", help="time the headline with eager launches only")
+    ap.add_argument("--depth", type=int, default=2,
+                    help="integrations in flight: plans, each on its own stream, taking integrations in turn")
+    ap.add_argument("--warmup-ms", type=float, default=150.0,
+                    help="sustained untimed integrations before the timed region (after the W warm-up steps)")
+    ap.add_argument("--separate", action="store_true",
+                    help="headline as ps_accumulate then ps_stokes (default: the one-call ps_accumulate_stokes)")
     ap.add_argument("--main-only", action="store_true",
                     help="only the headline workload (for profiler runs): no other sections, no CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time (whole integrations)")
@@ -571,13 +577,22 @@ def main():
     samples = F * N * S
     packed = torch.from_numpy(inst["packed"]).to(dev)
     # streaming: each step integrates a different, HBM-resident second of data (a ring of copies larger
-    # than the 256 MB last-level cache) into its own output, so no step finds its input in cache
-    side = torch.cuda.Stream(dev)
+    # than the 256 MB last-level cache) into its own output, so no step finds its input in cache.  `depth`
+    # integrations are in flight: integration i runs on plan i mod depth, each plan with its own workspace
+    # (inter-pass buffer and accumulators) on its own stream, so one integration's column pass overlaps the
+    # previous one's row pass and Stokes output.
+    depth = max(1, args.depth)
+    streams = [torch.cuda.Stream(dev) for _ in range(depth)]
+    side = streams[0]
     with torch.cuda.stream(side):
         ring = [packed.clone() for _ in range(max(1, args.ring))]
         outs = [torch.empty((1, 4, N // 2), dtype=torch.float32, device=dev) for _ in ring]
-        plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev, stream=side)
-    side.synchronize()
+    plans = []
+    for st in streams:
+        with torch.cuda.stream(st):
+            plans.append(pk.Plan([pk.Instance.from_synth(inst)], device=dev, stream=st))
+    torch.cuda.synchronize(dev)
+    plan = plans[0]
     if args.only == "overlap_form":
         print(json.dumps({"overlap_form": overlap_form(pk, torch, dev, inst, ring, args.steps)}), flush=True)
         return
@@ -585,48 +600,67 @@ def main():
 
     def step_on(pl, i):
         pl.reset()
-        pl.accumulate(ring[i % len(ring)])
-        pl.stokes(psi=0.25, out=outs[i % len(ring)])
+        if args.separate:
+            pl.accumulate(ring[i % len(ring)])
+            pl.stokes(psi=0.25, out=outs[i % len(ring)])
+        else:
+            pl.accumulate_stokes(ring[i % len(ring)], psi=0.25, out=outs[i % len(ring)])
 
     def step():
         i = pos["i"]
         pos["i"] += 1
-        step_on(plan, i)
+        with torch.cuda.stream(side):
+            step_on(plan, i)
 
-    with torch.cuda.stream(side):
-        for _ in range(args.warmup):
-            step()
+    def run_eager(n, d):
+        """n integrations, integration i on plan i mod d (its own stream)"""
+        for i in range(n):
+            with torch.cuda.stream(streams[i % d]):
+                step_on(plans[i % d], i)
+
+    def timed(fn, n):
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
+        fn()
         torch.cuda.synchronize(dev)
-        dt_eager = (time.perf_counter() - t0) / args.steps
-    dt = dt_eager
-    graph = None
+        return (time.perf_counter() - t0) / n
+
+    # warm-up: W integrations, then at least --warmup-ms of the same work (clocks, TLBs and caches reach their
+    # steady state only after some tens of milliseconds of sustained integrations)
+    run_eager(args.warmup, depth)
+    torch.cuda.synchronize(dev)
+    t_end = time.perf_counter() + args.warmup_ms / 1e3
+    while time.perf_counter() < t_end:
+        run_eager(len(ring), depth)
+        torch.cuda.synchronize(dev)
+    dt_eager = timed(lambda: run_eager(args.steps, depth), args.steps)
+    dt_eager_single = timed(lambda: run_eager(args.steps, 1), args.steps)
+    dt, dt_graph_single, graph = dt_eager, None, None
     if not args.no_graph:
-        # the streaming loop as replayed hipGraphs, exactly K integrations: graph A integrates n_a = min(K, ring)
-        # consecutive ring buffers and is replayed K // n_a times; graph B (a second plan) the remaining K % n_a
-        n_a = min(args.steps, len(ring))
-        reps, rem = divmod(args.steps, n_a)
-        plan.graph_capture(lambda: [step_on(plan, i) for i in range(n_a)])
-        plan_b = None
-        if rem:
-            with torch.cuda.stream(side):
-                plan_b = pk.Plan([pk.Instance.from_synth(inst)], device=dev, stream=side)
-            plan_b.graph_capture(lambda: [step_on(plan_b, n_a + i) for i in range(rem)])
+        # each plan captures its share of exactly K integrations (i = j, j + depth, ... < K) as one hipGraph;
+        # the timed region launches every plan's graph on its own stream once
+        share = [list(range(j, args.steps, depth)) for j in range(depth)]
+        used = [j for j in range(depth) if share[j]]
+        for j in used:
+            plans[j].graph_capture(lambda j=j: [step_on(plans[j], i) for i in share[j]])
+
+        def replay_all():
+            for j in used:
+                with torch.cuda.stream(streams[j]):
+                    plans[j].graph_replay()
+        t_end = time.perf_counter() + args.warmup_ms / 2e3
+        while True:
+            replay_all()
+            torch.cuda.synchronize(dev)
+            if time.perf_counter() >= t_end:
+                break
+        dt = timed(replay_all, args.steps)
+        graph = {"depth": depth, "integrations_per_graph": [len(share[j]) for j in used]}
+        # reference: all K integrations on one plan and stream, one graph
+        plan.graph_capture(lambda: [step_on(plan, i) for i in range(args.steps)])
         with torch.cuda.stream(side):
-            for _ in range(max(1, args.warmup // n_a)):
-                plan.graph_replay()
-            torch.cuda.synchronize(dev)
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                plan.graph_replay()
-            if plan_b is not None:
-                plan_b.graph_replay()
-            torch.cuda.synchronize(dev)
-            dt = (time.perf_counter() - t0) / args.steps
-        graph = {"integrations_per_replay": n_a, "replays": reps, "remainder_graph_integrations": rem}
+            plan.graph_replay()
+            dt_graph_single = timed(plan.graph_replay, args.steps)
 
     # per-kernel durations, hipEvents around each launch on the plan's stream (eager steps)
     plan.profile_enable(True)
@@ -662,16 +696,23 @@ def main():
         "config": {"workload": "paper-shaped integration: 2 int8 streams at 16 Msps, 2^18-pt rect frames, "
                                "61 frames (0.999424 s), FP32 passes + FP64 accumulation, Stokes; each step a "
                                f"different HBM-resident second of data (ring of {len(ring)}), "
-                               + ("eager launches" if graph is None else
-                                  f"timed as replayed hipGraphs ({graph['replays']} x {graph['integrations_per_replay']}"
-                                  f" + {graph['remainder_graph_integrations']} integrations)"),
+                               + (f"{depth} integrations in flight (integration i on plan i mod {depth}, each "
+                                  "plan with its own workspace and HIP stream), "
+                                  + ("eager launches" if graph is None else
+                                     "each plan's share of the K integrations replayed as one hipGraph")),
                    "n_streams": S, "bits": 8, "fft_len": N, "frames": F, "samples_per_step": samples},
         "x_realtime": (F * N / SAMPLE_RATE) / dt,
         "fft_tflops_nominal_5NlogN": nominal_flop / dt / 1e12,
+        "fft_frac_fp32_peak_nominal": nominal_flop / dt / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+        "fft_tflops_real_2.5NlogN": nominal_flop / 2 / dt / 1e12,
+        "fft_frac_fp32_peak_real": nominal_flop / 2 / dt / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
         "path_alg_bytes_per_step": path_bytes,
         "path_GBps": path_bytes / dt / 1e9,
         "path_frac_hbm": path_bytes / dt / 1e9 / HBM_PEAK_GBS,
         "ms_per_step_eager": dt_eager * 1e3,
+        "ms_per_step_single_stream_graph": None if dt_graph_single is None else dt_graph_single * 1e3,
+        "ms_per_step_single_stream_eager": dt_eager_single * 1e3,
+        "pipeline": graph,
         "ms_per_step_with_kernel_events": dt_prof * 1e3,
         "kernels": kernels,
         "roofline": roofline,

@@ -17,8 +17,9 @@
  *     library never allocates or frees device memory; a plan owns host metadata only.
  *   - All device work is enqueued asynchronously on the stream given to ps_bind; no call synchronises
  *     except ps_bind itself and the descriptor upload described next.  ps_reset, ps_accumulate,
- *     ps_spectra, ps_stokes, ps_stokes_all, ps_set_window_taps and ps_calibrate_backward enqueue kernels
- *     only (no allocation or memset), so they can be captured into a hipGraph (ps_graph_begin).
+ *     ps_accumulate_stokes, ps_spectra, ps_stokes, ps_stokes_all, ps_set_window_taps and
+ *     ps_calibrate_backward enqueue kernels only (no allocation or memset), so they can be captured into a
+ *     hipGraph (ps_graph_begin).
  *   - Plans of several instances run each pass as grouped launches (the batching form), whose
  *     per-instance launch descriptors live in the workspace.  ps_accumulate and ps_stokes_all upload them
  *     (waiting for the stream, then one copy from pinned host memory) only when they differ from the
@@ -200,6 +201,17 @@ ps_status ps_reset(ps_plan_t plan);
  * one workgroup per tile of all of them, in sub-batches of at most 128 MB of inter-pass data, each row
  * pass right after its column pass (up to 8 chunk rounds per call; beyond that instance by instance). */
 ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples);
+
+/* ps_accumulate followed by the Stokes spectra of the integration so far (Sec. 2 functions 2-4, then Eq. 2 of
+ * Sec. 2.1), for a streaming loop that outputs every integration: cal is NULL or n_inst calibrations,
+ * iquv_dev NULL or n_inst device pointers ([n_pairs][4][C] floats each; NULL entries skip an instance).  The
+ * results are those of ps_accumulate, then ps_stokes_all.  An instance with one accumulator slot and FP32
+ * four-step passes gets its Stokes spectra from the last row pass of the call (the final sums are still in
+ * registers there; no separate output launch, no re-read of the accumulators), the others from one output
+ * launch after the accumulation (grouped when there are several).  PS_ERR_STATE, before anything is enqueued, when a selected
+ * instance would have no frame. */
+ps_status ps_accumulate_stokes(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples,
+                               const ps_cal* cal, float* const* iquv_dev);
 
 /* Raw accumulated products of instance inst into out_dev [n_pairs][4][C] doubles:
  * sum over frames of XX*, YY*, Re XY*, Im XY* (unnormalised), and the frame count (host).

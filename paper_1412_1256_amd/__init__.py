@@ -113,6 +113,7 @@ def lib():
             "ps_profile_enable": [vp, i32],
             "ps_profile_read": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
             "ps_stokes_all": [vp, C.POINTER(_Cal), C.POINTER(vp)],
+            "ps_accumulate_stokes": [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(_Cal), C.POINTER(vp)],
             "ps_plan_scheduled": [C.POINTER(_Instance), C.POINTER(_Schedule), i32, C.POINTER(vp), C.POINTER(sz)],
             "ps_schedule_candidates": [C.POINTER(_Instance), C.POINTER(_Schedule), i32, C.POINTER(i32)],
             "ps_set_histograms": [vp, i32, i32],
@@ -265,6 +266,43 @@ class Plan:
                 n_samples.append(0 if p is None else p.numel() * 8 // bits_per_t)
         ns = (C.c_int64 * n)(*n_samples)
         _check(lib().ps_accumulate(self._h, ptrs, ns))
+
+    def accumulate_stokes(self, packed, n_samples=None, outs=None, cals=None, gain_x=None, gain_y=None,
+                          dterms=None, psi: float = 0.0, feed="linear", out=None):
+        """accumulate() and then the Stokes spectra of every instance (ps_accumulate_stokes).  For a
+        one-instance plan the calibration may be given as keywords and the output as out=; otherwise outs
+        and cals as in stokes_all().  Returns the list of output tensors."""
+        torch = self.torch
+        if not isinstance(packed, (list, tuple)):
+            packed = [packed]
+        n = len(self.instances)
+        if len(packed) != n:
+            raise ValueError(f"expected {n} packed buffers, got {len(packed)}")
+        ptrs = (C.c_void_p * n)(*[None if p is None else p.data_ptr() for p in packed])
+        if n_samples is None:
+            n_samples = [0 if p is None else p.numel() * 8 // (inst.n_streams * inst.bits)
+                         for inst, p in zip(self.instances, packed)]
+        ns = (C.c_int64 * n)(*n_samples)
+        if outs is None:
+            outs = [out] if (n == 1 and out is not None) else [
+                torch.empty((I.n_pairs, 4, I.channels), dtype=torch.float32, device=self.device)
+                for I in self.instances]
+        optr = (C.c_void_p * n)(*[None if o is None else o.data_ptr() for o in outs])
+        if cals is None and n == 1:
+            cals = [(gain_x, gain_y, dterms, psi, feed)]
+        arr, keep = None, []
+        if cals is not None:
+            arr = (_Cal * n)()
+            for i, c in enumerate(cals):
+                c = tuple(c) if c is not None else (None, None, None, 0.0)
+                gx, gy, dt, ps_ = c[:4]
+                fd = c[4] if len(c) > 4 else "linear"
+                gx, gy, dt = self._as_f32(gx), self._as_f32(gy), self._as_f32(dt)
+                keep += [gx, gy, dt]
+                arr[i] = self._cal(gx, gy, dt, ps_, fd)
+        self._cal_keepalive = keep
+        _check(lib().ps_accumulate_stokes(self._h, ptrs, ns, arr, optr))
+        return outs
 
     def spectra(self, inst: int = 0, out=None):
         I = self.instances[inst]

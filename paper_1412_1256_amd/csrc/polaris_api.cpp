@@ -108,6 +108,12 @@ struct Inst {
   // readers of more than kDirectSlots slots take their sum from a reduction into one slot
   size_t off_sumacc = 0, off_sumpart = 0;
   bool use_reduced() const { return slots_used() > ps::kDirectSlots; }
+  // accumulate-and-Stokes request of the current call: output, calibration (may be null), and whether the
+  // last row pass wrote the Stokes spectra itself
+  float* fuse_iquv = nullptr;
+  const ps_cal* fuse_cal = nullptr;
+  bool fuse_done = false;
+  bool can_fuse() const { return !fused && !mx() && G == 1; }
 };
 
 }  // namespace
@@ -729,9 +735,39 @@ ps_status accumulate_mx(ps_plan_t plan, Inst& I, const ps::ColArgs& ca) {
   return PS_OK;
 }
 
+// Arguments of the Stokes output of instance I over its first n_frames frames (Eq. 2 with cal, or unit
+// gains, no leakage and psi = 0 when cal is null).
+ps::OutArgs stokes_args(ps_plan_t plan, const Inst& I, int64_t n_frames, const ps_cal* cal, float* iquv) {
+  ps::OutArgs o{};
+  const bool reduced = std::min<int64_t>(I.G, n_frames) > ps::kDirectSlots;
+  o.acc = ws_ptr<double>(plan, reduced ? I.off_sumacc : I.off_acc);
+  o.slots = reduced ? 1 : (int32_t)std::min<int64_t>(I.G, n_frames);
+  o.slot_stride = (int64_t)I.slot_doubles();
+  o.N1 = (int32_t)I.N1;
+  o.N2 = (int32_t)I.N2;
+  o.P = I.cfg.n_pairs;
+  o.C = I.C;
+  o.n_frames = (double)n_frames;
+  o.sumw2_dev = ws_ptr<double>(plan, I.off_sumw2);
+  o.scale = 1.0 / ((double)n_frames * I.sumw2);
+  const double psi = cal ? cal->psi : 0.0;
+  o.cos2psi = std::cos(2.0 * psi);
+  o.sin2psi = std::sin(2.0 * psi);
+  o.circular = (cal && cal->feed == PS_FEED_CIRCULAR) ? 1 : 0;
+  if (cal) {
+    o.gain_x = cal->gain_x;
+    o.gain_y = cal->gain_y;
+    o.dterms = cal->dterms;
+  }
+  o.iquv = iquv;
+  return o;
+}
+
 // Frames 0 .. F-1 of the buffer at base (frame f at sample f * hop) in chunks of the instance's chunk size:
-// the column and row passes (or their 16-bit forms) of each chunk, frames in order.
-ps_status run_frames(ps_plan_t plan, Inst& I, const uint8_t* base, int64_t F) {
+// the column and row passes (or their 16-bit forms) of each chunk, frames in order.  With fuse and a
+// pending accumulate-and-Stokes request that the instance can take (one accumulator slot, FP32 four-step
+// passes), the last chunk's row pass also writes the Stokes spectra.
+ps_status run_frames(ps_plan_t plan, Inst& I, const uint8_t* base, int64_t F, bool fuse = false) {
   if (I.fused && !I.hist_on) {
     // single pass: no inter-pass buffer, so one launch takes up to 2^28 frames
     constexpr int64_t kMaxFused = int64_t(1) << 28;
@@ -778,8 +814,14 @@ ps_status run_frames(ps_plan_t plan, Inst& I, const uint8_t* base, int64_t F) {
                          [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cols, I.cfg.bits, mode, ca, l); });
     if (e != hipSuccess) return hip_fail(e, "column pass launch");
     const ps::RowArgs ra = row_args(plan, I, nf, I.n_frames);
-    e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& l) { return ps::launch_rowpass((int)I.N2, I.fb, ra, l); });
+    const bool fuse_now = fuse && I.fuse_iquv && I.can_fuse() && f0 + nf == F;
+    ps::OutArgs o{};
+    if (fuse_now) o = stokes_args(plan, I, I.n_frames + nf, I.fuse_cal, I.fuse_iquv);
+    e = timed(plan, PS_KERNEL_ROWPASS, [&](const ps::Launch& l) {
+      return ps::launch_rowpass((int)I.N2, I.fb, ra, l, fuse_now ? &o : nullptr);
+    });
     if (e != hipSuccess) return hip_fail(e, "row pass launch");
+    if (fuse_now) I.fuse_done = true;
     I.first = false;
     I.n_frames += nf;
   }
@@ -1028,7 +1070,7 @@ ps_status ps_reset(ps_plan_t plan) {
   return PS_OK;
 }
 
-ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples) {
+static ps_status check_accumulate(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples) {
   ps_status st = check_plan(plan, true);
   if (st != PS_OK) return st;
   if (!packed_dev || !n_samples) return fail(PS_ERR_ARG, "null packed or n_samples array");
@@ -1041,6 +1083,17 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
     if (n_samples[i] > 0 && !packed_dev[i]) return fail(PS_ERR_ARG, "instance %zu: null packed buffer", i);
     if (n_samples[i] / I.N > (int64_t(1) << 40)) return fail(PS_ERR_SIZE, "instance %zu: too many frames", i);
   }
+  return PS_OK;
+}
+
+// Frames of instance I in the integration once a call of T samples has been added.
+static int64_t frames_after(const Inst& I, int64_t T) {
+  if (T == 0) return I.n_frames;
+  return I.n_frames + I.frames_in(T) + (I.overlap() && I.n_frames > 0 ? (I.N - I.hop) / I.hop : 0);
+}
+
+static ps_status accumulate_impl(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples) {
+  ps_status st = PS_OK;
   // First, per instance: the histogram clear and, with overlapped frames, the frames that span the
   // previous call and this one (they precede this call's own frames in the integration).
   for (size_t i = 0; i < plan->inst.size(); ++i) {
@@ -1069,10 +1122,57 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
   for (size_t i = 0; i < plan->inst.size(); ++i) {
     if (done[i]) continue;
     Inst& I = plan->inst[i];
-    st = run_frames(plan, I, static_cast<const uint8_t*>(packed_dev[i]), I.frames_in(n_samples[i]));
+    st = run_frames(plan, I, static_cast<const uint8_t*>(packed_dev[i]), I.frames_in(n_samples[i]), true);
     if (st != PS_OK) return st;
   }
   return PS_OK;
+}
+
+ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples) {
+  ps_status st = check_accumulate(plan, packed_dev, n_samples);
+  if (st != PS_OK) return st;
+  return accumulate_impl(plan, packed_dev, n_samples);
+}
+
+ps_status ps_accumulate_stokes(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples,
+                               const ps_cal* cal, float* const* iquv_dev) {
+  ps_status st = check_accumulate(plan, packed_dev, n_samples);
+  if (st != PS_OK) return st;
+  const size_t n = plan->inst.size();
+  if (iquv_dev) {
+    for (size_t i = 0; i < n; ++i) {
+      if (!iquv_dev[i]) continue;
+      if (cal && cal[i].feed != PS_FEED_LINEAR && cal[i].feed != PS_FEED_CIRCULAR)
+        return fail(PS_ERR_ARG, "instance %zu: unknown feed %d", i, cal[i].feed);
+      if (frames_after(plan->inst[i], n_samples[i]) == 0)
+        return fail(PS_ERR_STATE, "instance %zu would have no accumulated frames", i);
+    }
+  }
+  for (size_t i = 0; i < n; ++i) {
+    Inst& I = plan->inst[i];
+    I.fuse_iquv = iquv_dev ? iquv_dev[i] : nullptr;
+    I.fuse_cal = cal ? &cal[i] : nullptr;
+    I.fuse_done = false;
+  }
+  st = accumulate_impl(plan, packed_dev, n_samples);
+  std::vector<float*> rest(n, nullptr);
+  int n_rest = 0, last = -1;
+  for (size_t i = 0; i < n; ++i) {
+    Inst& I = plan->inst[i];
+    if (I.fuse_iquv && !I.fuse_done) {
+      rest[i] = I.fuse_iquv;
+      ++n_rest;
+      last = (int)i;
+    }
+    I.fuse_iquv = nullptr;
+    I.fuse_cal = nullptr;
+  }
+  if (st != PS_OK || n_rest == 0) return st;
+  // instances whose Stokes did not come out of their last row pass: one output launch (its arguments passed
+  // directly when there is one instance, so that a loop over changing outputs can be captured), else one
+  // grouped launch
+  if (n_rest == 1) return ps_stokes(plan, last, cal ? &cal[last] : nullptr, rest[(size_t)last]);
+  return ps_stokes_all(plan, cal, rest.data());
 }
 
 // Sum the slots of an instance that uses many of them into one (readers then see a single slot).
@@ -1125,20 +1225,7 @@ ps_status ps_stokes(ps_plan_t plan, int32_t inst, const ps_cal* cal, float* iquv
   if (cal && cal->feed != PS_FEED_LINEAR && cal->feed != PS_FEED_CIRCULAR)
     return fail(PS_ERR_ARG, "unknown feed %d", cal->feed);
   if ((st = reduce_slots(plan, I)) != PS_OK) return st;
-  ps::OutArgs o = out_args(plan, I);
-  o.n_frames = (double)I.n_frames;
-  o.sumw2_dev = ws_ptr<double>(plan, I.off_sumw2);
-  o.scale = 1.0 / ((double)I.n_frames * I.sumw2);
-  const double psi = cal ? cal->psi : 0.0;
-  o.cos2psi = std::cos(2.0 * psi);
-  o.sin2psi = std::sin(2.0 * psi);
-  o.circular = (cal && cal->feed == PS_FEED_CIRCULAR) ? 1 : 0;
-  if (cal) {
-    o.gain_x = cal->gain_x;
-    o.gain_y = cal->gain_y;
-    o.dterms = cal->dterms;
-  }
-  o.iquv = iquv_dev;
+  const ps::OutArgs o = stokes_args(plan, I, I.n_frames, cal, iquv_dev);
   hipError_t e = timed(plan, PS_KERNEL_STOKES, [&](const ps::Launch& l) { return ps::launch_stokes(o, l); });
   if (e != hipSuccess) return hip_fail(e, "stokes launch");
   return PS_OK;
@@ -1155,22 +1242,9 @@ ps_status ps_stokes_all(ps_plan_t plan, const ps_cal* cal, float* const* iquv_de
     if (!iquv_dev[i]) continue;
     const Inst& I = plan->inst[i];
     if (I.n_frames == 0) return fail(PS_ERR_STATE, "instance %zu has no accumulated frames", i);
-    ps::OutArgs o = out_args(plan, I);
-    o.n_frames = (double)I.n_frames;
-    o.sumw2_dev = ws_ptr<double>(plan, I.off_sumw2);
-    o.scale = 1.0 / ((double)I.n_frames * I.sumw2);
-    const double psi = cal ? cal[i].psi : 0.0;
-    o.cos2psi = std::cos(2.0 * psi);
-    o.sin2psi = std::sin(2.0 * psi);
     if (cal && cal[i].feed != PS_FEED_LINEAR && cal[i].feed != PS_FEED_CIRCULAR)
       return fail(PS_ERR_ARG, "instance %zu: unknown feed %d", i, cal[i].feed);
-    o.circular = (cal && cal[i].feed == PS_FEED_CIRCULAR) ? 1 : 0;
-    if (cal) {
-      o.gain_x = cal[i].gain_x;
-      o.gain_y = cal[i].gain_y;
-      o.dterms = cal[i].dterms;
-    }
-    o.iquv = iquv_dev[i];
+    const ps::OutArgs o = stokes_args(plan, I, I.n_frames, cal ? &cal[i] : nullptr, iquv_dev[i]);
     outs.push_back(o);
     total += ps::output_tiles(o.N1, o.N2, o.P);
     ends.push_back(total);

@@ -188,7 +188,8 @@ hipError_t launch_colpass_mx(int N1, int prec, int bits, const MxColArgs& a, int
 hipError_t launch_rowpass_mx(int N2, int prec, int accum, const MxRowArgs& a, const Launch& l);
 
 hipError_t launch_colpass(int N1, int cols, int bits, int mode, const ColArgs& a, const Launch& l);
-hipError_t launch_rowpass(int N2, int fb, const RowArgs& a, const Launch& l);
+// o != nullptr (one accumulator slot): the row pass also writes the Stokes spectra described by *o
+hipError_t launch_rowpass(int N2, int fb, const RowArgs& a, const Launch& l, const OutArgs* o = nullptr);
 hipError_t launch_stokes(const OutArgs& a, const Launch& l);
 hipError_t launch_spectra(const OutArgs& a, const Launch& l);
 hipError_t launch_unpack(const void* packed, int bits, int S, int64_t n_time, float* out, hipStream_t s);

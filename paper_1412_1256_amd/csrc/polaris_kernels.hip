@@ -229,9 +229,69 @@ __global__ void __launch_bounds__(L * COLS / (8 * V))
   colpass_tile<L, COLS, V, BITS, FAST>(a, tile - (t ? tile_end[t - 1] : 0));
 }
 
+// Calibrated Stokes of channel k of pair p from its accumulated products (the sums of XX*, YY*, XY*):
+// normalised coherency M = A / (F sum w^2), calibration C = (G J)^-1 M (G J)^-H and Eq. 2 (or the circular
+// combination), all in FP64; I, Q, U, V are written to a.iquv [P][4][C] as floats.
+__device__ __forceinline__ void stokes_write(const OutArgs& a, const int p, const int64_t k, const double scale,
+                                             const double axx, const double ayy, const double axr,
+                                             const double axi) {
+  // normalised coherency M = A / (F sum w^2); C = Fi M Fi^H with Fi = (G J)^-1 (C_yx = conj C_xy)
+  const double mxx = axx * scale, myy = ayy * scale;
+  const cd mxy = {axr * scale, axi * scale}, myx = cdc(mxy);
+  double cxx = mxx, cyy = myy;
+  cd cxy = mxy;
+  if (a.gain_x || a.gain_y || a.dterms) {
+    cd gx = {1.0, 0.0}, gy = {1.0, 0.0}, dx = {0.0, 0.0}, dy = {0.0, 0.0};
+    const int64_t gi = 2 * ((int64_t)p * a.C + k);
+    if (a.gain_x) gx = {(double)a.gain_x[gi], (double)a.gain_x[gi + 1]};
+    if (a.gain_y) gy = {(double)a.gain_y[gi], (double)a.gain_y[gi + 1]};
+    if (a.dterms) {
+      dx = {(double)a.dterms[4 * p + 0], (double)a.dterms[4 * p + 1]};
+      dy = {(double)a.dterms[4 * p + 2], (double)a.dterms[4 * p + 3]};
+    }
+    // E = [[gx, gx dx], [gy dy, gy]], det E = gx gy (1 - dx dy), Fi = adj(E) / det E
+    const cd e01 = cdm(gx, dx), e10 = cdm(gy, dy);
+    const cd dxy = cdm(dx, dy);
+    const cd det = cdm(cdm(gx, gy), {1.0 - dxy.x, -dxy.y});
+    const double inv = 1.0 / (det.x * det.x + det.y * det.y);
+    const cd id = {det.x * inv, -det.y * inv};  // 1 / det
+    const cd f00 = cdm(gy, id), f01 = cdm({-e01.x, -e01.y}, id);
+    const cd f10 = cdm({-e10.x, -e10.y}, id), f11 = cdm(gx, id);
+    const cd t00 = cda(cdm(f00, {mxx, 0.0}), cdm(f01, myx)), t01 = cda(cdm(f00, mxy), cdm(f01, {myy, 0.0}));
+    const cd t10 = cda(cdm(f10, {mxx, 0.0}), cdm(f11, myx)), t11 = cda(cdm(f10, mxy), cdm(f11, {myy, 0.0}));
+    cxx = cda(cdm(t00, cdc(f00)), cdm(t01, cdc(f01))).x;
+    cxy = cda(cdm(t00, cdc(f10)), cdm(t01, cdc(f11)));
+    cyy = cda(cdm(t10, cdc(f10)), cdm(t11, cdc(f11))).x;
+  }
+  const double c2 = a.cos2psi, s2 = a.sin2psi;
+  double I, Q, Uq, V;
+  if (a.circular) {
+    // streams R, L: I = (C_rr + C_ll)/2, V = (C_rr - C_ll)/2, Q + iU = C_rl exp(2i psi)
+    I = 0.5 * (cxx + cyy);
+    V = 0.5 * (cxx - cyy);
+    Q = c2 * cxy.x - s2 * cxy.y;
+    Uq = s2 * cxy.x + c2 * cxy.y;
+  } else {
+    // Eq. 2 rows acting on [C_xx, C_xy, C_yx, C_yy] with C_yx = conj C_xy
+    I = 0.5 * (cxx + cyy);
+    Q = 0.5 * (c2 * (cxx - cyy) - s2 * 2.0 * cxy.x);
+    Uq = 0.5 * (s2 * (cxx - cyy) + c2 * 2.0 * cxy.x);
+    V = cxy.y;  // Re(-i C_xy + i C_yx) / 2
+  }
+  float* o = a.iquv + (int64_t)p * 4 * a.C + k;
+  o[0] = (float)I;
+  o[a.C] = (float)Q;
+  o[2 * a.C] = (float)Uq;
+  o[3 * a.C] = (float)V;
+}
+
 // one tile of the row pass: units bx*UB .. bx*UB+UB-1 of pair p, the launch's frames of accumulator slot g
-template <int L, int UB, int FB, int SQ>
-__device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, const int p, const int g) {
+// With STOKES (one accumulator slot, the integration's last launch), the owners of the channel slots also
+// write the calibrated Stokes of their channels from the final sums (exactly what the output kernel
+// computes from the stored accumulators).
+template <int L, int UB, int FB, int SQ, bool STOKES = false>
+__device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, const int p, const int g,
+                                             const OutArgs* o = nullptr) {
   constexpr int NT = UB * FB * L / (4 * SQ);
   constexpr int TPS = L / 8;                       // threads per row sequence
   constexpr int NCH = UB * L < NT ? UB * L : NT;   // threads that own channel slots
@@ -340,12 +400,35 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
       accp[k][2 * L] = sxr[k];
       accp[k][3 * L] = sxi[k];
     }
+    if constexpr (STOKES) {
+      const double scale = o->sumw2_dev ? 1.0 / (o->n_frames * o->sumw2_dev[0]) : o->scale;
+#pragma unroll
+      for (int k = 0; k < SPT; ++k) {
+        // slot s of unit uc holds bin k2 of row uc (half 0) or of its partner row (half 1): channel k2 N1 + row
+        const int id = tid + k * NCH;
+        const int uc = bx * UB + id / L, s = id % L;
+        const int half = s / (L / 2), k2 = s % (L / 2);
+        const int row = half ? (uc == 0 ? a.N1 / 2 : a.N1 - uc) : uc;
+        stokes_write(*o, p, (int64_t)k2 * a.N1 + row, scale, 0.25 * sxx[k], 0.25 * syy[k], 0.25 * sxr[k],
+                     0.25 * sxi[k]);
+      }
+    }
   }
 }
 
 template <int L, int UB, int FB, int SQ>
 __global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
   rowpass_tile<L, UB, FB, SQ>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z);
+}
+
+// The row pass that also writes the Stokes spectra (one slot).  A channel's four outputs are scattered
+// (channel k2 N1 + row), so the units are renumbered to keep runs of consecutive rows on one XCD: the 4-byte
+// writes of neighbouring rows then meet in that XCD's L2 and leave it as whole sectors.
+template <int L, int UB, int FB, int SQ>
+__global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass_stokes(RowArgs a, OutArgs o) {
+  const int nbx = (int)gridDim.x;
+  const int lin = xcd_remap((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
+  rowpass_tile<L, UB, FB, SQ, true>(a, lin % nbx, lin / nbx, 0, &o);
 }
 
 template <int L, int UB, int FB, int SQ>
@@ -420,54 +503,7 @@ __device__ __forceinline__ void output_tile(const OutArgs& a, const int bx, cons
       o[2 * a.C] = axr;
       o[3 * a.C] = axi;
     } else {
-      // normalised coherency M = A / (F sum w^2); C = Fi M Fi^H with Fi = (G J)^-1 (C_yx = conj C_xy)
-      const double mxx = axx * scale, myy = ayy * scale;
-      const cd mxy = {axr * scale, axi * scale}, myx = cdc(mxy);
-      double cxx = mxx, cyy = myy;
-      cd cxy = mxy;
-      if (a.gain_x || a.gain_y || a.dterms) {
-        cd gx = {1.0, 0.0}, gy = {1.0, 0.0}, dx = {0.0, 0.0}, dy = {0.0, 0.0};
-        const int64_t gi = 2 * ((int64_t)p * a.C + k);
-        if (a.gain_x) gx = {(double)a.gain_x[gi], (double)a.gain_x[gi + 1]};
-        if (a.gain_y) gy = {(double)a.gain_y[gi], (double)a.gain_y[gi + 1]};
-        if (a.dterms) {
-          dx = {(double)a.dterms[4 * p + 0], (double)a.dterms[4 * p + 1]};
-          dy = {(double)a.dterms[4 * p + 2], (double)a.dterms[4 * p + 3]};
-        }
-        // E = [[gx, gx dx], [gy dy, gy]], det E = gx gy (1 - dx dy), Fi = adj(E) / det E
-        const cd e01 = cdm(gx, dx), e10 = cdm(gy, dy);
-        const cd dxy = cdm(dx, dy);
-        const cd det = cdm(cdm(gx, gy), {1.0 - dxy.x, -dxy.y});
-        const double inv = 1.0 / (det.x * det.x + det.y * det.y);
-        const cd id = {det.x * inv, -det.y * inv};  // 1 / det
-        const cd f00 = cdm(gy, id), f01 = cdm({-e01.x, -e01.y}, id);
-        const cd f10 = cdm({-e10.x, -e10.y}, id), f11 = cdm(gx, id);
-        const cd t00 = cda(cdm(f00, {mxx, 0.0}), cdm(f01, myx)), t01 = cda(cdm(f00, mxy), cdm(f01, {myy, 0.0}));
-        const cd t10 = cda(cdm(f10, {mxx, 0.0}), cdm(f11, myx)), t11 = cda(cdm(f10, mxy), cdm(f11, {myy, 0.0}));
-        cxx = cda(cdm(t00, cdc(f00)), cdm(t01, cdc(f01))).x;
-        cxy = cda(cdm(t00, cdc(f10)), cdm(t01, cdc(f11)));
-        cyy = cda(cdm(t10, cdc(f10)), cdm(t11, cdc(f11))).x;
-      }
-      const double c2 = a.cos2psi, s2 = a.sin2psi;
-      double I, Q, Uq, V;
-      if (a.circular) {
-        // streams R, L: I = (C_rr + C_ll)/2, V = (C_rr - C_ll)/2, Q + iU = C_rl exp(2i psi)
-        I = 0.5 * (cxx + cyy);
-        V = 0.5 * (cxx - cyy);
-        Q = c2 * cxy.x - s2 * cxy.y;
-        Uq = s2 * cxy.x + c2 * cxy.y;
-      } else {
-        // Eq. 2 rows acting on [C_xx, C_xy, C_yx, C_yy] with C_yx = conj C_xy
-        I = 0.5 * (cxx + cyy);
-        Q = 0.5 * (c2 * (cxx - cyy) - s2 * 2.0 * cxy.x);
-        Uq = 0.5 * (s2 * (cxx - cyy) + c2 * 2.0 * cxy.x);
-        V = cxy.y;  // Re(-i C_xy + i C_yx) / 2
-      }
-      float* o = a.iquv + (int64_t)p * 4 * a.C + k;
-      o[0] = (float)I;
-      o[a.C] = (float)Q;
-      o[2 * a.C] = (float)Uq;
-      o[3 * a.C] = (float)V;
+      stokes_write(a, p, k, scale, axx, ayy, axr, axi);
     }
   }
 }
@@ -631,9 +667,14 @@ hipError_t launch_colpass(int N1, int cols, int bits, int mode, const ColArgs& a
 }
 
 template <int L, int UB, int FB, int SQ>
-static hipError_t rowpass_launch(const RowArgs& a, const Launch& s) {
+static hipError_t rowpass_launch(const RowArgs& a, const Launch& s, const OutArgs* o) {
   const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P, (unsigned)a.G), block(UB * FB * L / (4 * SQ));
-  PS_LAUNCH((k_rowpass<L, UB, FB, SQ>), grid, block, s, a);
+  if (o) {
+    if (a.G != 1) return hipErrorInvalidValue;
+    PS_LAUNCH((k_rowpass_stokes<L, UB, FB, SQ>), grid, block, s, a, *o);
+  } else {
+    PS_LAUNCH((k_rowpass<L, UB, FB, SQ>), grid, block, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -644,22 +685,22 @@ bool rowpass_has(int N2, int fb) {
   return (N2 == 256 || N2 == 512) && fb == 4;
 }
 
-hipError_t launch_rowpass(int N2, int fb, const RowArgs& a, const Launch& s) {
+hipError_t launch_rowpass(int N2, int fb, const RowArgs& a, const Launch& s, const OutArgs* o) {
   constexpr int SQ = PS_ROWPASS_SQ;
   if (fb != rowpass_frames(N2)) {
-    if (N2 == 256 && fb == 4) return rowpass_launch<256, 1, 4, SQ>(a, s);
-    if (N2 == 512 && fb == 4) return rowpass_launch<512, 1, 4, SQ>(a, s);
+    if (N2 == 256 && fb == 4) return rowpass_launch<256, 1, 4, SQ>(a, s, o);
+    if (N2 == 512 && fb == 4) return rowpass_launch<512, 1, 4, SQ>(a, s, o);
     return hipErrorInvalidValue;
   }
   switch (N2) {
-    case 16: return rowpass_launch<16, 8, 8, 2>(a, s);
-    case 32: return rowpass_launch<32, 8, 8, 2>(a, s);
-    case 64: return rowpass_launch<64, 4, 8, 2>(a, s);
-    case 128: return rowpass_launch<128, 2, 8, 2>(a, s);
-    case 256: return rowpass_launch<256, 1, 8, SQ>(a, s);
-    case 512: return rowpass_launch<512, 1, 8, SQ>(a, s);
-    case 1024: return rowpass_launch<1024, 1, 4, 2>(a, s);
-    case 2048: return rowpass_launch<2048, 1, 2, 2>(a, s);
+    case 16: return rowpass_launch<16, 8, 8, 2>(a, s, o);
+    case 32: return rowpass_launch<32, 8, 8, 2>(a, s, o);
+    case 64: return rowpass_launch<64, 4, 8, 2>(a, s, o);
+    case 128: return rowpass_launch<128, 2, 8, 2>(a, s, o);
+    case 256: return rowpass_launch<256, 1, 8, SQ>(a, s, o);
+    case 512: return rowpass_launch<512, 1, 8, SQ>(a, s, o);
+    case 1024: return rowpass_launch<1024, 1, 4, 2>(a, s, o);
+    case 2048: return rowpass_launch<2048, 1, 2, 2>(a, s, o);
     default: return hipErrorInvalidValue;
   }
 }

@@ -97,6 +97,8 @@ def test_calls_before_bind_are_state_errors():
     ns = (C.c_int64 * 1)(0)
     assert pk.STATUS[L.ps_accumulate(h, ptrs, ns)] == "PS_ERR_STATE"
     assert pk.STATUS[L.ps_stokes(h, 0, None, C.c_void_p(16))] == "PS_ERR_STATE"
+    outs = (C.c_void_p * 1)(16)
+    assert pk.STATUS[L.ps_accumulate_stokes(h, ptrs, ns, None, outs)] == "PS_ERR_STATE"
     L.ps_destroy(h)
 
 
