@@ -299,6 +299,17 @@ ps_status ps_bandpass_work_bytes(int64_t n_chan, int32_t knot_spacing, double ed
 ps_status ps_bandpass_fit(const float* h_dev, int64_t n_chan, int32_t knot_spacing, double edge_frac,
                           void* work_dev, size_t work_bytes, float* smooth_dev, void* hip_stream);
 
+/* ps_bandpass_fit for callers that cannot allocate device memory (code under hipGraph capture, serving
+ * loops, harnesses that forbid allocation): the same kernels, with the work buffer taken from a static
+ * device array of 128 KiB that each GPU holds until the process ends, enough for fits of up to 1024
+ * spline coefficients (131072 channels at 128-channel knots need 905).  Allocates nothing and calls no
+ * allocating routine; its first call on a GPU looks up that GPU's copy of the array.  Larger fits return
+ * PS_ERR_SIZE before anything is enqueued.  Every call on one GPU uses the same array (every byte a call
+ * reads is written earlier in that call, so nothing carries over), so calls that overlap on one GPU, e.g.
+ * on two streams at once, race. */
+ps_status ps_bandpass_fit_static(const float* h_dev, int64_t n_chan, int32_t knot_spacing, double edge_frac,
+                                 float* smooth_dev, void* hip_stream);
+
 /* Bandpass variation (Sec. 3.3.2): out[k][c] = hk[k][c] / (gain[k] smooth[c]) for spectra k < n_spec
  * (<= 65535) of n_chan channels; gain [n_spec] double (the total-power gain G_k of each integration) or NULL
  * (= 1).  FP64 arithmetic, FP32 output. */

@@ -125,6 +125,7 @@ def lib():
             "ps_bandpass_work_bytes": [i64, i32, C.c_double, C.POINTER(sz)],
             "ps_bandpass_fit": [vp, i64, i32, C.c_double, vp, sz, vp, vp],
             "ps_bandpass_correct": [vp, i64, i64, vp, vp, vp, vp],
+            "ps_bandpass_fit_static": [vp, i64, i32, C.c_double, vp, vp],
             "ps_band_stats": [vp, i64, i64, vp, vp],
             "ps_allan_work_bytes": [i64, i64, i64, i64, i32, C.POINTER(sz)],
             "ps_allan": [vp, i64, i64, i64, i64, C.POINTER(i32), i32, C.c_double, i32, vp, sz, vp, vp],

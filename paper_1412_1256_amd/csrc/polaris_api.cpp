@@ -1640,6 +1640,17 @@ ps_status ps_bandpass_work_bytes(int64_t n_chan, int32_t knot_spacing, double ed
   return PS_OK;
 }
 
+static ps_status bandpass_fit_in(ps::SplineArgs& a, const float* h_dev, char* work, float* smooth_dev,
+                                  void* hip_stream) {
+  a.h = h_dev;
+  a.partial = reinterpret_cast<double*>(work);
+  a.coef = reinterpret_cast<double*>(work + align_up((size_t)a.n_int * 14 * 8));
+  a.smooth = smooth_dev;
+  hipError_t e = ps::launch_bandpass_fit(a, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "bandpass fit launch");
+  return PS_OK;
+}
+
 ps_status ps_bandpass_fit(const float* h_dev, int64_t n_chan, int32_t knot_spacing, double edge_frac,
                           void* work_dev, size_t work_bytes, float* smooth_dev, void* hip_stream) {
   if (!h_dev || !smooth_dev) return fail(PS_ERR_ARG, "null spectrum or output");
@@ -1651,14 +1662,23 @@ ps_status ps_bandpass_fit(const float* h_dev, int64_t n_chan, int32_t knot_spaci
   if (work_bytes < spline_work_bytes(a))
     return fail(PS_ERR_WORKSPACE, "work buffer of %zu bytes is smaller than the %zu needed", work_bytes,
                 spline_work_bytes(a));
-  char* w = static_cast<char*>(work_dev);
-  a.h = h_dev;
-  a.partial = reinterpret_cast<double*>(w);
-  a.coef = reinterpret_cast<double*>(w + align_up((size_t)a.n_int * 14 * 8));
-  a.smooth = smooth_dev;
-  hipError_t e = ps::launch_bandpass_fit(a, static_cast<hipStream_t>(hip_stream));
-  if (e != hipSuccess) return hip_fail(e, "bandpass fit launch");
-  return PS_OK;
+  return bandpass_fit_in(a, h_dev, static_cast<char*>(work_dev), smooth_dev, hip_stream);
+}
+
+ps_status ps_bandpass_fit_static(const float* h_dev, int64_t n_chan, int32_t knot_spacing, double edge_frac,
+                                 float* smooth_dev, void* hip_stream) {
+  if (!h_dev || !smooth_dev) return fail(PS_ERR_ARG, "null spectrum or output");
+  ps::SplineArgs a{};
+  ps_status st = spline_args(n_chan, knot_spacing, edge_frac, &a);
+  if (st != PS_OK) return st;
+  if (spline_work_bytes(a) > ps::kBandpassScratchBytes)
+    return fail(PS_ERR_SIZE, "%lld spline coefficients need %zu bytes of scratch; the static buffer holds %zu (%lld coefficients)",
+                (long long)a.n_coef, spline_work_bytes(a), ps::kBandpassScratchBytes,
+                (long long)ps::kBandpassScratchCoef);
+  void* work = nullptr;
+  hipError_t e = ps::bandpass_scratch(static_cast<hipStream_t>(hip_stream), &work);
+  if (e != hipSuccess) return hip_fail(e, "static scratch address");
+  return bandpass_fit_in(a, h_dev, static_cast<char*>(work), smooth_dev, hip_stream);
 }
 
 ps_status ps_bandpass_correct(const float* hk_dev, int64_t n_spec, int64_t n_chan, const float* smooth_dev,

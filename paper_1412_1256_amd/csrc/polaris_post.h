@@ -45,6 +45,18 @@ int64_t allan_part_doubles(int64_t n_points, int64_t n_series, int64_t point_str
 
 hipError_t launch_channel_average(const ChanAvgArgs& a, hipStream_t s);
 hipError_t launch_bandpass_fit(const SplineArgs& a, hipStream_t s);
+
+// Allocation-free bandpass fit: its work (interval partials and coefficients) lives in a static device array
+// of this size on each GPU, enough for fits of up to kBandpassScratchCoef spline coefficients.
+constexpr int64_t kBandpassScratchCoef = 1024;
+constexpr size_t kBandpassScratchBytes = 128 * 1024;
+static_assert(((kBandpassScratchCoef - 3) * 14 * 8 + 255) / 256 * 256 + ((kBandpassScratchCoef * 8 + 255) / 256 * 256) <=
+                  kBandpassScratchBytes,
+              "the scratch holds the work of every fit of kBandpassScratchCoef coefficients");
+constexpr int kMaxDevices = 64;
+// Device address of the scratch array on the GPU of stream (the current GPU for the null stream), found on
+// the first call for that GPU.
+hipError_t bandpass_scratch(hipStream_t stream, void** ptr);
 hipError_t launch_bandpass_correct(const float* hk, int64_t n_spec, int64_t n_chan, const float* smooth,
                                    const double* gain, float* out, hipStream_t s);
 hipError_t launch_band_stats(const float* x, int64_t n_spec, int64_t n_chan, double* mean_sd, hipStream_t s);

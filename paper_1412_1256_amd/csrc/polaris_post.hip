@@ -6,6 +6,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace ps {
 
 namespace {
@@ -439,6 +441,35 @@ hipError_t launch_channel_average(const ChanAvgArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_chan_avg_wide, dim3((unsigned)n_bins, (unsigned)a.n_spec), dim3(kNT), 0, s, a);
   }
   return hipGetLastError();
+}
+
+// ---- scratch of the allocation-free bandpass fit: a file-scope device array, one copy per GPU, found once
+// per device with hipGetSymbolAddress (host code may use only that address, never the array's name)
+static __device__ __align__(256) unsigned char scratch[kBandpassScratchBytes];
+
+hipError_t bandpass_scratch(hipStream_t stream, void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = stream ? hipStreamGetDevice(stream, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    int cur = -1;
+    if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_bandpass_fit(const SplineArgs& a, hipStream_t s) {
