@@ -135,7 +135,9 @@ typedef struct {
   float* d_taps;
 } ps_cal_grad;
 
-/* Validate n_inst instances, build host tables and report the workspace size (bytes, 256-aligned).
+/* Validate n_inst instances, build host tables and report the workspace size (bytes, 256-aligned).  An
+ * instance is one sampler stream set with its polarization pairs: Table 1's four IFs X0, X1, Y0, Y1 make one
+ * instance of four streams and two pairs (X0, Y0), (X1, Y1); a plan of several instances runs them together.
  * Errors: PS_ERR_ARG for bad fields, PS_ERR_UNSUPPORTED for valid but unimplemented options. */
 ps_status ps_plan(const ps_instance* inst, int32_t n_inst, ps_plan_t* out, size_t* workspace_bytes);
 
@@ -180,17 +182,20 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
 ps_status ps_schedule_candidates(const ps_instance* inst, ps_schedule* out, int32_t capacity, int32_t* count);
 
 /* Attach a device workspace (>= the reported size, 256-byte aligned) and a HIP stream (hipStream_t,
- * NULL = the default stream); uploads the FP64-generated twiddle and window tables and waits for the
- * upload.  Re-binding is allowed and resets every integration. */
+ * NULL = the default stream); uploads the FP64-generated twiddle and window tables of the transforms of
+ * Sec. 2 (function 2) and waits for the upload.  Re-binding is allowed and resets every integration. */
 ps_status ps_bind(ps_plan_t plan, void* workspace_dev, size_t bytes, void* hip_stream);
 
 /* Set the n_taps window control points of a PS_WIN_TAPS instance from device floats (enqueued). */
 ps_status ps_set_window_taps(ps_plan_t plan, int32_t inst, const float* taps_dev);
 
-/* Start a new integration for every instance (host bookkeeping only; enqueues nothing). */
+/* Start a new integration for every instance (Sec. 2, function 4: the products are integrated from here
+ * on; Table 1's output period is 1 s).  Host bookkeeping only; enqueues nothing. */
 ps_status ps_reset(ps_plan_t plan);
 
-/* Add whole segments to each instance's integration (Sec. 2: FFT, cross products, accumulation).
+/* Add whole segments to each instance's integration: Sec. 2 functions 1-4 (accept the two polarizations,
+ * Fourier-transform them, multiply the spectra into power and cross-power spectra, integrate), in the
+ * Fig. 2 caption's order (data translation, segmentation, FFT, cross products, accumulation).
  *   packed_dev[i]   device pointer to instance i's packed buffer (layout above); may be NULL when
  *                   n_samples[i] == 0.
  *   n_samples[i]    samples per stream, a multiple of fft_len (PS_ERR_SIZE otherwise).
@@ -213,8 +218,9 @@ ps_status ps_accumulate(ps_plan_t plan, const void* const* packed_dev, const int
 ps_status ps_accumulate_stokes(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples,
                                const ps_cal* cal, float* const* iquv_dev);
 
-/* Raw accumulated products of instance inst into out_dev [n_pairs][4][C] doubles:
- * sum over frames of XX*, YY*, Re XY*, Im XY* (unnormalised), and the frame count (host).
+/* Raw accumulated products of instance inst into out_dev [n_pairs][4][C] doubles: Table 1's four real and
+ * two complex products per pair of IFs, i.e. the sums over frames of XX*, YY*, Re XY*, Im XY* (unnormalised),
+ * and the frame count (host).
  * PS_ERR_STATE if no frame has been accumulated since ps_reset. */
 ps_status ps_spectra(ps_plan_t plan, int32_t inst, double* out_dev, int64_t* n_frames);
 
@@ -261,6 +267,13 @@ ps_status ps_graph_launch(ps_plan_t plan);
  * transformed again instead of being stored.  PS_ERR_STATE if the frame count does not match. */
 ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed_dev, int64_t n_samples,
                                 const ps_cal* cal, const float* dL_diquv_dev, const ps_cal_grad* grad);
+
+/* Integration id of instance inst: a number that changes whenever the state ps_calibrate_backward reads
+ * changes (ps_reset, ps_accumulate or ps_accumulate_stokes with frames, ps_set_window_taps, ps_state_import,
+ * ps_graph_launch, ps_bind).  A caller that takes a gradient later, e.g. an autograd node, records the id after
+ * its forward and compares it before the backward: a different id means another forward ran on the plan in
+ * between, and the backward would return that forward's gradients. */
+ps_status ps_integration_id(ps_plan_t plan, int32_t inst, uint64_t* id);
 
 /* Integration state for checkpoint and resume: the accumulators and, for overlapped segmentation, the
  * samples waiting for the next call (the frame count is passed separately).  Device buffers of

@@ -126,6 +126,7 @@ def lib():
             "ps_bandpass_fit": [vp, i64, i32, C.c_double, vp, sz, vp, vp],
             "ps_bandpass_correct": [vp, i64, i64, vp, vp, vp, vp],
             "ps_bandpass_fit_static": [vp, i64, i32, C.c_double, vp, vp],
+            "ps_integration_id": [vp, i32, C.POINTER(C.c_uint64)],
             "ps_band_stats": [vp, i64, i64, vp, vp],
             "ps_allan_work_bytes": [i64, i64, i64, i64, i32, C.POINTER(sz)],
             "ps_allan": [vp, i64, i64, i64, i64, C.POINTER(i32), i32, C.c_double, i32, vp, sz, vp, vp],
@@ -417,6 +418,12 @@ class Plan:
         _check(lib().ps_calibrate_backward(self._h, inst, _ptr(packed), n_samples, C.byref(cal), _ptr(g),
                                            C.byref(grad)))
         return outs
+
+    def integration_id(self, inst: int = 0) -> int:
+        """Changes whenever the integration a gradient would be taken of changes (see ps_integration_id)."""
+        v = C.c_uint64()
+        _check(lib().ps_integration_id(self._h, inst, C.byref(v)))
+        return v.value
 
     def set_window_taps(self, taps, inst: int = 0):
         t = self._as_f32(taps)

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import torch
 
-from . import Plan
+from . import Plan, PolarisError
 
 
 class StokesFn(torch.autograd.Function):
@@ -25,10 +25,16 @@ class StokesFn(torch.autograd.Function):
         ctx.save_for_backward(*(t if t is not None else torch.empty(0) for t in (gain_x, gain_y, dterms, taps)))
         ctx.present = tuple(t is not None for t in (gain_x, gain_y, dterms, taps))
         ctx.plan, ctx.packed, ctx.psi = plan, packed, psi
+        ctx.integration = plan.integration_id()
         return iquv
 
     @staticmethod
     def backward(ctx, g_iquv):
+        if ctx.plan.integration_id() != ctx.integration:
+            # another forward (or reset, accumulate, new taps) ran on the plan since this node's forward: its
+            # accumulators and window are no longer this node's
+            raise PolarisError(4, "the plan's integration changed after this forward; run the backward before "
+                                  "the next forward on the same plan, or use one plan per forward")
         gx, gy, dt, taps = (t if p else None for t, p in zip(ctx.saved_tensors, ctx.present))
         want = []
         if ctx.needs_input_grad[0]:

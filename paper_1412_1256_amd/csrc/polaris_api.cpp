@@ -114,6 +114,9 @@ struct Inst {
   const ps_cal* fuse_cal = nullptr;
   bool fuse_done = false;
   bool can_fuse() const { return !fused && !mx() && G == 1; }
+  // integration id: changes whenever the state a gradient would be taken of changes (reset, frames added,
+  // window taps set, state imported, graph replayed, plan re-bound)
+  uint64_t gen = 0;
 };
 
 }  // namespace
@@ -147,6 +150,8 @@ struct ps_plan_s {
     int64_t n_frames, hist_frames;
   };
   std::vector<InstState> graph_state;
+  uint64_t gen_counter = 0;
+  void touch(Inst& I) { I.gen = ++gen_counter; }
   ~ps_plan_s() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (acc_desc.host) (void)hipHostFree(acc_desc.host);
@@ -1029,7 +1034,12 @@ ps_status ps_bind(ps_plan_t plan, void* workspace_dev, size_t bytes, void* hip_s
     I.n_frames = 0;
     I.hist_zeroed = false;
     I.hist_frames = 0;
+    plan->touch(I);
   }
+  // the descriptor regions of the new workspace hold nothing yet (the cached images describe the old one,
+  // and a new workspace at the same address still starts uninitialised)
+  plan->acc_desc.current.clear();
+  plan->out_desc.current.clear();
   hipError_t e = hipStreamSynchronize(plan->stream);
   if (e != hipSuccess) return hip_fail(e, "ps_bind synchronise");
   plan->bound = true;
@@ -1043,6 +1053,7 @@ ps_status ps_set_window_taps(ps_plan_t plan, int32_t inst, const float* taps_dev
   Inst& I = plan->inst[(size_t)inst];
   if (!I.taps()) return fail(PS_ERR_ARG, "instance %d does not use a PS_WIN_TAPS window", inst);
   if (!taps_dev) return fail(PS_ERR_ARG, "null taps");
+  plan->touch(I);
   hipError_t e = ps::launch_copy(taps_dev, plan->ws + I.off_taps, (size_t)I.cfg.n_taps * 4, plan->stream);
   if (e != hipSuccess) return hip_fail(e, "taps copy");
   ps::WinArgs w{};
@@ -1066,6 +1077,7 @@ ps_status ps_reset(ps_plan_t plan) {
     I.n_frames = 0;
     I.hist_zeroed = false;
     I.hist_frames = 0;
+    plan->touch(I);
   }
   return PS_OK;
 }
@@ -1094,6 +1106,8 @@ static int64_t frames_after(const Inst& I, int64_t T) {
 
 static ps_status accumulate_impl(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples) {
   ps_status st = PS_OK;
+  for (size_t i = 0; i < plan->inst.size(); ++i)
+    if (n_samples[i] > 0) plan->touch(plan->inst[i]);
   // First, per instance: the histogram clear and, with overlapped frames, the frames that span the
   // previous call and this one (they precede this call's own frames in the integration).
   for (size_t i = 0; i < plan->inst.size(); ++i) {
@@ -1355,6 +1369,7 @@ ps_status ps_graph_launch(ps_plan_t plan) {
     I.n_frames = g.n_frames;
     I.hist_zeroed = g.hist_zeroed;
     I.hist_frames = g.hist_frames;
+    plan->touch(I);
   }
   return PS_OK;
 }
@@ -1533,6 +1548,16 @@ ps_status ps_state_import(ps_plan_t plan, int32_t inst, const void* src_dev, int
   if (e != hipSuccess) return hip_fail(e, "state import");
   I.n_frames = n_frames;
   I.first = false;
+  plan->touch(I);
+  return PS_OK;
+}
+
+ps_status ps_integration_id(ps_plan_t plan, int32_t inst, uint64_t* id) {
+  if (!plan) return fail(PS_ERR_ARG, "null plan");
+  ps_status st = check_inst(plan, inst);
+  if (st != PS_OK) return st;
+  if (!id) return fail(PS_ERR_ARG, "null id");
+  *id = plan->inst[(size_t)inst].gen;
   return PS_OK;
 }
 

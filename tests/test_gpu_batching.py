@@ -89,8 +89,84 @@ def test_grouped_sub_batches_share_the_inter_pass_buffer(env):
     c = run(env, insts)
     for i, (x, y) in enumerate(zip(a, c)):
         assert np.array_equal(x, y), f"instance {i} (second plan)"
+    # the same plan object again: reset, then every instance's samples in two calls (whole frames each)
+    plan = pk.Plan([pk.Instance.from_synth(d) for d in insts], device=dev)
+    packed = [torch.from_numpy(d["packed"]).to(dev) for d in insts]
+    plan.reset()
+    plan.accumulate(packed)
+    plan.reset()
+    cut = [(d["n_frames"] // 2) * d["fft_len"] * d["n_streams"] * d["bits"] // 8 for d in insts]
+    plan.accumulate([p[:k] for p, k in zip(packed, cut)])
+    plan.accumulate([p[k:] for p, k in zip(packed, cut)])
+    for i in range(len(insts)):
+        assert np.array_equal(plan.spectra(i)[0].cpu().numpy(), a[i]), f"instance {i} (same plan, two calls)"
     acc, nf, _, _ = oracle.run_instance(insts[1])
     assert np.max(np.abs(a[1] - acc) / np.mean(acc[:, 0:1, :], axis=2, keepdims=True)) < 1e-5
+
+
+def test_grouped_long_transforms(env):
+    """The grouped 1024- and 2048-point pass kernels (2^19 as 1024 x 512, 2^20 as 512 x 2048) in one plan with
+    a 2^17 instance, 2- and 8-bit, at least 32 frames each: bitwise equal to separate plans, and every instance's
+    Stokes products within 1e-5 of the FP64 oracle (per channel, relative to I)."""
+    torch, pk, dev = env
+    say("grouped plan of 2^17, 2^19 and 2^20 instances")
+    spec = [(17, 8, 40), (19, 2, 32), (19, 8, 34), (20, 8, 32), (20, 2, 33)]
+    insts = [synth.make_correlated_noise(bits, 0.1 + 0.08 * i, 1 << e, F, cfg=4, seed_extra=950 + i)
+             for i, (e, bits, F) in enumerate(spec)]
+    packed = [torch.from_numpy(d["packed"]).to(dev) for d in insts]
+    plan = pk.Plan([pk.Instance.from_synth(d) for d in insts], device=dev)
+    plan.profile_enable(True)
+    plan.reset()
+    plan.accumulate(packed)
+    outs = plan.stokes_all(cals=[(None, None, None, 0.2 * i) for i in range(len(insts))])
+    prof = plan.profile_read()
+    plan.profile_enable(False)
+    torch.cuda.synchronize(dev)
+    # one grouped column pass and one row pass per shape class (2^17; 2^19 2-bit and 8-bit; 2^20 2- and 8-bit)
+    say(f"  launches {prof}")
+    assert prof["colpass"][1] == 5 and prof["rowpass"][1] == 5
+    sep = run(env, insts, separate=True)
+    for i, d in enumerate(insts):
+        assert np.array_equal(plan.spectra(i)[0].cpu().numpy(), sep[i]), f"instance {i}"
+        acc, nf, s2, _ = oracle.run_instance(d)
+        ref = oracle.stokes(acc, nf, s2, psi=0.2 * i)
+        got = outs[i].cpu().numpy().astype(np.float64)
+        e = np.max(np.abs(got - ref) / ref[:, 0:1, :], axis=2)
+        say(f"  N=2^{spec[i][0]} bits={spec[i][1]} F={spec[i][2]} stokes err {e.ravel().tolist()}")
+        assert np.all(e < 1e-5), (i, e)
+
+
+def test_rebind_uploads_descriptors_again(env):
+    """ps_bind onto a fresh (zeroed) workspace, at the same address when the allocator hands it back: the
+    grouped launches' descriptors must be uploaded again, and the results equal the first binding's."""
+    import ctypes as C
+    torch, pk, dev = env
+    say("re-bound grouped plan")
+    insts = mixed_set()[:5]
+    packed = [torch.from_numpy(d["packed"]).to(dev) for d in insts]
+    plan = pk.Plan([pk.Instance.from_synth(d) for d in insts], device=dev)
+    plan.reset()
+    plan.accumulate(packed)
+    first = [o.clone() for o in plan.stokes_all()]
+    torch.cuda.synchronize(dev)
+    addr = plan.workspace.data_ptr()
+    n = plan.workspace_bytes
+    del plan.workspace
+    plan._ws_raw = None
+    torch.cuda.synchronize(dev)
+    raw = torch.zeros(n + 256, dtype=torch.uint8, device=dev)
+    off = (-raw.data_ptr()) % 256
+    ws = raw[off:off + n]
+    say(f"  same address: {ws.data_ptr() == addr}")
+    st = pk.lib().ps_bind(plan._h, C.c_void_p(ws.data_ptr()), n, C.c_void_p(plan.stream.cuda_stream))
+    assert st == 0, pk.lib().ps_last_error()
+    plan._ws_raw, plan.workspace = raw, ws
+    plan.reset()
+    plan.accumulate(packed)
+    again = plan.stokes_all()
+    torch.cuda.synchronize(dev)
+    for i, (x, y) in enumerate(zip(first, again)):
+        assert torch.equal(x, y), f"instance {i}"
 
 
 def test_grouped_against_oracle(env):

@@ -133,3 +133,24 @@ def test_chunks_and_calls(env):
     rel = np.max(np.abs(a - b) / a[:, 0:1, :])
     say(f"  chunked vs whole {rel}")
     assert rel < 1e-6
+
+
+@pytest.fixture(scope="module")
+def config3():
+    """The precision case at its stated length: 4 int8 streams (2 bands x 2 pols), 2^18 points, 610 frames
+    (10 s), and its FP64 oracle Stokes."""
+    inst = synth.make_precision(n_frames=610)
+    return inst, ref_stokes(inst)
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_precision_config_610_frames(env, config3, precision):
+    """Both 16-bit formats with Kahan-compensated integration over the 610 frames: every Stokes product of
+    both pairs within 1e-3 of the oracle (per channel, relative to I).  By the estimate above the errors at
+    F = 610 are about 6.9e-5 (FP16) and 5.7e-4 (BF16), the 32-frame figures times sqrt(32 / 610)."""
+    inst, ref = config3
+    say(f"precision case, 610 frames, {precision} + kahan32")
+    got = run_gpu(env, inst, precision, "kahan32")
+    e = np.max(np.abs(got - ref) / ref[:, 0:1, :], axis=2)
+    say(f"  per-Stokes errors {e.tolist()}")
+    assert np.all(e < 1e-3), e
