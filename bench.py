@@ -50,7 +50,7 @@ def parse():
                     help="headline as ps_accumulate then ps_stokes (default: the one-call ps_accumulate_stokes)")
     ap.add_argument("--main-only", action="store_true",
                     help="only the headline workload (for profiler runs): no other sections, no CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="minimum oracle time (whole integrations)")
+    ap.add_argument("--cpu-seconds", type=float, default=6.0, help="minimum oracle time (whole integrations)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
     ap.add_argument("--only", choices=["short_transforms", "post_reduction", "table1_modes", "overlap_form", "fwd_bwd",
                                        "precision_form"],
@@ -122,25 +122,98 @@ def counter_traffic() -> dict:
 
 
 def cpu_baseline(inst: dict, min_seconds: float):
-    """Whole integrations by the oracle, repeated until at least min_seconds of CPU work have run."""
+    """The FP64 oracle on the host: the paper-shaped integration (the headline workload) on all threads (up to
+    16) and on one, and the other configurations: the tiny case, the differentiation case (forward + analytic
+    gradient), and bounded subsets of the precision case (1 s of its 10 s) and of the batching case (frames
+    capped at 16 per instance), each extrapolated linearly in frames to the whole configuration."""
+    import numpy as np
+
     import oracle
+    import synth
     threads = min(16, os.cpu_count() or 1)
-    # one untimed run builds/loads the oracle
-    acc, nf, s2, _ = oracle.run_instance(inst, nthreads=threads)
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        acc, nf, s2, _ = oracle.run_instance(inst, nthreads=threads)
-        oracle.stokes(acc, nf, s2, psi=0.25)
-        reps += 1
-        dt = time.perf_counter() - t0
-        if dt >= min_seconds:
-            break
-    samples = inst["n_samples"] * inst["n_streams"] * reps
-    return {"value": samples / dt / 1e9, "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} full integrations of the paper-shaped workload ({inst['n_frames']} frames of "
-                      f"2x2^18 int8 samples each), FP64 radix-2 oracle incl. Stokes",
-            "seconds": dt, "x_realtime": reps * inst["n_samples"] / SAMPLE_RATE / dt}
+
+    def run(fn, min_s, max_reps=10 ** 6, warm=True):
+        if warm:
+            fn()  # untimed: builds/loads the oracle and touches the data
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_s or reps >= max_reps:
+                return dt / reps
+
+    def integrate(d, nt, psi=0.25):
+        acc, nf, s2, _ = oracle.run_instance(d, nthreads=nt)
+        oracle.stokes(acc, nf, s2, psi=psi)
+
+    def entry(samples, seconds_of_data, t, nt, sample):
+        return {"Gsamples_per_s": samples / t / 1e9, "x_realtime": seconds_of_data / t, "seconds_per_integration": t,
+                "threads": nt, "sample": sample}
+
+    n2 = inst["n_samples"] * inst["n_streams"]
+    sec2 = inst["n_samples"] / SAMPLE_RATE
+    t_all = run(lambda: integrate(inst, threads), min_seconds)
+    t_one = run(lambda: integrate(inst, 1), 0.0, max_reps=1, warm=False)
+    out = {"value": n2 / t_all / 1e9, "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
+           "sample": f"whole integrations of the paper-shaped workload ({inst['n_frames']} frames of 2 x 2^18 int8 "
+                     f"samples), FP64 radix-2 oracle incl. Stokes, repeated for >= {min_seconds:g} s on {threads} "
+                     "threads",
+           "x_realtime": sec2 / t_all,
+           "one_core": entry(n2, sec2, t_one, 1, "one whole integration on one thread")}
+    cfg = {}
+    tiny = synth.make_tiny()
+    nt_ = tiny["n_samples"] * tiny["n_streams"]
+    cfg["tiny"] = {"all_threads": entry(nt_, tiny["n_samples"] / SAMPLE_RATE, run(lambda: integrate(tiny, threads), 0.5),
+                                        threads, "whole integrations (2 x 2-bit, 1024-pt Hann frames, 64 frames)"),
+                   "one_core": entry(nt_, tiny["n_samples"] / SAMPLE_RATE, run(lambda: integrate(tiny, 1), 0.5), 1,
+                                     "whole integrations")}
+    dif = synth.make_differentiation()
+    N5, C5 = dif["fft_len"], dif["fft_len"] // 2
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal((1, 4, C5))
+    gx = dif["init_gain_x"][None].astype(np.complex128)
+    gy = dif["init_gain_y"][None].astype(np.complex128)
+    taps = np.ones(64)
+
+    def fwd_bwd():
+        w, s2 = oracle.window("taps", N5, taps=taps)
+        acc, nf = oracle.accumulate(dif["packed"], 8, 2, dif["n_samples"], N5, w, dif["pairs"], nthreads=threads)
+        oracle.stokes(acc, nf, s2, gain_x=gx, gain_y=gy, dterms=np.zeros((1, 2)))
+        oracle.calibrate_backward(dif["packed"], 8, 2, dif["n_samples"], N5, w, dif["pairs"], acc, nf, s2, g,
+                                  gain_x=gx, gain_y=gy, dterms=np.zeros((1, 2)), taps=taps, nthreads=threads)
+    n5 = dif["n_samples"] * 2
+    cfg["differentiation_fwd_bwd"] = entry(n5, dif["n_samples"] / SAMPLE_RATE, run(fwd_bwd, 1.0), threads,
+                                           "forward (64-tap window, integration, calibrated Stokes) + analytic "
+                                           "gradient of gains, leakage and taps, 2 x int8, 2^16 pts, 128 frames")
+    # the oracle's cost does not depend on the sample values: random codes of each configuration's format
+    rb = np.random.default_rng(14121256)
+    N3, F3 = 1 << 18, 61
+    d3 = dict(packed=rb.integers(0, 256, F3 * N3 * 4, dtype=np.uint8), bits=8, n_streams=4, fft_len=N3, n_frames=F3,
+              n_samples=F3 * N3, window="rect", pairs=[(0, 2), (1, 3)])
+    t3 = run(lambda: integrate(d3, threads), 1.0)
+    e3 = entry(4 * F3 * N3, F3 * N3 / SAMPLE_RATE, t3, threads, "1 s (61 frames) of the precision case's 4 int8 "
+               "streams, 2 pairs, FP64 (the oracle has no 16-bit form)")
+    e3["extrapolated_seconds_per_10s_integration"] = t3 * 610 / 61
+    cfg["precision_1s_subset"] = e3
+    e, F, bits, _ = synth.batching_params()
+    t4_sub, t4_full, s4_sub, s4_full = 0.0, 0.0, 0, 0
+    for ei, Fi, bi in zip(e, F, bits):
+        Ni, Fc = 1 << int(ei), min(int(Fi), 16)
+        di = dict(packed=rb.integers(0, 256, Fc * Ni * 2 * int(bi) // 8, dtype=np.uint8), bits=int(bi), n_streams=2,
+                  fft_len=Ni, n_frames=Fc, n_samples=Fc * Ni, window="rect", pairs=[(0, 1)])
+        ti = run(lambda: integrate(di, threads, psi=0.0), 0.0, max_reps=1, warm=False)
+        t4_sub += ti
+        t4_full += ti * int(Fi) / Fc
+        s4_sub += 2 * Fc * Ni
+        s4_full += 2 * int(Fi) * Ni
+    cfg["batching_F16_subset"] = {"Gsamples_per_s": s4_sub / t4_sub / 1e9, "seconds": t4_sub, "threads": threads,
+                                  "extrapolated_seconds_per_integration": t4_full,
+                                  "extrapolated_Gsamples_per_s": s4_full / t4_full / 1e9,
+                                  "sample": "the 64 instances (2^12 .. 2^20 pts, 2/8-bit) with frames capped at 16, "
+                                            "each timed once; whole-set time scaled per instance by F / min(F, 16)"}
+    out["configs"] = cfg
+    return out
 
 
 def time_steps(torch, dev, fn, steps, warmup):
