@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 METRIC = "input Gsamples/s (×real-time) FFT+Stokes at 2^18 pts; fwd+bwd vs plain"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+MFMA_16BIT_PEAK_TFLOPS = 2500.0  # dense FP16 / BF16 matrix-core peak, published
 SAMPLE_RATE = 16e6             # per stream
 
 
@@ -216,10 +217,15 @@ def cpu_baseline(inst: dict, min_seconds: float):
     return out
 
 
-def time_steps(torch, dev, fn, steps, warmup):
+def time_steps(torch, dev, fn, steps, warmup, warmup_s=0.05):
+    """seconds per call of fn over `steps` calls, after `warmup` calls and at least warmup_s of them"""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize(dev)
+    t_end = time.perf_counter() + warmup_s
+    while time.perf_counter() < t_end:
+        fn()
+        torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
@@ -323,7 +329,14 @@ def precision_form(pk, torch, dev, steps, warmup, with_oracle=True):
             kern[k] = {"us_per_step": ms / 2 * 1e3, "launches_per_step": n / 2,
                        "GBps": nbytes / (ms / 2 / 1e3) / 1e9}
         r = {"us_per_step": t * 1e6, "Gsamples_per_s": samples / t / 1e9, "x_realtime": F * N / SAMPLE_RATE / t,
+             "path_GBps": (kb("colpass", inst, F) + kb("rowpass", inst, F) + P * (N // 2) * 48) / t / 1e9,
              "kernels": kern}
+        if prec != "fp32":
+            # matrix-core work actually issued: N / 16 products of 16 x 16 x 32 (hi and lo parts of the DFT
+            # matrices both counted) per frame and pair, 2 x 16 x 16 x 32 flops each
+            mf = 1024.0 * N * F * P / t / 1e12
+            r["mfma_tflops"] = mf
+            r["mfma_frac_dense_peak"] = mf / MFMA_16BIT_PEAK_TFLOPS
         if ref is not None:
             got = out.cpu().numpy().astype(np.float64)
             e = np.max(np.abs(got - ref) / ref[:, 0:1, :], axis=2)
