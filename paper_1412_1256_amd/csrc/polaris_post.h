@@ -8,6 +8,7 @@ namespace ps {
 
 constexpr int kMaxAllanLags = 64;
 constexpr int64_t kAllanChunk = 4096;  // points per workgroup of a series (block form)
+constexpr int kWinMaxLag = 512;        // largest lag of the LDS-window form (side-by-side series)
 constexpr int64_t kMaxSplineCoef = 3072;  // basis functions of one bandpass fit (LDS of the solve)
 
 struct ChanAvgArgs {

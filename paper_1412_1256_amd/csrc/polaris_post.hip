@@ -429,6 +429,173 @@ __global__ void __launch_bounds__(kColsSeries * kColsSlices) k_allan_cols(AllanA
   }
 }
 
+// The same for side-by-side series whose lags are at most kWinMaxLag, through a window of the series held in
+// LDS.  A workgroup owns 32 neighbouring series (128-byte rows of the [t][series] array) and walks t in steps
+// of 64 rows; every row is read from memory once and then serves all its second differences from LDS.  The
+// window is a ring of kWinRing rows (the rows t - 2 Lmax .. t + 63 of a step) whose first 64 slots are
+// repeated after its end, so a run of 64 consecutive rows never wraps.  Thread (group g, phase q, half h)
+// holds the four series 4g .. 4g+3 (16-byte LDS reads) and takes the point t = r0 - Lmax + q of every step
+// r0 (the point whose t + Lmax has just arrived) for lags 4h .. 4h+3 of a group of up to eight.  A term is
+// added without a finiteness test: a series with a non-finite sample ends with a non-finite sum, and only
+// then is that (series, lag) summed again term by term, leaving out non-finite triples.  The 64 phases'
+// sums are added in phase order.  Needs rows that are 8-byte aligned and a row stride of whole float pairs.
+constexpr int kWinSeries = 32, kWinStep = 64, kWinGroups = kWinSeries / 4, kWinLags = 8, kWinAhead = 2;
+constexpr int kWinHalfLags = kWinLags / 2;
+constexpr int kWinRing = 2 * kWinMaxLag + 2 * kWinStep;
+constexpr int kWinThreads = kWinGroups * kWinStep * 2;
+
+__global__ void __launch_bounds__(kWinThreads) k_allan_window(AllanArgs a) {
+  __shared__ __align__(16) float buf[(kWinRing + kWinStep) * kWinSeries];
+  double* red = reinterpret_cast<double*>(buf);  // [lag][phase][series] phase sums, after a sweep
+  __shared__ double meanv[kWinSeries];            // squared series means (normalisation)
+  static_assert(kWinLags * kWinStep * kWinSeries * 8 <= (kWinRing + kWinStep) * kWinSeries * 4,
+                "the phase sums fit in the ring");
+  const int tid = (int)threadIdx.x;
+  const int g = tid % kWinGroups, q = (tid / kWinGroups) % kWinStep, h = tid / (kWinGroups * kWinStep);
+  const int64_t sb = (int64_t)blockIdx.x * kWinSeries;  // first series of the workgroup
+  const int P = (int)a.n_points;                          // < 2^31 (checked by the launcher)
+  const int64_t st = a.point_stride;
+  // loads: row r0 + q, the two series 4g + 2h, 4g + 2h + 1 (a wave reads whole 128-byte rows).  The series
+  // count is even, so a pair is wholly in or out; every load is issued (past the end: from row P - 1 or the
+  // first pair, a valid address) and replaced by zeros, so no load sits behind a branch.
+  const int ls = 4 * g + 2 * h;
+  const bool pin = sb + ls < a.n_series;
+  const float* xl = a.x + (pin ? sb + ls : 0);
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  // (the zeros are substituted when the pair enters the ring, so the load is not waited for until then)
+  auto fetch = [&](f2& d, int r) { d = *reinterpret_cast<const f2*>(xl + (int64_t)(r < P ? r : P - 1) * st); };
+  auto wrap = [](int k) { return k >= kWinRing ? k - kWinRing : k; };
+  auto rd = [&](int slot) { return *reinterpret_cast<const f4*>(&buf[slot * kWinSeries + 4 * g]); };
+  double xs[2] = {0, 0}, xn[2] = {0, 0};  // finite samples of the loaded series (normalisation), first sweep
+  for (int l0 = 0; l0 < a.n_lags; l0 += kWinLags) {
+    int L[kWinLags];
+    int lmax = 1;
+#pragma unroll
+    for (int l = 0; l < kWinLags; ++l) {
+      L[l] = l0 + l < a.n_lags ? a.lags[l0 + l] : 0;  // 0: not a lag of this group
+      lmax = L[l] > lmax ? L[l] : lmax;
+    }
+    int Lh[kWinHalfLags];
+#pragma unroll
+    for (int l = 0; l < kWinHalfLags; ++l) Lh[l] = h ? L[kWinHalfLags + l] : L[l];
+    double S[kWinHalfLags][4];
+#pragma unroll
+    for (int l = 0; l < kWinHalfLags; ++l)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) S[l][c] = 0.0;
+    f2 pre[kWinAhead];
+#pragma unroll
+    for (int u = 0; u < kWinAhead; ++u) fetch(pre[u], u * kWinStep + q);
+    int k0 = 0;                // slot of row r0
+    int bt = kWinRing - lmax;  // slot of row r0 - lmax (lmax <= kWinMaxLag < kWinRing)
+    auto step = [&](const int r0, f2& d) {
+      __syncthreads();  // every thread is done with the previous step's rows
+      {
+        if (!(pin && r0 + q < P)) d = f2{0.f, 0.f};
+        const int k = wrap(k0 + q);
+        *reinterpret_cast<f2*>(&buf[k * kWinSeries + ls]) = d;
+        if (k < kWinStep) *reinterpret_cast<f2*>(&buf[(k + kWinRing) * kWinSeries + ls]) = d;
+        if (l0 == 0 && a.normalize && r0 + q < P) {
+          if (isfinite(d.x)) {
+            xs[0] += (double)d.x;
+            xn[0] += 1.0;
+          }
+          if (isfinite(d.y)) {
+            xs[1] += (double)d.y;
+            xn[1] += 1.0;
+          }
+        }
+      }
+      fetch(d, r0 + kWinAhead * kWinStep + q);
+      __syncthreads();
+      // the point t = r0 - lmax + q counts for lag L when L <= t < P - L
+      const int t = r0 - lmax + q;
+      const f4 b = rd(bt + q);
+      const double xb[4] = {b.x, b.y, b.z, b.w};
+      bool all = true;  // every point of the step counts for every lag of this half (the same for every lane)
+#pragma unroll
+      for (int l = 0; l < kWinHalfLags; ++l)
+        all = all && Lh[l] >= 1 && r0 - lmax >= Lh[l] && r0 - lmax + kWinStep - 1 < P - Lh[l];
+      auto terms = [&](const bool masked) {
+#pragma unroll
+        for (int l = 0; l < kWinHalfLags; ++l) {
+          const f4 ua = rd(wrap(bt + Lh[l]) + q);
+          const f4 dc = rd((bt >= Lh[l] ? bt - Lh[l] : bt - Lh[l] + kWinRing) + q);
+          const double xa[4] = {ua.x, ua.y, ua.z, ua.w}, xc[4] = {dc.x, dc.y, dc.z, dc.w};
+          const bool use = !masked || (Lh[l] >= 1 && t >= Lh[l] && t < P - Lh[l]);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double dd = xa[c] - 2.0 * xb[c] + xc[c];
+            const double e = use ? dd : 0.0;  // an exact zero term outside the lag's range
+            S[l][c] = fma(e, e, S[l][c]);
+          }
+        }
+      };
+      if (all) terms(false);  // the bulk of the steps: no range test
+      else terms(true);
+      k0 = wrap(k0 + kWinStep);
+      bt = wrap(bt + kWinStep);
+    };
+    for (int r0 = 0; r0 < P + lmax; r0 += kWinAhead * kWinStep) {
+#pragma unroll
+      for (int u = 0; u < kWinAhead; ++u)
+        if (r0 + u * kWinStep < P + lmax) step(r0 + u * kWinStep, pre[u]);
+    }
+    __syncthreads();  // the ring is free: it holds the phase sums from here on
+    if (l0 == 0 && a.normalize) {  // series means: [2][phase][series] sums, added in phase order
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        red[q * kWinSeries + ls + c] = xs[c];
+        red[(kWinStep + q) * kWinSeries + ls + c] = xn[c];
+      }
+      __syncthreads();
+      if (tid < kWinSeries) {
+        double sx = 0.0, sn = 0.0;
+        for (int p = 0; p < kWinStep; ++p) {
+          sx += red[p * kWinSeries + tid];
+          sn += red[(kWinStep + p) * kWinSeries + tid];
+        }
+        meanv[tid] = (sx / sn) * (sx / sn);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int l = 0; l < kWinHalfLags; ++l)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[((h * kWinHalfLags + l) * kWinStep + q) * kWinSeries + 4 * g + c] = S[l][c];
+    __syncthreads();
+    // writers: one thread per (series, lag) of the group
+    if (tid < kWinSeries * kWinLags) {
+      const int c = tid % kWinSeries, l = tid / kWinSeries;
+      const int64_t sr = sb + c;
+      if (sr < a.n_series && l0 + l < a.n_lags) {
+        const double mean2 = a.normalize ? meanv[c] : 1.0;
+        double sum = 0.0;
+        for (int p = 0; p < kWinStep; ++p) sum += red[(l * kWinStep + p) * kWinSeries + c];
+        const int64_t Ll = L[l];
+        double n = (double)(P - 2 * Ll > 0 ? P - 2 * Ll : 0);  // every term counts (finite sum)
+        if (!isfinite(sum)) {
+          // a non-finite sample in the series: the terms again, in t order, without the non-finite ones
+          const float* xc = a.x + sr;
+          sum = 0.0;
+          n = 0.0;
+          for (int64_t t = Ll; t < P - Ll; ++t) {
+            const double dd = (double)xc[(t + Ll) * st] - 2.0 * (double)xc[t * st] + (double)xc[(t - Ll) * st];
+            if (isfinite(dd)) {
+              sum += dd * dd;
+              n += 1.0;
+            }
+          }
+        }
+        const double tau = (double)Ll * a.spacing;
+        a.out[sr * a.n_lags + l0 + l] = n > 0.0 && Ll >= 1 && 2 * Ll < P ? sum / n / (2.0 * tau * tau) / mean2 : NAN;
+      }
+    }
+    __syncthreads();  // the next lag group refills the ring
+  }
+}
+
 }  // namespace
 
 hipError_t launch_channel_average(const ChanAvgArgs& a, hipStream_t s) {
@@ -503,7 +670,14 @@ int64_t allan_part_doubles(int64_t n_points, int64_t n_series, int64_t point_str
 }
 
 hipError_t launch_allan(const AllanArgs& a, hipStream_t s) {
-  if (allan_cols(a.n_series, a.point_stride, a.series_stride)) {
+  int lmax = 0;
+  for (int l = 0; l < a.n_lags; ++l) lmax = a.lags[l] > lmax ? a.lags[l] : lmax;
+  const bool rows16 = reinterpret_cast<uintptr_t>(a.x) % 8 == 0 && a.point_stride % 2 == 0 && a.n_series % 2 == 0;
+  if (allan_cols(a.n_series, a.point_stride, a.series_stride) && lmax <= kWinMaxLag && rows16 &&
+      a.n_points < (int64_t(1) << 31)) {
+    hipLaunchKernelGGL(k_allan_window, dim3((unsigned)((a.n_series + kWinSeries - 1) / kWinSeries)),
+                       dim3(kWinThreads), 0, s, a);
+  } else if (allan_cols(a.n_series, a.point_stride, a.series_stride)) {
     hipLaunchKernelGGL(k_allan_cols, dim3((unsigned)((a.n_series + kColsSeries - 1) / kColsSeries)),
                        dim3(kColsSeries * kColsSlices), 0, s, a);
   } else {

@@ -161,6 +161,30 @@ def test_time_allan_variance_across_channels(env):
     assert np.all(np.isnan(got[:, -1]))  # 2 L >= n_points
 
 
+def test_time_allan_variance_window_form(env):
+    """TAV of side-by-side series with every lag at most 512 (the LDS-window form): the benchmark's lag set over
+    1800 1-s integrations, normalised, and a lag set of two groups with a non-multiple-of-32 channel count."""
+    torch, pk, dev = env
+    rng = np.random.default_rng(11)
+    T, C = 1800, 2048
+    x = (1 + 0.002 * np.sin(np.arange(T) / 97.0)[:, None] + 0.01 * rng.standard_normal((T, C))).astype(np.float32)
+    lags = [1, 2, 4, 8, 16, 64, 256, 512]
+    got = pk.allan(torch.from_numpy(x).to(dev), lags, spacing=1.0, normalize=True, axis=0).cpu().numpy()
+    rel_close(got, post.allan(x.T, lags, spacing=1.0, normalize=True), 1e-10)
+    # a partial last workgroup (998 series, the window form) and an odd series count (999, the column form),
+    # infinite samples (left out), lags in two groups of eight, and lags with one or no term
+    for C in (998, 999):
+        T = 777
+        x = (3 + 0.05 * rng.standard_normal((T, C))).astype(np.float32)
+        x[rng.integers(0, T, 200), rng.integers(0, C, 200)] = np.inf
+        lags = [1, 2, 3, 5, 8, 13, 21, 34, 55, 89, 144, 233, 377, 388, 389]
+        got = pk.allan(torch.from_numpy(x).to(dev), lags, spacing=0.5, axis=0).cpu().numpy()
+        ref = post.allan(x.T, lags, spacing=0.5)
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        ok = ~np.isnan(ref)
+        rel_close(got[ok], ref[ok], 1e-10)
+
+
 def test_time_allan_variance_ragged_with_flags(env):
     """TAV of side-by-side series: a channel count that is not a whole number of 64-series workgroups, a
     series length that does not split evenly over the time slices, NaN (flagged) samples, both with and
