@@ -308,15 +308,15 @@ __global__ void __launch_bounds__(UB * FB * L / 4) k_bw_rowpass(BwRowArgs a, int
     }
     __syncthreads();
   };
+  // unconditional prefetches (past the end they re-read the last frame): each batch waits only for its
+  // own loads, as in the forward row pass
   float2 va[1][8], vb[1][8];
   fetch(va, 0);
   for (int f0 = 0; f0 < n_frames; f0 += 2 * FB) {
-    const bool second = f0 + FB < n_frames;
-    if (second) fetch(vb, f0 + FB);
+    fetch(vb, f0 + FB);
     batch(va, f0);
-    if (!second) break;
-    if (f0 + 2 * FB < n_frames) fetch(va, f0 + 2 * FB);
-    batch(vb, f0 + FB);
+    fetch(va, f0 + 2 * FB);
+    if (f0 + FB < n_frames) batch(vb, f0 + FB);
   }
 }
 
@@ -354,23 +354,33 @@ __global__ void __launch_bounds__(L * COLS / 16) k_bw_colpass(BwColArgs a) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) acc[c][r] = 0.0;
 
-  for (int f = f_begin; f < f_end; ++f) {
-    // T'[f][p][m1][n2b ..]: the inverse transform's input, conjugated
+  // The next frame's T' and samples are fetched while the current one is transformed (unconditionally: the
+  // last frame fetches itself again, so every frame waits only for its own loads).
+  float4 zn[8];
+  ColLoader<BITS, FAST, V> ldn;
+  auto fetch = [&](int f) {
+    // T'[f][p][m1][n2b ..]: the inverse transform's input
     const float2* srcT = a.col.T + ((int64_t)f * a.col.P + p) * (int64_t)L * a.col.N2 + n2b;
-    float2 v[V][8];
 #pragma unroll
     for (int i = 0; i < 8 / R0; ++i)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        const float4 z = *reinterpret_cast<const float4*>(srcT + (int64_t)pin<L, R0>(ts, i, r) * a.col.N2);
-        v[0][i * R0 + r] = make_float2(z.x, -z.y);
-        v[1][i * R0 + r] = make_float2(z.z, -z.w);
-      }
+      for (int r = 0; r < R0; ++r)
+        zn[i * R0 + r] = *reinterpret_cast<const float4*>(srcT + (int64_t)pin<L, R0>(ts, i, r) * a.col.N2);
+    // samples x, y at n = (ts + r L/8) N2 + n2b + c
+    ldn.template fetch<L, 8>(a.col, (int64_t)f * a.col.hop, ts, n2b);
+  };
+  if (f_begin < f_end) fetch(f_begin);
+  for (int f = f_begin; f < f_end; ++f) {
+    float2 v[V][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      v[0][e] = make_float2(zn[e].x, -zn[e].y);  // conjugated
+      v[1][e] = make_float2(zn[e].z, -zn[e].w);
+    }
+    const ColLoader<BITS, FAST, V> ld = ldn;
+    fetch(min(f + 1, f_end - 1));
     col_chain<L, COLS, V, NB, 0>(v, ts, cv, tw, tile);
     if constexpr (NB == 2 && (SC::NPASS - 1) % 2 == 1) __syncthreads();
-    // samples x, y at n = (ts + r L/8) N2 + n2b + c
-    ColLoader<BITS, FAST, V> ld;
-    ld.template fetch<L, 8>(a.col, (int64_t)f * a.col.hop, ts, n2b);
     float2 xs[V][8];
     ld.template convert<L, 8>(xs, a.col, ts, n2b, sx, sy);
 #pragma unroll

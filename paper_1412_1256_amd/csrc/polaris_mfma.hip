@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
         const w4v v = {Y[h][i][0], Y[h][i][1], Y[h][i][2], Y[h][i][3]};
         *reinterpret_cast<w4v*>(&X[((h * 16 + 4 * g + i) * 16 + n) * XS + 4 * w]) = v;
       }
-    if (f + 1 < f_end) fetch(f + 1);
+    fetch(min(f + 1, f_end - 1));  // unconditional (the last frame fetches itself again): see the row pass
     __syncthreads();
     // ---- stage B and the four-step twiddle
     const uint32_t* Tf = a.T + ((int64_t)f * c.P + p) * (int64_t)N1 * N2;
@@ -337,6 +337,8 @@ __global__ void __launch_bounds__(256, 2) k_rowpass_mx(MxRowArgs a) {
           raw[r][h][jj] = *(const __attribute__((address_space(1))) uint32_t*)(
               fb + 4u * (uint32_t)(rows[r] * N2 + R * (4 * g + jj) + 16 * h + n));
   };
+  // prefetches are unconditional (past the end a wave fetches its last frame again), so each frame waits
+  // only for its own loads and the next frame's stay in flight
   if (w < a.n_frames) fetch(w);
   for (int f = w; f < a.n_frames; f += NW) {
     uint32_t cur[2][H][4];
@@ -346,7 +348,7 @@ __global__ void __launch_bounds__(256, 2) k_rowpass_mx(MxRowArgs a) {
       for (int h = 0; h < H; ++h)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) cur[r][h][jj] = raw[r][h][jj];
-    if (f + NW < a.n_frames) fetch(f + NW);
+    fetch(f + NW < a.n_frames ? f + NW : f);
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       f4v o[H][2];
