@@ -53,8 +53,8 @@ def parse():
                     help="only the headline workload (for profiler runs): no other sections, no CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=6.0, help="minimum oracle time (whole integrations)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
-    ap.add_argument("--only", choices=["short_transforms", "post_reduction", "table1_modes", "overlap_form", "fwd_bwd",
-                                       "precision_form"],
+    ap.add_argument("--only", choices=["short_transforms", "long_transforms", "post_reduction", "table1_modes",
+                                       "overlap_form", "fwd_bwd", "precision_form", "batching_form"],
                     help="run one further section alone and print it (for profiler runs)")
     return ap.parse_args()
 
@@ -85,6 +85,8 @@ def kernel_bytes(kind: str, inst: dict, frames: int) -> float:
         return frames * N * S * b / 8 + frames * P * N * 8 + win
     if kind == "rowpass":   # intermediate read once + FP64 accumulators written (first call: no read)
         return frames * P * N * 8 + P * C * 32
+    if kind == "rowpass_stokes":  # the row pass with the Stokes epilogue: also writes FP32 I, Q, U, V
+        return frames * P * N * 8 + P * C * 32 + P * C * 16
     if kind == "stokes":    # FP64 accumulators read + FP32 I, Q, U, V written
         return P * C * 32 + P * C * 16
     if kind == "spectra":
@@ -96,7 +98,7 @@ def kernel_bytes(kind: str, inst: dict, frames: int) -> float:
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1412_1256_amd", "csrc", f) for f in
                   ("polaris_kernels.hip", "polaris_device.h", "polaris_internal.h")]
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_paper_2e18.txt")
-KIND_OF = {"k_colpass": "colpass", "k_rowpass": "rowpass", "k_output": "stokes"}
+KIND_OF = {"k_colpass": "colpass", "k_rowpass": "rowpass", "k_rowpass_stokes": "rowpass", "k_output": "stokes"}
 
 
 def counter_traffic() -> dict:
@@ -233,6 +235,28 @@ def time_steps(torch, dev, fn, steps, warmup, warmup_s=0.05):
     return (time.perf_counter() - t0) / steps
 
 
+def pipelined_time(torch, dev, plans, run_on, steps, warmup_s=0.05):
+    """Seconds per integration with len(plans) integrations in flight: integration i is run_on(plans[i % d], i),
+    enqueued on that plan's own stream (each plan holds its own workspace, so one integration's column pass
+    overlaps the previous one's row pass)."""
+    d = len(plans)
+
+    def run(n):
+        for i in range(n):
+            run_on(plans[i % d], i)
+
+    run(2 * d)
+    torch.cuda.synchronize(dev)
+    t_end = time.perf_counter() + warmup_s
+    while time.perf_counter() < t_end:
+        run(2 * d)
+        torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize(dev)
+    return (time.perf_counter() - t0) / steps
+
+
 def differentiation_form(pk, torch, dev, steps, warmup):
     """fwd+bwd vs plain on the differentiation workload: 2 int8 pols, 2^16-point frames, 128 frames, learnable
     per-channel gains, leakage terms and a 64-tap window; the backward recomputes every frame."""
@@ -304,6 +328,7 @@ def precision_form(pk, torch, dev, steps, warmup, with_oracle=True):
     res = {"workload": "4 int8 streams (2 bands x 2 pols), 2^18-pt rect frames, 610 frames (9.99 s), Stokes of "
                        "pairs (0,2), (1,3)", "samples_per_step": samples}
     out = torch.empty((P, 4, N // 2), dtype=torch.float32, device=dev)
+    packed2 = packed.clone()
     for prec, accum in (("fp32", "fp64"), ("fp16", "kahan32"), ("bf16", "kahan32")):
         plan = pk.Plan([pk.Instance.from_synth(inst, precision=prec, accum=accum, chunk_frames=128)], device=dev)
 
@@ -341,8 +366,27 @@ def precision_form(pk, torch, dev, steps, warmup, with_oracle=True):
             got = out.cpu().numpy().astype(np.float64)
             e = np.max(np.abs(got - ref) / ref[:, 0:1, :], axis=2)
             r["err_vs_oracle_IQUV"] = [float(v) for v in e.max(axis=0)]
+        # two integrations in flight: a second plan on its own stream takes every other integration, from
+        # its own copy of the input
+        streams = [torch.cuda.Stream(dev) for _ in range(2)]
+        plans2 = [pk.Plan([pk.Instance.from_synth(inst, precision=prec, accum=accum, chunk_frames=128)],
+                          device=dev, stream=st) for st in streams]
+        bufs, outs2 = [packed, packed2], [out, torch.empty_like(out)]
+
+        def run_on(pl, i):
+            pl.reset()
+            pl.accumulate(bufs[i % 2])
+            pl.stokes(out=outs2[i % 2])
+
+        t2 = pipelined_time(torch, dev, plans2, run_on, max(2, 2 * steps))
+        r["depth2"] = {"us_per_step": t2 * 1e6, "Gsamples_per_s": samples / t2 / 1e9,
+                       "x_realtime": F * N / SAMPLE_RATE / t2,
+                       "path_GBps": (kb("colpass", inst, F) + kb("rowpass", inst, F) + P * (N // 2) * 48) / t2 / 1e9}
+        if prec != "fp32":
+            r["depth2"]["mfma_tflops"] = 1024.0 * N * F * P / t2 / 1e12
+            r["depth2"]["mfma_frac_dense_peak"] = r["depth2"]["mfma_tflops"] / MFMA_16BIT_PEAK_TFLOPS
         res[f"{prec}_{accum}"] = r
-        del plan
+        del plan, plans2
     return res
 
 
@@ -401,7 +445,23 @@ def batching_form(pk, torch, dev, reps):
     t_grp = timed(run_grouped)
     grp.graph_capture(run_grouped)
     t_graph = timed(grp.graph_replay)
-    del grp
+    # two integrations in flight: a second grouped plan on its own stream, with its own copies of the inputs
+    # and outputs, replays its own graph; the two graphs alternate
+    side2 = torch.cuda.Stream(dev)
+    with torch.cuda.stream(side2):
+        packed2 = [b.clone() for b in packed]
+        outs2 = [torch.empty_like(o) for o in outs]
+        grp2 = pk.Plan(insts, device=dev, stream=side2)
+    side2.synchronize()
+
+    def run_grouped2():
+        grp2.reset()
+        grp2.accumulate(packed2)
+        grp2.stokes_all(outs2)
+
+    grp2.graph_capture(run_grouped2)
+    t_graph2 = pipelined_time(torch, dev, [grp, grp2], lambda pl, i: pl.graph_replay(), 2 * reps)
+    del grp, grp2, packed2, outs2
     # the same with every instance on its autotuned schedule (tuned alone, one shape at a time)
     from paper_1412_1256_amd import autotune
     cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "polaris_bench_batch_tune.json")
@@ -423,6 +483,8 @@ def batching_form(pk, torch, dev, reps):
             "samples_per_integration": samples, "separate_plans_us": t_sep * 1e6, "grouped_us": t_grp * 1e6,
             "grouped_graph_us": t_graph * 1e6, "grouped_graph_tuned_us": t_tuned * 1e6,
             "Gsamples_per_s_grouped_graph": samples / t_graph / 1e9,
+            "grouped_graph_depth2_us": t_graph2 * 1e6,
+            "Gsamples_per_s_grouped_graph_depth2": samples / t_graph2 / 1e9,
             "Gsamples_per_s_grouped_graph_tuned": samples / t_tuned / 1e9,
             "x_realtime_tuned": samples / 2 / SAMPLE_RATE / t_tuned,
             "speedup_grouped_vs_separate": t_sep / t_grp, "speedup_graph_vs_separate": t_sep / t_graph,
@@ -506,6 +568,20 @@ def _ring_integrations(pk, torch, dev, inst, ring, steps, warmup=3):
     prof = plan.profile_read()
     plan.profile_enable(False)
     kern = {k: {"launches": n / steps, "avg_us": ms / n * 1e3} for k, (ms, n) in prof.items()}
+    # two integrations in flight (a second plan on its own stream with its own output takes every other one)
+    st2 = torch.cuda.Stream(dev)
+    with torch.cuda.stream(st2):
+        plan2 = pk.Plan([pk.Instance.from_synth(inst)], device=dev, stream=st2)
+        out2 = torch.empty_like(out)
+    st2.synchronize()
+
+    def run_on(pl, i):
+        pl.reset()
+        pl.accumulate(ring[i % len(ring)])
+        pl.stokes(psi=0.25, out=out if pl is plan else out2)
+
+    kern["depth2_us"] = pipelined_time(torch, dev, [plan, plan2], run_on, max(4, steps)) * 1e6
+    del plan2
     return t, kern, plan
 
 
@@ -524,6 +600,8 @@ def overlap_form(pk, torch, dev, inst, ring, steps):
             if k in kern:
                 r[f"{k}_us"] = kern[k]["avg_us"]
                 r[f"{k}_launches"] = kern[k]["launches"]
+        r["depth2_us"] = kern["depth2_us"]
+        r["depth2_Gsamples_per_s"] = inst["n_samples"] * 2 / (kern["depth2_us"] * 1e-6) / 1e9
         # column pass: each frame's input bytes (overlapped samples are read by both frames) + intermediate
         cp = kernel_bytes("colpass", d, frames)
         r["colpass_GBps_frame_bytes"] = cp / (r["colpass_us"] * 1e-6) / 1e9 if "colpass_us" in r else None
@@ -546,8 +624,32 @@ def modes_form(pk, torch, dev, steps, ring_n):
         res[mode] = {"bits": d["bits"], "fft_len": d["fft_len"], "n_streams": 4, "frames": d["n_frames"],
                      "data_seconds": seconds, "us": t * 1e6,
                      "Gsamples_per_s": d["n_samples"] * 4 / t / 1e9, "x_realtime": seconds / t,
-                     "kernels_us": {k: v["avg_us"] for k, v in kern.items()}}
+                     "depth2_us": kern["depth2_us"],
+                     "depth2_Gsamples_per_s": d["n_samples"] * 4 / (kern["depth2_us"] * 1e-6) / 1e9,
+                     "kernels_us": {k: v["avg_us"] for k, v in kern.items() if k != "depth2_us"}}
         del ring, packed
+    return res
+
+
+def long_form(pk, torch, dev, steps):
+    """Long transforms (two streams, 2- and 8-bit, 2^19 and 2^20 points, 2^25 samples per stream per
+    integration, streamed from a ring of HBM-resident buffers larger than the last-level cache): whole
+    integrations with one and with two integrations in flight, per-kernel times from the one-plan run."""
+    import synth
+    res = {}
+    for m in (19, 20):
+        N = 1 << m
+        for bits in (2, 8):
+            d = synth.make_correlated_noise(bits, 0.3, N, (1 << 25) // N, seed_extra=m + bits)
+            packed = torch.from_numpy(d["packed"]).to(dev)
+            ring = [packed] + [packed.clone() for _ in range(max(1, (512 << 20) // packed.numel()) - 1)]
+            t, kern, plan = _ring_integrations(pk, torch, dev, d, ring, steps)
+            samples = d["n_samples"] * 2
+            res[f"2^{m}_{bits}bit"] = {
+                "frames": d["n_frames"], "us": t * 1e6, "Gsamples_per_s": samples / t / 1e9,
+                "depth2_us": kern["depth2_us"], "depth2_Gsamples_per_s": samples / (kern["depth2_us"] * 1e-6) / 1e9,
+                "kernels_us": {k: v["avg_us"] for k, v in kern.items() if k != "depth2_us"}}
+            del ring, packed, plan
     return res
 
 
@@ -650,8 +752,11 @@ def main():
 
     pk.lib()  # fail loudly when the HIP library is missing
     dev = torch.device("cuda:0")
-    if args.only in ("short_transforms", "post_reduction", "table1_modes", "fwd_bwd", "precision_form"):
+    if args.only in ("short_transforms", "long_transforms", "post_reduction", "table1_modes", "fwd_bwd",
+                     "precision_form", "batching_form"):
         fn = {"short_transforms": lambda: short_form(pk, torch, dev, args.steps),
+              "long_transforms": lambda: long_form(pk, torch, dev, args.steps),
+              "batching_form": lambda: batching_form(pk, torch, dev, args.steps),
               "post_reduction": lambda: post_form(pk, torch, dev, args.steps),
               "table1_modes": lambda: modes_form(pk, torch, dev, args.steps, args.ring),
               "fwd_bwd": lambda: differentiation_form(pk, torch, dev, args.steps, 2),
@@ -760,9 +865,12 @@ def main():
     prof = plan.profile_read()
     plan.profile_enable(False)
     kernels = {}
+    # one-call integration: the last row-pass launch of a step also writes the Stokes spectra, and no
+    # Stokes pass runs (its accumulator read is not part of the path)
+    fused = "stokes" not in prof
     for k, (ms, n) in prof.items():
         avg_s = ms / n / 1e3
-        nbytes = kernel_bytes(k, inst, F)
+        nbytes = kernel_bytes("rowpass_stokes" if fused and k == "rowpass" else k, inst, F)
         kernels[k] = {"launches_per_step": n / args.steps, "avg_us": avg_s * 1e6,
                       "alg_bytes": nbytes, "GBps": nbytes / avg_s / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches_per_step"])
@@ -774,7 +882,8 @@ def main():
 
     value = samples / dt / 1e9
     nominal_flop = S * F * 5 * N * math.log2(N)      # 5 N log2 N per N-point real frame per stream
-    path_bytes = sum(kernel_bytes(k, inst, F) for k in ("colpass", "rowpass", "stokes"))
+    path_bytes = sum(kernel_bytes(k, inst, F)
+                     for k in (("colpass", "rowpass_stokes") if fused else ("colpass", "rowpass", "stokes")))
     out = {
         "metric": METRIC, "value": value, "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -813,6 +922,7 @@ def main():
     out["table1_modes"] = modes_form(pk, torch, dev, max(8, args.steps // 2), args.ring)
     out["post_reduction"] = post_form(pk, torch, dev, 10)
     out["short_transforms"] = short_form(pk, torch, dev, max(5, args.steps // 4))
+    out["long_transforms"] = long_form(pk, torch, dev, max(5, args.steps // 4))
     if not args.no_batching:
         out["batching_form"] = batching_form(pk, torch, dev, max(3, args.steps // 10))
     if not args.no_precision:

@@ -716,6 +716,7 @@ ps_status accumulate_mx(ps_plan_t plan, Inst& I, const ps::ColArgs& ca) {
   m.mode = 0;
   if (c.bits == 8 && c.n_streams == 2 && c.n_pairs == 1 && c.pair_x[0] == 0 && c.pair_y[0] == 1) m.mode = 1;
   if (c.bits == 8 && c.n_streams == 4) m.mode = 2;
+  if (ca.in_bytes == 0) m.mode = 0;  // the word paths address the launch's input with 32-bit offsets
   const int n_blocks = (int)(groups * per_frame);
   hipError_t e = timed(plan, PS_KERNEL_COLPASS, [&](const ps::Launch& l) {
     return ps::launch_colpass_mx((int)I.N1, c.precision, c.bits, m, n_blocks, l);

@@ -36,16 +36,17 @@ typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef uint32_t w4v __attribute__((ext_vector_type(4)));
 
-// (re, im) rounded to nearest even in the 16-bit format, re in the low half
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+
+// (re, im) rounded to nearest even in the 16-bit format, re in the low half (one packed conversion on
+// gfx950: v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32)
 template <int PREC>
 __device__ __forceinline__ uint32_t pk(float re, float im) {
-  if constexpr (PREC == PS_PREC_FP16) {
-    const _Float16 a = (_Float16)re, b = (_Float16)im;
-    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
-  } else {
-    const __bf16 a = (__bf16)re, b = (__bf16)im;
-    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
-  }
+  const f2v v = {re, im};
+  if constexpr (PREC == PS_PREC_FP16) return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, h2v));
+  else return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, b2v));
 }
 
 template <int PREC>
@@ -101,10 +102,10 @@ __device__ __forceinline__ void wave_sync() {
 template <int BITS, int MODE>
 struct MxIn {
   uint32_t raw;
-  // fb: wave-uniform base of the frame's samples (bytes); off: this sample's time index within the frame
-  __device__ __forceinline__ void fetch(gbytes fb, uint32_t off) {
-    if constexpr (MODE == 1) raw = *(const __attribute__((address_space(1))) uint16_t*)(fb + 2u * off);
-    else if constexpr (MODE == 2) raw = *(const __attribute__((address_space(1))) uint32_t*)(fb + 4u * off);
+  // buffer load of the launch's input: voff the lane's byte offset, soff the wave-uniform byte offset
+  __device__ __forceinline__ void fetch(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+    if constexpr (MODE == 1) raw = __builtin_amdgcn_raw_buffer_load_b16(rs, voff, soff, 0);
+    else if constexpr (MODE == 2) raw = __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0);
     else raw = 0;
   }
   __device__ __forceinline__ float2 level(const ColArgs& c, int64_t t, int sx, int sy) const {
@@ -187,18 +188,19 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
   MxIn<BITS, MODE> in[4][H][4];  // [j][b_hi][point a = 4g + jj]
   constexpr int BPT = MODE == 1 ? 2 : 4;  // bytes per time step on the word paths
   // time index of element (j, h, jj) within the frame: lane_t + (R jj + 4w + j + 16h) N2
+  // the word paths read through a buffer resource over the launch's input (fewer than 2^31 bytes): the
+  // frame and element offsets are wave-uniform (scalar registers), the lane's offset one 32-bit register
+  const __amdgpu_buffer_rsrc_t rin = buffer_rsrc(c.in, c.in_bytes);
   auto fetch = [&](int f) {
     if constexpr (MODE != 0) {
+      const uint32_t fo = ((uint32_t)__builtin_amdgcn_readfirstlane(f) * (uint32_t)c.hop + 4u * w * N2) * BPT;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int h = 0; h < H; ++h)
 #pragma unroll
-          for (int jj = 0; jj < 4; ++jj) {
-            const gbytes fb = uniform_gptr(
-                c.in + ((int64_t)f * c.hop + (int64_t)(R * jj + 4 * w + j + 16 * h) * N2) * BPT);
-            in[j][h][jj].fetch(fb, lane_t);
-          }
+          for (int jj = 0; jj < 4; ++jj)
+            in[j][h][jj].fetch(rin, lane_t * BPT, fo + (uint32_t)((R * jj + j + 16 * h) * N2 * BPT));
     }
   };
   if (f_begin < f_end) fetch(f_begin);
@@ -253,10 +255,14 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
         const w4v v = {Y[h][i][0], Y[h][i][1], Y[h][i][2], Y[h][i][3]};
         *reinterpret_cast<w4v*>(&X[((h * 16 + 4 * g + i) * 16 + n) * XS + 4 * w]) = v;
       }
-    fetch(min(f + 1, f_end - 1));  // unconditional (the last frame fetches itself again): see the row pass
+    // the next frame's words: issued here, not earlier, so they do not hold registers through stage A;
+    // unconditional (the last frame fetches itself again), see the row pass
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(min(f + 1, f_end - 1));
     __syncthreads();
     // ---- stage B and the four-step twiddle
-    const uint32_t* Tf = a.T + ((int64_t)f * c.P + p) * (int64_t)N1 * N2;
+    const uint32_t* Tf = a.T + ((int64_t)__builtin_amdgcn_readfirstlane(f) * c.P + p) * (int64_t)N1 * N2;
+    const __amdgpu_buffer_rsrc_t rout = buffer_rsrc(Tf, (uint32_t)(N1 * N2 * 4));
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int kap = w + 4 * t;
@@ -268,9 +274,9 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           // k1 = kap + 16 (H (4g + i) + h): lane part 16 H 4g, uniform part kap + 16 (H i + h)
-          const gbytes ob = uniform_gptr(reinterpret_cast<const uint8_t*>(Tf + (kap + 16 * (H * i + h)) * N2));
           const float2 v = cmul(make_float2(o[0][i], o[1][i]), cmul(t1[t], t2[h][i]));
-          *(__attribute__((address_space(1))) uint32_t*)(ob + lane_o) = pk<PREC>(v.x, v.y);
+          __builtin_amdgcn_raw_buffer_store_b32(pk<PREC>(v.x, v.y), rout, lane_o,
+                                                (uint32_t)((kap + 16 * (H * i + h)) * N2 * 4), 0);
         }
       }
     }
@@ -326,16 +332,19 @@ __global__ void __launch_bounds__(256, 2) k_rowpass_mx(MxRowArgs a) {
     for (int k = 0; k < 4; ++k) sum[m][k] = cmp[m][k] = 0;
 
   uint32_t raw[2][H][4];
+  // buffer loads over one frame of the pair: the row and element offsets are wave-uniform, the lane's
+  // offset (column R (4g) + n) one 32-bit register
+  const uint32_t lane_c = (uint32_t)(R * 4 * g + n) * 4u;
   auto fetch = [&](int f) {
-    const gbytes fb = uniform_gptr(reinterpret_cast<const uint8_t*>(a.T + ((int64_t)f * a.P + p) * N1 * N2));
+    const uint32_t* Tf = a.T + ((int64_t)__builtin_amdgcn_readfirstlane(f) * a.P + p) * N1 * N2;
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(Tf, (uint32_t)(N1 * N2 * 4));
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int h = 0; h < H; ++h)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
-          raw[r][h][jj] = *(const __attribute__((address_space(1))) uint32_t*)(
-              fb + 4u * (uint32_t)(rows[r] * N2 + R * (4 * g + jj) + 16 * h + n));
+          raw[r][h][jj] = __builtin_amdgcn_raw_buffer_load_b32(rs, lane_c, (uint32_t)(rows[r] * N2 + R * jj + 16 * h) * 4u, 0);
   };
   // prefetches are unconditional (past the end a wave fetches its last frame again), so each frame waits
   // only for its own loads and the next frame's stay in flight
