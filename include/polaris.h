@@ -263,8 +263,11 @@ ps_status ps_graph_launch(ps_plan_t plan);
 
 /* Gradient of a real loss L(iquv) with respect to the gains, leakage terms and window taps, given
  * dL_diquv_dev [n_pairs][4][C] floats.  Needs the current integration (the forward's accumulators,
- * not reset) and the same packed input (n_samples per stream, all frames of the integration); frames are
- * transformed again instead of being stored.  PS_ERR_STATE if the frame count does not match. */
+ * not reset) and the same packed input (n_samples per stream, all frames of the integration).  When the
+ * integration was one ps_accumulate call of at most chunk_frames frames and nothing has written the
+ * workspace's inter-pass buffer since (no other accumulate on the plan, no graph replay), its column-pass
+ * output is used as it stands; otherwise the frames are transformed again.  The call overwrites that buffer.
+ * PS_ERR_STATE if the frame count does not match. */
 ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed_dev, int64_t n_samples,
                                 const ps_cal* cal, const float* dL_diquv_dev, const ps_cal_grad* grad);
 

@@ -427,6 +427,9 @@ class Plan:
 
     def set_window_taps(self, taps, inst: int = 0):
         t = self._as_f32(taps)
+        n = self.instances[inst].n_taps
+        if n > 0 and t.numel() != n:  # (an instance without a taps window is refused by the library)
+            raise ValueError(f"instance {inst} has {n} window taps, got {t.numel()}")
         _check(lib().ps_set_window_taps(self._h, inst, _ptr(t)))
         self._taps_keepalive = t
 

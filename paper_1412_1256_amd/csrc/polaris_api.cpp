@@ -69,7 +69,7 @@ struct Inst {
   size_t off_tw_col = 0, off_tw_row = 0, off_tw_lo = 0, off_win = 0, off_taps = 0, off_sumw2 = 0;
   size_t off_T = 0, off_acc = 0, end = 0;
   // differentiation form: window partial sums, Gb(A), per-unit partials, normaliser terms, partial dL/dw
-  size_t off_wpart = 0, off_ga = 0, off_red = 0, off_norm = 0, off_dw = 0;
+  size_t off_wpart = 0, off_ga = 0, off_red = 0, off_norm = 0, off_dw = 0, off_tpart = 0;
   bool taps() const { return cfg.window == PS_WIN_TAPS; }
   std::vector<float> tw_col, tw_row, tw_lo, win, ones;
   // schedule (autotuner's choices): columns per column-pass workgroup, frames per row-pass batch,
@@ -151,7 +151,15 @@ struct ps_plan_s {
   };
   std::vector<InstState> graph_state;
   uint64_t gen_counter = 0;
-  void touch(Inst& I) { I.gen = ++gen_counter; }
+  // The inter-pass buffer still holds the column-pass output of instance t_inst's whole integration
+  // (generation t_gen, every frame in one launch) when t_inst >= 0: the adjoint then uses it instead of
+  // recomputing the column pass.  Any other write of the buffer, or change of the integration, clears it.
+  int t_inst = -1;
+  uint64_t t_gen = 0;
+  void touch(Inst& I) {
+    I.gen = ++gen_counter;
+    t_inst = -1;
+  }
   ~ps_plan_s() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (acc_desc.host) (void)hipHostFree(acc_desc.host);
@@ -574,6 +582,7 @@ void append_bytes(std::vector<unsigned char>& v, const T* p, size_t n) {
 // launch per N2, per chunk round; each launch has one workgroup per tile of all its instances.
 ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, const int64_t* n_samples,
                              std::vector<char>& done) {
+  plan->t_inst = -1;
   int64_t rounds = 0;
   for (size_t i = 0; i < plan->inst.size(); ++i) {
     const Inst& I = plan->inst[i];
@@ -698,6 +707,7 @@ ps_status accumulate_grouped(ps_plan_t plan, const void* const* packed_dev, cons
 // Precision form of one chunk: 16-bit column pass (16 columns per workgroup, about two workgroups per CU) and
 // 16-bit row pass with FP64 or compensated FP32 sums (one workgroup per unit and pair).
 ps_status accumulate_mx(ps_plan_t plan, Inst& I, const ps::ColArgs& ca) {
+  plan->t_inst = -1;
   ps::MxColArgs m{};
   m.col = ca;
   m.col.n_colblk = (int32_t)(I.N2 / 16);
@@ -774,6 +784,7 @@ ps::OutArgs stokes_args(ps_plan_t plan, const Inst& I, int64_t n_frames, const p
 // pending accumulate-and-Stokes request that the instance can take (one accumulator slot, FP32 four-step
 // passes), the last chunk's row pass also writes the Stokes spectra.
 ps_status run_frames(ps_plan_t plan, Inst& I, const uint8_t* base, int64_t F, bool fuse = false) {
+  plan->t_inst = -1;
   if (I.fused && !I.hist_on) {
     // single pass: no inter-pass buffer, so one launch takes up to 2^28 frames
     constexpr int64_t kMaxFused = int64_t(1) << 28;
@@ -819,6 +830,10 @@ ps_status run_frames(ps_plan_t plan, Inst& I, const uint8_t* base, int64_t F, bo
     hipError_t e = timed(plan, PS_KERNEL_COLPASS,
                          [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, I.cols, I.cfg.bits, mode, ca, l); });
     if (e != hipSuccess) return hip_fail(e, "column pass launch");
+    if (!plan->capturing && I.n_frames == 0 && f0 == 0 && nf == F) {  // the whole integration in one launch
+      plan->t_inst = (int)(&I - plan->inst.data());
+      plan->t_gen = I.gen;
+    }
     const ps::RowArgs ra = row_args(plan, I, nf, I.n_frames);
     const bool fuse_now = fuse && I.fuse_iquv && I.can_fuse() && f0 + nf == F;
     ps::OutArgs o{};
@@ -968,6 +983,7 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
       I.off_wpart = off; off = align_up(off + (size_t)ps::window_taps_blocks(I.N) * sizeof(double));
       I.off_ga = off; off = align_up(off + P * (size_t)I.C * 4 * sizeof(float));
       I.off_dw = off; off = align_up(off + (size_t)ps::kMaxBwGroups * (size_t)I.N * sizeof(double));
+      I.off_tpart = off; off = align_up(off + (size_t)ps::bw_taps_part_doubles(I.N) * sizeof(double));
     }
     I.end = off;
   }
@@ -996,6 +1012,7 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
 }
 
 ps_status ps_bind(ps_plan_t plan, void* workspace_dev, size_t bytes, void* hip_stream) {
+  plan->t_inst = -1;
   ps_status st = check_plan(plan, false);
   if (st != PS_OK) return st;
   if (!workspace_dev) return fail(PS_ERR_WORKSPACE, "null workspace");
@@ -1423,13 +1440,18 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
   ca.g_a = want_taps ? ws_ptr<float>(plan, I.off_ga) : nullptr;
   ca.red = ws_ptr<double>(plan, I.off_red);
   ca.norm = ws_ptr<double>(plan, I.off_norm);
-  hipError_t e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_bw_channel((int)I.N2, ca, l); });
+  // with the one-pass tap gradient, that kernel also reduces the channel kernel's unit partials
+  const bool taps_reduce = want_taps && ps::bw_taps_block_form(I.N, I.cfg.n_taps);
+  hipError_t e = timed(plan, PS_KERNEL_BACKWARD,
+                       [&](const ps::Launch& l) { return ps::launch_bw_channel((int)I.N2, ca, l, !taps_reduce); });
   if (e != hipSuccess) return hip_fail(e, "backward channel launch");
   if (!want_taps) return PS_OK;
 
   const int64_t F = I.n_frames;
   const uint8_t* base = static_cast<const uint8_t*>(packed_dev);
   int groups_used = 0;
+  // the forward's column-pass output of this integration, if the inter-pass buffer still holds all of it
+  const bool reuse_T = !plan->capturing && plan->t_inst == inst && plan->t_gen == I.gen && F <= I.chunk;
   for (int64_t f0 = 0; f0 < F; f0 += I.chunk) {
     const int nf = (int)((F - f0) < I.chunk ? (F - f0) : I.chunk);
     ps::ColArgs col{};
@@ -1462,8 +1484,11 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
     col.tw_lo = ws_ptr<float2>(plan, I.off_tw_lo);
     col.lo_bits = I.m2;
     col.T = ws_ptr<float2>(plan, I.off_T);
-    e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, ps::colpass_cols((int)I.N1), I.cfg.bits, mode, col, l); });
-    if (e != hipSuccess) return hip_fail(e, "backward forward-recompute launch");
+    if (!reuse_T) {
+      e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_colpass((int)I.N1, ps::colpass_cols((int)I.N1), I.cfg.bits, mode, col, l); });
+      if (e != hipSuccess) return hip_fail(e, "backward forward-recompute launch");
+    }
+    plan->t_inst = -1;  // the backward row pass writes T' over T
     ps::BwRowArgs ra{};
     ra.T = col.T;
     ra.N1 = (int32_t)I.N1;
@@ -1506,6 +1531,10 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
   ta.norm = ca.norm;
   ta.P = I.cfg.n_pairs;
   ta.d_taps = grad->d_taps;
+  ta.part = ws_ptr<double>(plan, I.off_tpart);
+  ta.red = ca.red;
+  ta.U = (int32_t)(I.N1 / 2);
+  ta.d_dterms = taps_reduce ? grad->d_dterms : nullptr;
   e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_bw_taps(ta, l); });
   if (e != hipSuccess) return hip_fail(e, "tap gradient launch");
   return PS_OK;

@@ -176,18 +176,28 @@ __global__ void __launch_bounds__(L) k_bw_channel(BwChanArgs a) {
   if (s < kBwRed) a.red[((int64_t)p * U + u) * kBwRed + s] = red[s][0];
 }
 
-// per pair: leakage gradients and the normaliser term, summing the unit partials in unit order
+// per pair: leakage gradients and the normaliser term.  Lane t sums the units t, t + 64, ... (in order), then
+// the 64 lanes' sums are added pairwise in a fixed tree, so the result does not depend on timing.
 __global__ void __launch_bounds__(64) k_bw_reduce(BwChanArgs a) {
-  const int U = a.N1 / 2, p = (int)blockIdx.x;
-  if (threadIdx.x < kBwRed) {
-    double v = 0.0;
-#pragma unroll 8
-    for (int u = 0; u < U; ++u) v += a.red[((int64_t)p * U + u) * kBwRed + threadIdx.x];  // loads 8 at a time
-    if (threadIdx.x < 4) {
-      if (a.d_dterms) a.d_dterms[4 * p + threadIdx.x] = (float)v;
-    } else {
-      a.norm[p] = v;
-    }
+  __shared__ double sh[kBwRed][64];
+  const int U = a.N1 / 2, p = (int)blockIdx.x, t = (int)threadIdx.x;
+  double v[kBwRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int u = t; u < U; u += 64)
+#pragma unroll
+    for (int r = 0; r < kBwRed; ++r) v[r] += a.red[((int64_t)p * U + u) * kBwRed + r];
+#pragma unroll
+  for (int r = 0; r < kBwRed; ++r) sh[r][t] = v[r];
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if (t < h)
+#pragma unroll
+      for (int r = 0; r < kBwRed; ++r) sh[r][t] += sh[r][t + h];
+    __syncthreads();
+  }
+  if (t < 4) {
+    if (a.d_dterms) a.d_dterms[4 * p + t] = (float)sh[t][0];
+  } else if (t == 4) {
+    a.norm[p] = sh[4][0];
   }
 }
 
@@ -420,6 +430,94 @@ __global__ void __launch_bounds__(256) k_bw_dw_sum(double* __restrict__ dw, int 
   dw[n] = s;
 }
 
+// One pass over dL/dw in blocks of kTapThreads samples: each sample's dL/dw (the groups' partials added in
+// group order, plus the normaliser term -2 w nt / s) split between the two taps around it (weights 1 - t
+// and t: the window is linear between taps), summed per tap within the block by a fixed tree.  The
+// dL/dw part and the window part are summed apart and combined once nt (the sum of the channel kernel's
+// per-unit normaliser partials, also reduced here) is known.  Block b writes part[b][i], the sum for tap
+// j_lo(b) + i (j_lo(b): the tap segment of its first sample); block 0 also writes the leakage gradients.
+// The host launches this form only when a block's samples touch fewer than kTapSpan taps.
+constexpr int kTapSpan = 8;
+constexpr int kTapRows = 2 * kTapSpan + 1;
+
+// tap segment of sample n (as tap_position, in integer arithmetic: both give floor(n (T-1) / (N-1)))
+__device__ __forceinline__ int tap_segment(int64_t n, int64_t N, int T) {
+  const int64_t j = n * (int64_t)(T - 1) / (N - 1);
+  return j > T - 2 ? T - 2 : (int)j;
+}
+
+template <int ROWS>
+__device__ __forceinline__ void tree_sum(double (&red)[ROWS][kTapThreads], int tid) {
+  __syncthreads();
+  for (int h = kTapThreads / 2; h > 0; h >>= 1) {
+    if (tid < h)
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) red[i][tid] += red[i][tid + h];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kTapThreads) k_bw_taps_block(BwTapArgs a) {
+  __shared__ double red[kTapRows][kTapThreads];
+  const int tid = (int)threadIdx.x, T = a.n_taps;
+  const int64_t n0 = (int64_t)blockIdx.x * kTapThreads;
+  const int j_lo = tap_segment(n0, a.N, T);
+#pragma unroll
+  for (int i = 0; i < kTapRows; ++i) red[i][tid] = 0.0;
+  double v = 0.0;  // normaliser partials: thread tid takes units tid, tid + 256, ... of every pair
+  for (int p = 0; p < a.P; ++p)
+    for (int u = tid; u < a.U; u += kTapThreads) v += a.red[((int64_t)p * a.U + u) * kBwRed + 4];
+  red[2 * kTapSpan][tid] = v;
+  const int64_t n = n0 + tid;
+  if (n < a.N) {
+    int jn;
+    double t;
+    tap_position(n, a.N, T, jn, t);
+    double dw = 0.0;
+#pragma unroll 8
+    for (int g = 0; g < a.groups; ++g) dw += a.dw[(int64_t)g * a.N + n];
+    const double w = (1.0 - t) * (double)a.taps[jn] + t * (double)a.taps[jn + 1];
+    red[jn - j_lo][tid] = (1.0 - t) * dw;
+    red[jn + 1 - j_lo][tid] = t * dw;
+    red[kTapSpan + jn - j_lo][tid] = (1.0 - t) * w;
+    red[kTapSpan + jn + 1 - j_lo][tid] = t * w;
+  }
+  tree_sum(red, tid);
+  if (tid < kTapSpan) {
+    const double coef = -2.0 * red[2 * kTapSpan][0] / a.sumw2[0];
+    a.part[(int64_t)blockIdx.x * kTapSpan + tid] = red[tid][0] + coef * red[kTapSpan + tid][0];
+  }
+  if (blockIdx.x == 0 && a.d_dterms) {  // leakage gradients: per pair, the unit partials 0..3
+    for (int p = 0; p < a.P; ++p) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double s = 0.0;
+        for (int u = tid; u < a.U; u += kTapThreads) s += a.red[((int64_t)p * a.U + u) * kBwRed + r];
+        red[r][tid] = s;
+      }
+      tree_sum<kTapRows>(red, tid);
+      if (tid < 4) a.d_dterms[4 * p + tid] = (float)red[tid][0];
+    }
+  }
+}
+
+// tap j: the blocks whose samples can touch it (segments j - 1 and j), in block order
+__global__ void __launch_bounds__(256) k_bw_taps_sum(BwTapArgs a) {
+  const int j = (int)(blockIdx.x * 256 + threadIdx.x), T = a.n_taps;
+  if (j >= T) return;
+  // first sample of segment j - 1 and last sample of segment j (the last segment takes the tail)
+  const int64_t lo = j == 0 ? 0 : ((int64_t)(j - 1) * (a.N - 1) + (T - 2)) / (T - 1);
+  const int64_t hi = j >= T - 2 ? a.N - 1 : ((int64_t)(j + 1) * (a.N - 1) + (T - 2)) / (T - 1);
+  double s = 0.0;
+#pragma unroll 4
+  for (int64_t b = lo / kTapThreads; b <= hi / kTapThreads; ++b) {
+    const int i = j - tap_segment(b * kTapThreads, a.N, T);
+    if (i >= 0 && i < kTapSpan) s += a.part[b * kTapSpan + i];
+  }
+  a.d_taps[j] = (float)s;
+}
+
 __global__ void __launch_bounds__(kTapThreads) k_bw_taps(BwTapArgs a) {
   __shared__ double red[kTapThreads];
   const int j = (int)blockIdx.x;
@@ -475,22 +573,22 @@ int window_taps_blocks(int64_t N) {
 }
 
 template <int L>
-static hipError_t bw_channel_launch(const BwChanArgs& a, const Launch& l) {
+static hipError_t bw_channel_launch(const BwChanArgs& a, const Launch& l, bool with_reduce) {
   PS_LAUNCH((k_bw_channel<L>), dim3((unsigned)(a.N1 / 2), (unsigned)a.P), dim3(L), l, a);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !with_reduce) return e;
   hipLaunchKernelGGL(k_bw_reduce, dim3((unsigned)a.P), dim3(64), 0, l.stream, a);
   return hipGetLastError();
 }
 
-hipError_t launch_bw_channel(int N2, const BwChanArgs& a, const Launch& l) {
+hipError_t launch_bw_channel(int N2, const BwChanArgs& a, const Launch& l, bool with_reduce) {
   switch (N2) {
-    case 16: return bw_channel_launch<16>(a, l);
-    case 32: return bw_channel_launch<32>(a, l);
-    case 64: return bw_channel_launch<64>(a, l);
-    case 128: return bw_channel_launch<128>(a, l);
-    case 256: return bw_channel_launch<256>(a, l);
-    case 512: return bw_channel_launch<512>(a, l);
+    case 16: return bw_channel_launch<16>(a, l, with_reduce);
+    case 32: return bw_channel_launch<32>(a, l, with_reduce);
+    case 64: return bw_channel_launch<64>(a, l, with_reduce);
+    case 128: return bw_channel_launch<128>(a, l, with_reduce);
+    case 256: return bw_channel_launch<256>(a, l, with_reduce);
+    case 512: return bw_channel_launch<512>(a, l, with_reduce);
     default: return hipErrorInvalidValue;
   }
 }
@@ -550,7 +648,20 @@ hipError_t launch_bw_colpass(int N1, int bits, bool fast, const BwColArgs& a, co
   }
 }
 
+bool bw_taps_block_form(int64_t N, int n_taps) {
+  // a block of kTapThreads samples spans at most ceil(255 (T - 1) / (N - 1)) + 1 segment boundaries
+  return 255.0 * (double)(n_taps - 1) <= (double)(kTapSpan - 3) * (double)(N - 1);
+}
+int64_t bw_taps_part_doubles(int64_t N) { return ((N + kTapThreads - 1) / kTapThreads) * kTapSpan; }
+
 hipError_t launch_bw_taps(const BwTapArgs& a, const Launch& l) {
+  if (a.part && bw_taps_block_form(a.N, a.n_taps)) {
+    hipExtLaunchKernelGGL(k_bw_taps_block, dim3((unsigned)((a.N + kTapThreads - 1) / kTapThreads)), dim3(kTapThreads),
+                          0, l.stream, l.start, nullptr, 0, a);
+    hipExtLaunchKernelGGL(k_bw_taps_sum, dim3((unsigned)((a.n_taps + 255) / 256)), dim3(256), 0, l.stream, nullptr,
+                          l.stop, 0, a);
+    return hipGetLastError();
+  }
   hipExtLaunchKernelGGL(k_bw_dw_sum, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, l.stream, l.start, nullptr, 0,
                         const_cast<double*>(a.dw), a.groups, a.N);  // the plan's workspace
   BwTapArgs b = a;

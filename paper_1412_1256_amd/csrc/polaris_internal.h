@@ -157,6 +157,12 @@ struct BwTapArgs {          // tap gradient
   const double* norm;       // [P]
   int32_t P;
   float* d_taps;
+  double* part;             // [ceil(N / 256)][8] per-block tap sums of the one-pass form, or nullptr
+  // one-pass form: the channel kernel's per-unit partials [P][U][5], reduced here (normaliser; leakage
+  // gradients into d_dterms [P][4] when not nullptr)
+  const double* red;
+  int32_t U;
+  float* d_dterms;
 };
 
 // Stream of a launch, and optionally two events the dispatch itself stamps with the kernel's start and end.
@@ -197,10 +203,14 @@ hipError_t launch_unpack(const void* packed, int bits, int S, int64_t n_time, fl
 constexpr int kMaxBwGroups = 32;  // partial dL/dw buffers of the backward column pass (groups x pairs)
 int window_taps_blocks(int64_t N);
 hipError_t launch_window_taps(const WinArgs& a, int n_blocks, double* sumw2, const Launch& l);
-hipError_t launch_bw_channel(int N2, const BwChanArgs& a, const Launch& l);
+// with_reduce: also the per-pair reduction of the unit partials (leakage gradients, normaliser); without
+// it, the one-pass tap gradient reduces them
+hipError_t launch_bw_channel(int N2, const BwChanArgs& a, const Launch& l, bool with_reduce = true);
 hipError_t launch_bw_rowpass(int N2, const BwRowArgs& a, const Launch& l);
 hipError_t launch_bw_colpass(int N1, int bits, bool fast, const BwColArgs& a, const Launch& l);
 hipError_t launch_bw_taps(const BwTapArgs& a, const Launch& l);
+bool bw_taps_block_form(int64_t N, int n_taps);  // the one-pass tap gradient applies (else two kernels)
+int64_t bw_taps_part_doubles(int64_t N);         // its per-block sums
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_hist_power(const unsigned long long* counts, int n_streams, int bits, double* power,
