@@ -380,27 +380,32 @@ def precision_form(pk, torch, dev, steps, warmup, with_oracle=True):
             got = out.cpu().numpy().astype(np.float64)
             e = np.max(np.abs(got - ref) / ref[:, 0:1, :], axis=2)
             r["err_vs_oracle_IQUV"] = [float(v) for v in e.max(axis=0)]
-        # two integrations in flight: a second plan on its own stream takes every other integration, from
-        # its own copy of the input
+        res[f"{prec}_{accum}"] = r
+        del plan
+    # two integrations in flight: two plans, each on its own stream with its own copy of the input and its own
+    # output, take the integrations in turn (timed after every single-plan case, each with fresh plans)
+    outs2 = [out, torch.empty_like(out)]
+    bufs = [packed, packed2]
+    for prec, accum in (("fp16", "kahan32"), ("bf16", "kahan32"), ("fp32", "fp64")):
         streams = [torch.cuda.Stream(dev) for _ in range(2)]
         plans2 = [pk.Plan([pk.Instance.from_synth(inst, precision=prec, accum=accum, chunk_frames=128)],
                           device=dev, stream=st) for st in streams]
-        bufs, outs2 = [packed, packed2], [out, torch.empty_like(out)]
 
         def run_on(pl, i):
             pl.reset()
             pl.accumulate(bufs[i % 2])
             pl.stokes(out=outs2[i % 2])
 
-        t2 = pipelined_time(torch, dev, plans2, run_on, max(2, 2 * steps))
-        r["depth2"] = {"us_per_step": t2 * 1e6, "Gsamples_per_s": samples / t2 / 1e9,
-                       "x_realtime": F * N / SAMPLE_RATE / t2,
-                       "path_GBps": (kb("colpass", inst, F) + kb("rowpass", inst, F) + P * (N // 2) * 48) / t2 / 1e9}
+        t2 = pipelined_time(torch, dev, plans2, run_on, max(4, 2 * steps), warmup_s=0.2)
+        kb = kernel_bytes if prec == "fp32" else kernel_bytes_mx
+        d2 = {"us_per_step": t2 * 1e6, "Gsamples_per_s": samples / t2 / 1e9, "x_realtime": F * N / SAMPLE_RATE / t2,
+              "path_GBps": (kb("colpass", inst, F) + kb("rowpass", inst, F) + P * (N // 2) * 48) / t2 / 1e9}
         if prec != "fp32":
-            r["depth2"]["mfma_tflops"] = 1024.0 * N * F * P / t2 / 1e12
-            r["depth2"]["mfma_frac_dense_peak"] = r["depth2"]["mfma_tflops"] / MFMA_16BIT_PEAK_TFLOPS
-        res[f"{prec}_{accum}"] = r
-        del plan, plans2
+            d2["mfma_tflops"] = 1024.0 * N * F * P / t2 / 1e12
+            d2["mfma_frac_dense_peak"] = d2["mfma_tflops"] / MFMA_16BIT_PEAK_TFLOPS
+        res[f"{prec}_{accum}"]["depth2"] = d2
+        torch.cuda.synchronize(dev)
+        del plans2
     return res
 
 

@@ -711,7 +711,15 @@ ps_status accumulate_mx(ps_plan_t plan, Inst& I, const ps::ColArgs& ca) {
   ps::MxColArgs m{};
   m.col = ca;
   m.col.n_colblk = (int32_t)(I.N2 / 16);
-  const int64_t per_frame = (int64_t)m.col.n_colblk * ca.P;
+  const ps_instance& c = I.cfg;
+  m.mode = 0;
+  if (c.bits == 8 && c.n_streams == 2 && c.n_pairs == 1 && c.pair_x[0] == 0 && c.pair_y[0] == 1) m.mode = 1;
+  if (c.bits == 8 && c.n_streams == 4) m.mode = 2;
+  // four streams as the pairs (0, 2) and (1, 3): one workgroup transforms both from the words it reads
+  if (m.mode == 2 && c.n_pairs == 2 && c.pair_x[0] == 0 && c.pair_y[0] == 2 && c.pair_x[1] == 1 && c.pair_y[1] == 3)
+    m.mode = 3;
+  if (ca.in_bytes == 0) m.mode = 0;  // the word paths address the launch's input with 32-bit offsets
+  const int64_t per_frame = (int64_t)m.col.n_colblk * (m.mode == 3 ? 1 : ca.P);
   // two or three workgroups fit on a CU: aim at two per CU, each looping over a group of frames
   int64_t groups = (2 * plan->n_cu + per_frame / 2) / per_frame;
   if (groups < 1) groups = 1;
@@ -722,11 +730,6 @@ ps_status accumulate_mx(ps_plan_t plan, Inst& I, const ps::ColArgs& ca) {
   m.m.aR = ws_ptr<uint32_t>(plan, I.N1 == 512 ? I.off_mx32 : I.off_mx16);
   m.m.tws = ws_ptr<float2>(plan, I.off_tws_col);
   m.T = ws_ptr<uint32_t>(plan, I.off_T);
-  const ps_instance& c = I.cfg;
-  m.mode = 0;
-  if (c.bits == 8 && c.n_streams == 2 && c.n_pairs == 1 && c.pair_x[0] == 0 && c.pair_y[0] == 1) m.mode = 1;
-  if (c.bits == 8 && c.n_streams == 4) m.mode = 2;
-  if (ca.in_bytes == 0) m.mode = 0;  // the word paths address the launch's input with 32-bit offsets
   const int n_blocks = (int)(groups * per_frame);
   hipError_t e = timed(plan, PS_KERNEL_COLPASS, [&](const ps::Launch& l) {
     return ps::launch_colpass_mx((int)I.N1, c.precision, c.bits, m, n_blocks, l);

@@ -435,7 +435,7 @@ __global__ void __launch_bounds__(256) k_bw_dw_sum(double* __restrict__ dw, int 
 // and t: the window is linear between taps), summed per tap within the block by a fixed tree.  The
 // dL/dw part and the window part are summed apart and combined once nt (the sum of the channel kernel's
 // per-unit normaliser partials, also reduced here) is known.  Block b writes part[b][i], the sum for tap
-// j_lo(b) + i (j_lo(b): the tap segment of its first sample); block 0 also writes the leakage gradients.
+// j_lo(b) + i (j_lo(b): the tap segment of its first sample); one extra block writes the leakage gradients.
 // The host launches this form only when a block's samples touch fewer than kTapSpan taps.
 constexpr int kTapSpan = 8;
 constexpr int kTapRows = 2 * kTapSpan + 1;
@@ -460,6 +460,21 @@ __device__ __forceinline__ void tree_sum(double (&red)[ROWS][kTapThreads], int t
 __global__ void __launch_bounds__(kTapThreads) k_bw_taps_block(BwTapArgs a) {
   __shared__ double red[kTapRows][kTapThreads];
   const int tid = (int)threadIdx.x, T = a.n_taps;
+  if (blockIdx.x == gridDim.x - 1) {  // the extra last block: leakage gradients, per pair the unit partials 0..3
+    if (!a.d_dterms) return;
+    for (int p = 0; p < a.P; ++p) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double s = 0.0;
+        for (int u = tid; u < a.U; u += kTapThreads) s += a.red[((int64_t)p * a.U + u) * kBwRed + r];
+        red[r][tid] = s;
+      }
+      tree_sum<kTapRows>(red, tid);
+      if (tid < 4) a.d_dterms[4 * p + tid] = (float)red[tid][0];
+    }
+    return;
+  }
   const int64_t n0 = (int64_t)blockIdx.x * kTapThreads;
   const int j_lo = tap_segment(n0, a.N, T);
 #pragma unroll
@@ -487,32 +502,25 @@ __global__ void __launch_bounds__(kTapThreads) k_bw_taps_block(BwTapArgs a) {
     const double coef = -2.0 * red[2 * kTapSpan][0] / a.sumw2[0];
     a.part[(int64_t)blockIdx.x * kTapSpan + tid] = red[tid][0] + coef * red[kTapSpan + tid][0];
   }
-  if (blockIdx.x == 0 && a.d_dterms) {  // leakage gradients: per pair, the unit partials 0..3
-    for (int p = 0; p < a.P; ++p) {
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double s = 0.0;
-        for (int u = tid; u < a.U; u += kTapThreads) s += a.red[((int64_t)p * a.U + u) * kBwRed + r];
-        red[r][tid] = s;
-      }
-      tree_sum<kTapRows>(red, tid);
-      if (tid < 4) a.d_dterms[4 * p + tid] = (float)red[tid][0];
-    }
-  }
 }
 
 // tap j: the blocks whose samples can touch it (segments j - 1 and j), in block order
 __global__ void __launch_bounds__(256) k_bw_taps_sum(BwTapArgs a) {
   const int j = (int)(blockIdx.x * 256 + threadIdx.x), T = a.n_taps;
   if (j >= T) return;
-  // first sample of segment j - 1 and last sample of segment j (the last segment takes the tail)
-  const int64_t lo = j == 0 ? 0 : ((int64_t)(j - 1) * (a.N - 1) + (T - 2)) / (T - 1);
-  const int64_t hi = j >= T - 2 ? a.N - 1 : ((int64_t)(j + 1) * (a.N - 1) + (T - 2)) / (T - 1);
+  // samples of segments j - 1 and j, widened by one on each side (a block that does not touch tap j
+  // holds zero in its slot for it; the last segment takes the tail)
+  const double seg = (double)(a.N - 1) / (double)(T - 1);
+  int64_t lo = (int64_t)floor((double)(j - 1) * seg) - 1, hi = (int64_t)ceil((double)(j + 1) * seg) + 1;
+  if (j >= T - 2) hi = a.N - 1;
+  if (lo < 0) lo = 0;
+  if (hi > a.N - 1) hi = a.N - 1;
   double s = 0.0;
-#pragma unroll 4
   for (int64_t b = lo / kTapThreads; b <= hi / kTapThreads; ++b) {
-    const int i = j - tap_segment(b * kTapThreads, a.N, T);
+    int jl;
+    double t;
+    tap_position(b * kTapThreads, a.N, T, jl, t);  // the same segment as tap_segment (both exact floors)
+    const int i = j - jl;
     if (i >= 0 && i < kTapSpan) s += a.part[b * kTapSpan + i];
   }
   a.d_taps[j] = (float)s;
@@ -656,8 +664,9 @@ int64_t bw_taps_part_doubles(int64_t N) { return ((N + kTapThreads - 1) / kTapTh
 
 hipError_t launch_bw_taps(const BwTapArgs& a, const Launch& l) {
   if (a.part && bw_taps_block_form(a.N, a.n_taps)) {
-    hipExtLaunchKernelGGL(k_bw_taps_block, dim3((unsigned)((a.N + kTapThreads - 1) / kTapThreads)), dim3(kTapThreads),
-                          0, l.stream, l.start, nullptr, 0, a);
+    // one block per kTapThreads samples, and one for the leakage gradients
+    hipExtLaunchKernelGGL(k_bw_taps_block, dim3((unsigned)((a.N + kTapThreads - 1) / kTapThreads + 1)),
+                          dim3(kTapThreads), 0, l.stream, l.start, nullptr, 0, a);
     hipExtLaunchKernelGGL(k_bw_taps_sum, dim3((unsigned)((a.n_taps + 255) / 256)), dim3(256), 0, l.stream, nullptr,
                           l.stop, 0, a);
     return hipGetLastError();

@@ -226,8 +226,11 @@ struct ColLoader {
 // offset NS*BITS*t, so the V adjacent columns (t a multiple of V) of a row are one word of V*NS*BITS bits
 // (8 to 64), fetched ahead of use.  Two streams form the pair (0, 1); of four, the pair's streams sx, sy are
 // picked from the word by shifts.
-// input words are read once: stream them past the caches (keeps the last-level cache for the
-// intermediate buffer; about 4 % faster with input streamed from HBM)
+// Input words are read once: with column blocks of at least 16 columns (N1 <= 512) they are streamed past
+// the caches (keeps the last-level cache for the intermediate buffer; about 4 % faster at 2^18 with input
+// streamed from HBM).  Longer columns come in blocks of 8 or fewer columns, whose row segments are a
+// fraction of a cache line: those loads go through L2, where the neighbouring blocks (same XCD) find the
+// rest of each line.
 #ifndef PS_INPUT_NONTEMPORAL
 #define PS_INPUT_NONTEMPORAL 1
 #endif
@@ -240,14 +243,12 @@ struct ColLoaderWords {
   static_assert(WBITS >= 8 && WBITS <= 64, "one load per row");
   using word = typename std::conditional<(WBITS > 32), uint64_t, uint32_t>::type;
   word raw[8];  // the row's V x NS codes
-  template <class T>
+  template <class T, bool NT>
   static __device__ __forceinline__ word load(gbytes p) {
-#if PS_INPUT_NONTEMPORAL
-    // read once: streamed past the caches
-    return (word)__builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
-#else
-    return (word)*(const __attribute__((address_space(1))) T*)p;
-#endif
+    if constexpr (NT && PS_INPUT_NONTEMPORAL)  // read once: streamed past the caches
+      return (word)__builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
+    else
+      return (word)*(const __attribute__((address_space(1))) T*)p;
   }
   template <int L, int R0>
   __device__ __forceinline__ void fetch(const ColArgs& a, int64_t fb, int ts, int n2b) {
@@ -260,10 +261,11 @@ struct ColLoaderWords {
       for (int r = 0; r < R0; ++r) {
         const int64_t t0 = fb + (int64_t)a.N2 * (i * (L / 8) + r * (L / R0));
         const gbytes p = uniform_gptr(a.in + t0 * (NS * BITS) / 8) + voff;
-        if constexpr (WBITS == 64) raw[i * R0 + r] = load<uint64_t>(p);
-        else if constexpr (WBITS == 32) raw[i * R0 + r] = load<uint32_t>(p);
-        else if constexpr (WBITS == 16) raw[i * R0 + r] = load<uint16_t>(p);
-        else raw[i * R0 + r] = load<uint8_t>(p);
+        constexpr bool NT = L <= 512;
+        if constexpr (WBITS == 64) raw[i * R0 + r] = load<uint64_t, NT>(p);
+        else if constexpr (WBITS == 32) raw[i * R0 + r] = load<uint32_t, NT>(p);
+        else if constexpr (WBITS == 16) raw[i * R0 + r] = load<uint16_t, NT>(p);
+        else raw[i * R0 + r] = load<uint8_t, NT>(p);
       }
   }
   static __device__ __forceinline__ float lvl(word w, int field) {

@@ -87,7 +87,8 @@ struct MxColArgs {
   ColArgs col;              // geometry and input; col.T is unused
   MxMats m;
   uint32_t* T;              // packed 16-bit complex [n_frames][P][N1][N2]
-  int32_t mode;             // input access: 0 generic, 1 int8 two streams pair (0,1), 2 int8 four streams
+  int32_t mode;             // input access: 0 generic, 1 int8 two streams pair (0,1), 2 int8 four streams,
+                            // 3 int8 four streams as the pairs (0,2), (1,3), both in one workgroup
 };
 
 struct MxRowArgs {

@@ -97,7 +97,8 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Input samples of the pair (x, y) at time t of the launch.  MODE 1: int8, two streams, pair (0, 1): one
-// 16-bit word.  MODE 2: int8, four streams: one 32-bit word holding every stream.  MODE 0: any format,
+// 16-bit word.  MODE 2: int8, four streams: one 32-bit word holding every stream.  MODE 3: as MODE 2 with
+// the pairs (0, 2) and (1, 3), both transformed by the workgroup that reads the word.  MODE 0: any format,
 // decoded item by item.
 template <int BITS, int MODE>
 struct MxIn {
@@ -105,13 +106,13 @@ struct MxIn {
   // buffer load of the launch's input: voff the lane's byte offset, soff the wave-uniform byte offset
   __device__ __forceinline__ void fetch(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
     if constexpr (MODE == 1) raw = __builtin_amdgcn_raw_buffer_load_b16(rs, voff, soff, 0);
-    else if constexpr (MODE == 2) raw = __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0);
+    else if constexpr (MODE >= 2) raw = __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0);
     else raw = 0;
   }
   __device__ __forceinline__ float2 level(const ColArgs& c, int64_t t, int sx, int sy) const {
     if constexpr (MODE == 1) {
       return make_float2((float)(int)(int8_t)(raw & 0xffu), (float)(int)(int8_t)(raw >> 8));
-    } else if constexpr (MODE == 2) {
+    } else if constexpr (MODE >= 2) {  // (MODE 3: sx, sy are constants after unrolling, so byte selects)
       return make_float2((float)(int)(int8_t)(raw >> (8 * sx)), (float)(int)(int8_t)(raw >> (8 * sy)));
     } else {
       return make_float2(level_of<BITS>(c.in, t * c.S + sx), level_of<BITS>(c.in, t * c.S + sy));
@@ -143,14 +144,14 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
   const int tid = (int)threadIdx.x, lane = tid & 63, g = lane >> 4, n = lane & 15;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
   const int blk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  constexpr int NPP = MODE == 3 ? 2 : 1;  // pairs transformed by the workgroup
   const int cb = blk % c.n_colblk;
   const int rest = blk / c.n_colblk;
-  const int p = rest % c.P;
-  const int grp = rest / c.P;
+  const int p0 = NPP == 2 ? 0 : rest % c.P;
+  const int grp = NPP == 2 ? rest : rest / c.P;
   const int f_begin = grp * c.frames_per_block;
   const int f_end = min(c.n_frames, f_begin + c.frames_per_block);
   const int n2 = cb * 16 + n;
-  const int sx = c.px[p], sy = c.py[p];
   // Addresses: a wave-uniform base (SGPRs) per element, which changes with the frame, plus one per-lane
   // offset shared by every element, so no per-element offsets stay live across the frame loop.
   const uint32_t lane_t = (uint32_t)(4 * R * g * N2 + n2);                // time index, lane part
@@ -205,82 +206,90 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
   };
   if (f_begin < f_end) fetch(f_begin);
   for (int f = f_begin; f < f_end; ++f) {
-    // the stage twiddles are read from LDS in every frame: an opaque zero keeps the compiler from holding
-    // all of them in registers across the frame loop
-    int z0;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(z0));
-    // ---- stage A (and the radix-2 butterfly of a radix-32 stage B)
-    uint32_t Y[H][4][4];  // [half][i][j]
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int b = 4 * w + j;
-      f4v o[H][2];
+    for (int pp = 0; pp < NPP; ++pp) {
+      const int p = p0 + pp;
+      const int sx = NPP == 2 ? pp : c.px[p], sy = NPP == 2 ? pp + 2 : c.py[p];
+      // the stage twiddles are read from LDS in every frame: an opaque zero keeps the compiler from holding
+      // all of them in registers across the frame loop
+      int z0;
+      asm volatile("v_mov_b32 %0, 0" : "=v"(z0));
+      // ---- stage A (and the radix-2 butterfly of a radix-32 stage B)
+      uint32_t Y[H][4][4];  // [half][i][j]
 #pragma unroll
-      for (int h = 0; h < H; ++h) {
-        w4v xb[1];
+      for (int j = 0; j < 4; ++j) {
+        const int b = 4 * w + j;
+        f4v o[H][2];
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int64_t tt = (int64_t)f * c.hop + (int64_t)(R * jj + b + 16 * h) * N2 + lane_t;
-          float2 v = in[j][h][jj].level(c, tt, sx, sy);
-          if constexpr (WIN) {
-            const gbytes wb = uniform_gptr(reinterpret_cast<const uint8_t*>(c.win + (R * jj + b + 16 * h) * N2));
-            const float wv = *(const __attribute__((address_space(1))) float*)(wb + 4u * lane_t);
-            v = make_float2(v.x * wv, v.y * wv);
+        for (int h = 0; h < H; ++h) {
+          w4v xb[1];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int64_t tt = (int64_t)f * c.hop + (int64_t)(R * jj + b + 16 * h) * N2 + lane_t;
+            float2 v = in[j][h][jj].level(c, tt, sx, sy);
+            if constexpr (WIN) {
+              const gbytes wb = uniform_gptr(reinterpret_cast<const uint8_t*>(c.win + (R * jj + b + 16 * h) * N2));
+              const float wv = *(const __attribute__((address_space(1))) float*)(wb + 4u * lane_t);
+              v = make_float2(v.x * wv, v.y * wv);
+            }
+            xb[0][jj] = pk<PREC>(v.x, v.y);
           }
-          xb[0][jj] = pk<PREC>(v.x, v.y);
+          A16.template apply<PREC>(xb, o[h]);
         }
-        A16.template apply<PREC>(xb, o[h]);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int kap = 4 * g + i;
-        const float2 y0 = make_float2(o[0][0][i], o[0][1][i]);
-        if constexpr (H == 1) {
-          const float2 t = tws[((b * kap) & (N1 - 1)) + z0];
-          Y[0][i][j] = pk<PREC>(y0.x * t.x - y0.y * t.y, y0.x * t.y + y0.y * t.x);
-        } else {
-          const float2 v = cmul(w32[i], make_float2(o[1][0][i], o[1][1][i]));
-          const float2 s0 = cadd(y0, v), d0 = csub(y0, v);
-          const float2 ta = tws[((b * kap) & (N1 - 1)) + z0];
-          const float2 tb = tws[((b * (kap + 16)) & (N1 - 1)) + z0];
-          Y[0][i][j] = pk<PREC>(s0.x * ta.x - s0.y * ta.y, s0.x * ta.y + s0.y * ta.x);
-          Y[1][i][j] = pk<PREC>(d0.x * tb.x - d0.y * tb.y, d0.x * tb.y + d0.y * tb.x);
-        }
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < H; ++h)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const w4v v = {Y[h][i][0], Y[h][i][1], Y[h][i][2], Y[h][i][3]};
-        *reinterpret_cast<w4v*>(&X[((h * 16 + 4 * g + i) * 16 + n) * XS + 4 * w]) = v;
-      }
-    // the next frame's words: issued here, not earlier, so they do not hold registers through stage A;
-    // unconditional (the last frame fetches itself again), see the row pass
-    __builtin_amdgcn_sched_barrier(0);
-    fetch(min(f + 1, f_end - 1));
-    __syncthreads();
-    // ---- stage B and the four-step twiddle
-    const uint32_t* Tf = a.T + ((int64_t)__builtin_amdgcn_readfirstlane(f) * c.P + p) * (int64_t)N1 * N2;
-    const __amdgpu_buffer_rsrc_t rout = buffer_rsrc(Tf, (uint32_t)(N1 * N2 * 4));
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int kap = w + 4 * t;
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const w4v xs[1] = {*reinterpret_cast<const w4v*>(&X[((h * 16 + kap) * 16 + n) * XS + 4 * g])};
-        f4v o[2];
-        A16.template apply<PREC>(xs, o);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          // k1 = kap + 16 (H (4g + i) + h): lane part 16 H 4g, uniform part kap + 16 (H i + h)
-          const float2 v = cmul(make_float2(o[0][i], o[1][i]), cmul(t1[t], t2[h][i]));
-          __builtin_amdgcn_raw_buffer_store_b32(pk<PREC>(v.x, v.y), rout, lane_o,
-                                                (uint32_t)((kap + 16 * (H * i + h)) * N2 * 4), 0);
+          const int kap = 4 * g + i;
+          const float2 y0 = make_float2(o[0][0][i], o[0][1][i]);
+          if constexpr (H == 1) {
+            const float2 t = tws[((b * kap) & (N1 - 1)) + z0];
+            Y[0][i][j] = pk<PREC>(y0.x * t.x - y0.y * t.y, y0.x * t.y + y0.y * t.x);
+          } else {
+            const float2 v = cmul(w32[i], make_float2(o[1][0][i], o[1][1][i]));
+            const float2 s0 = cadd(y0, v), d0 = csub(y0, v);
+            const float2 ta = tws[((b * kap) & (N1 - 1)) + z0];
+            const float2 tb = tws[((b * (kap + 16)) & (N1 - 1)) + z0];
+            Y[0][i][j] = pk<PREC>(s0.x * ta.x - s0.y * ta.y, s0.x * ta.y + s0.y * ta.x);
+            Y[1][i][j] = pk<PREC>(d0.x * tb.x - d0.y * tb.y, d0.x * tb.y + d0.y * tb.x);
+          }
         }
       }
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const w4v v = {Y[h][i][0], Y[h][i][1], Y[h][i][2], Y[h][i][3]};
+          *reinterpret_cast<w4v*>(&X[((h * 16 + 4 * g + i) * 16 + n) * XS + 4 * w]) = v;
+        }
+      // the next frame's words, once the last pair's stage A has used this frame's: issued here, not earlier,
+      // so they do not hold registers through stage A; unconditional (the last frame fetches itself again),
+      // see the row pass
+      if (pp == NPP - 1) {
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(min(f + 1, f_end - 1));
+      }
+      __syncthreads();
+      // ---- stage B and the four-step twiddle
+      const uint32_t* Tf = a.T + ((int64_t)__builtin_amdgcn_readfirstlane(f) * c.P + p) * (int64_t)N1 * N2;
+      const __amdgpu_buffer_rsrc_t rout = buffer_rsrc(Tf, (uint32_t)(N1 * N2 * 4));
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int kap = w + 4 * t;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          const w4v xs[1] = {*reinterpret_cast<const w4v*>(&X[((h * 16 + kap) * 16 + n) * XS + 4 * g])};
+          f4v o[2];
+          A16.template apply<PREC>(xs, o);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            // k1 = kap + 16 (H (4g + i) + h): lane part 16 H 4g, uniform part kap + 16 (H i + h)
+            const float2 v = cmul(make_float2(o[0][i], o[1][i]), cmul(t1[t], t2[h][i]));
+            __builtin_amdgcn_raw_buffer_store_b32(pk<PREC>(v.x, v.y), rout, lane_o,
+                                                  (uint32_t)((kap + 16 * (H * i + h)) * N2 * 4), 0);
+          }
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -472,6 +481,7 @@ hipError_t colpass_mx_bits(int bits, const MxColArgs& a, int n_blocks, const Lau
   switch (a.mode) {
     case 1: PS_LAUNCH((k_colpass_mx<R, N2, PREC, 8, 1, false>), grid, block, l, a); break;
     case 2: PS_LAUNCH((k_colpass_mx<R, N2, PREC, 8, 2, false>), grid, block, l, a); break;
+    case 3: PS_LAUNCH((k_colpass_mx<R, N2, PREC, 8, 3, false>), grid, block, l, a); break;
     default: return colpass_mx_generic<R, N2, PREC, false>(bits, a, grid, l);
   }
   return hipGetLastError();

@@ -88,6 +88,20 @@ def test_four_streams_two_pairs(env, precision):
     assert np.all(e < TOL[precision])
 
 
+@pytest.mark.parametrize("pairs", [((0, 1), (2, 3)), ((3, 1),)])
+def test_four_streams_other_pairs(env, pairs):
+    """Four int8 streams paired otherwise than (0, 2), (1, 3): each workgroup transforms one pair, taking its
+    two streams out of the four-stream word (the (0, 2), (1, 3) layout is transformed two pairs at a time)."""
+    say(f"precision fp16 S=4 pairs {pairs} N=2^17 F=96")
+    inst = dict(synth.make_precision(n_frames=48), pairs=[list(p) for p in pairs])
+    inst = dict(inst, fft_len=1 << 17, n_frames=96)  # the same samples as 2^17-point frames
+    ref = ref_stokes(inst)
+    got = run_gpu(env, inst, "fp16", "kahan32")
+    e = stokes_err(got, ref)
+    say(f"  err per pair, I,Q,U,V {e.tolist()}")
+    assert np.all(e < TOL["fp16"])
+
+
 @pytest.mark.parametrize("bits", [2, 4, 32])
 def test_other_formats_and_hann(env, bits):
     say(f"precision fp16 bits={bits} Hann N=2^16 F=40")
