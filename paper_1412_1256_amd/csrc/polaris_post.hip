@@ -674,7 +674,7 @@ hipError_t launch_allan(const AllanArgs& a, hipStream_t s) {
   for (int l = 0; l < a.n_lags; ++l) lmax = a.lags[l] > lmax ? a.lags[l] : lmax;
   const bool rows16 = reinterpret_cast<uintptr_t>(a.x) % 8 == 0 && a.point_stride % 2 == 0 && a.n_series % 2 == 0;
   if (allan_cols(a.n_series, a.point_stride, a.series_stride) && lmax <= kWinMaxLag && rows16 &&
-      a.n_points < (int64_t(1) << 31)) {
+      a.n_points >= 1 && a.n_points < (int64_t(1) << 31)) {  // (no rows: the column form writes NaN)
     hipLaunchKernelGGL(k_allan_window, dim3((unsigned)((a.n_series + kWinSeries - 1) / kWinSeries)),
                        dim3(kWinThreads), 0, s, a);
   } else if (allan_cols(a.n_series, a.point_stride, a.series_stride)) {
