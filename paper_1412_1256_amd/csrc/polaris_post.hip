@@ -451,7 +451,10 @@ __global__ void __launch_bounds__(kWinThreads) k_allan_window(AllanArgs a) {
   static_assert(kWinLags * kWinStep * kWinSeries * 8 <= (kWinRing + kWinStep) * kWinSeries * 4,
                 "the phase sums fit in the ring");
   const int tid = (int)threadIdx.x;
-  const int g = tid % kWinGroups, q = (tid / kWinGroups) % kWinStep, h = tid / (kWinGroups * kWinStep);
+  const int g = tid % kWinGroups, q = (tid / kWinGroups) % kWinStep;
+  // the half is the same for a whole wave (512-thread halves): made visibly uniform, so the lag and ring-slot
+  // arithmetic below runs on the scalar unit
+  const int h = __builtin_amdgcn_readfirstlane(tid / (kWinGroups * kWinStep));
   const int64_t sb = (int64_t)blockIdx.x * kWinSeries;  // first series of the workgroup
   const int P = (int)a.n_points;                          // < 2^31 (checked by the launcher)
   const int64_t st = a.point_stride;
@@ -485,8 +488,13 @@ __global__ void __launch_bounds__(kWinThreads) k_allan_window(AllanArgs a) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) S[l][c] = 0.0;
     f2 pre[kWinAhead];
+    // issued in step order (the loop then finds the same order each time round: a step waits only for the
+    // loads issued before its own)
 #pragma unroll
-    for (int u = 0; u < kWinAhead; ++u) fetch(pre[u], u * kWinStep + q);
+    for (int u = 0; u < kWinAhead; ++u) {
+      fetch(pre[u], u * kWinStep + q);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     int k0 = 0;                // slot of row r0
     int bt = kWinRing - lmax;  // slot of row r0 - lmax (lmax <= kWinMaxLag < kWinRing)
     auto step = [&](const int r0, f2& d) {
@@ -537,10 +545,12 @@ __global__ void __launch_bounds__(kWinThreads) k_allan_window(AllanArgs a) {
       k0 = wrap(k0 + kWinStep);
       bt = wrap(bt + kWinStep);
     };
+    // Every step of an unrolled group runs: a step past the last point writes zero rows and adds exact
+    // zeros (its points are out of every lag's range), and no load then sits behind a branch, so each step
+    // waits only for its own rows while the later steps' loads stay in flight.
     for (int r0 = 0; r0 < P + lmax; r0 += kWinAhead * kWinStep) {
 #pragma unroll
-      for (int u = 0; u < kWinAhead; ++u)
-        if (r0 + u * kWinStep < P + lmax) step(r0 + u * kWinStep, pre[u]);
+      for (int u = 0; u < kWinAhead; ++u) step(r0 + u * kWinStep, pre[u]);
     }
     __syncthreads();  // the ring is free: it holds the phase sums from here on
     if (l0 == 0 && a.normalize) {  // series means: [2][phase][series] sums, added in phase order
