@@ -354,10 +354,12 @@ ps_status upload(ps_plan_t plan, size_t off, const void* src, size_t bytes) {
 }
 
 // Default split N = N1 x N2 (log2 N1) of the four-step passes: N1 = 2^floor(m/2), except where timing on the
-// device favours another: 2^19 as 1024 x 512 (rows of 512 points stay wave-local) and 2^20 as 512 x 2048.
-// Default FP32 schedules of the four-step passes, from whole-integration timings on the device (2^25 samples
-// per stream and integration, int8 and 2-bit): 2^13 .. 2^17 run with the longer column pass first and 2 or 4
-// column-pass workgroups per CU; 2^19 as 1024 x 512, 2^20 as 512 x 2048.
+// device favours another.  Default FP32 schedules of the four-step passes, from whole-integration timings on
+// the device (2^25 samples per stream and integration, int8 and 2-bit): 2^13 .. 2^17 run with the longer
+// column pass first and 2 or 4 column-pass workgroups per CU; 2^19 as 512 x 1024 for 8-bit and wider codes
+// (the 1024-point rows held 16 points per lane; 455 against 418 Gsamples/s as 1024 x 512, whose 8-column
+// blocks of 1024-point columns read byte-sized input slowly) and 1024 x 512 for 2- and 4-bit codes; 2^20 as
+// 512 x 2048.
 int default_log2_n1(const ps_instance& c) {
   const int m = ilog2_exact(c.fft_len);
   if (c.precision != PS_PREC_FP32) return m / 2;
@@ -367,7 +369,7 @@ int default_log2_n1(const ps_instance& c) {
     case 15: return 7;
     case 16: return 8;
     case 17: return 9;
-    case 19: return 10;
+    case 19: return c.bits >= 8 ? 9 : 10;
     case 20: return 9;
     default: return m / 2;
   }

@@ -71,6 +71,52 @@ struct Dft<8> {
   }
 };
 
+// 16- and 32-point DFTs: even/odd split into two half-length DFTs, the odd half rotated by W_R^k
+// (W_32^k = exp(-2 pi i k / 32) rounded to FP32; W_16^k = W_32^(2k)).
+struct W32 {
+  static constexpr float c[16] = {1.0f,           9.807852804e-01f, 9.238795325e-01f, 8.314696123e-01f,
+                                  7.071067812e-01f, 5.555702330e-01f, 3.826834324e-01f, 1.950903220e-01f,
+                                  0.0f,           -1.950903220e-01f, -3.826834324e-01f, -5.555702330e-01f,
+                                  -7.071067812e-01f, -8.314696123e-01f, -9.238795325e-01f, -9.807852804e-01f};
+  static constexpr float s[16] = {0.0f,           -1.950903220e-01f, -3.826834324e-01f, -5.555702330e-01f,
+                                  -7.071067812e-01f, -8.314696123e-01f, -9.238795325e-01f, -9.807852804e-01f,
+                                  -1.0f,          -9.807852804e-01f, -9.238795325e-01f, -8.314696123e-01f,
+                                  -7.071067812e-01f, -5.555702330e-01f, -3.826834324e-01f, -1.950903220e-01f};
+};
+
+// a * W_R^k for R = 16 or 32 (k < R/2, a compile-time constant after unrolling)
+template <int R>
+__device__ __forceinline__ float2 rot_w(float2 a, int k) {
+  if (k == 0) return a;
+  if (4 * k == R) return cmul_mi(a);
+  const int e = k * (32 / R);
+  return make_float2(a.x * W32::c[e] - a.y * W32::s[e], a.x * W32::s[e] + a.y * W32::c[e]);
+}
+
+template <int R>
+struct DftSplit {
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 e[R / 2], o[R / 2];
+#pragma unroll
+    for (int m = 0; m < R / 2; ++m) {
+      e[m] = v[2 * m];
+      o[m] = v[2 * m + 1];
+    }
+    Dft<R / 2>::run(e);
+    Dft<R / 2>::run(o);
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      const float2 t = rot_w<R>(o[k], k);
+      v[k] = cadd(e[k], t);
+      v[k + R / 2] = csub(e[k], t);
+    }
+  }
+};
+template <>
+struct Dft<16> : DftSplit<16> {};
+template <>
+struct Dft<32> : DftSplit<32> {};
+
 // ------------------------------------------------------------------------------------------------
 // Stockham schedule for a length-L sequence held as 8 points per thread (L/8 threads per sequence).
 // Pass p has radix R_p (first 2, 4 or 8, then 8) and sub-transform length NS_p = prod_{q<p} R_q.
@@ -410,6 +456,63 @@ __device__ __forceinline__ void row_chain(float2 (&v)[SQ][8], int ts, const Pass
     exchange_sync<L>();
     row_chain<L, SQ, P + 1>(v, ts, tw, seq);
   }
+}
+
+// Wide rows (L = 1024, 2048): a row held as 16 points per thread (T = L/16 threads: one wave for 1024
+// points, two for 2048), with three passes of radix 8, R1 = L/128 and 16 (two exchanges, where 8 points per
+// thread need four passes and three exchanges).  The thread's points are ts + k T (k < 16); task
+// j = ts + i T (i < 16/R) of a radix-R pass takes registers i + r 16/R (points j + r L/R), rotates input r by
+// W_(NS R)^(r (j mod NS)), applies the R-point DFT and writes output r to (j / NS) NS R + (j mod NS) + r NS.
+// NS (1, 8, 8 R1) divides T, so j mod NS = ts mod NS for every task of the thread, and its pass twiddles are
+// loaded once.  After the last pass the row is in natural order.
+template <int L>
+struct WideTw {
+  static constexpr int T = L / 16, R1 = L / 128;
+  float2 w1[R1 - 1], w2[15];
+  __device__ __forceinline__ void load(const float2* __restrict__ table, int ts) {  // table: W_L^m, m < L
+    const int m1 = ts & 7, m2 = ts & (8 * R1 - 1);
+#pragma unroll
+    for (int r = 1; r < R1; ++r) w1[r - 1] = table[r * m1 * 16];  // W_(8 R1)^(r m1)
+#pragma unroll
+    for (int r = 1; r < 16; ++r) w2[r - 1] = table[r * m2];       // W_L^(r m2)
+  }
+};
+
+template <int L, int P>
+__device__ __forceinline__ void wide_pass(float2 (&v)[16], const WideTw<L>& tw, int ts, float2* __restrict__ seq) {
+  constexpr int T = L / 16, R1 = L / 128;
+  constexpr int R = P == 0 ? 8 : (P == 1 ? R1 : 16), NT = 16 / R, NS = P == 0 ? 1 : (P == 1 ? 8 : 8 * R1);
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    float2 t[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) t[r] = v[i + r * NT];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      if constexpr (P == 1) t[r] = cmul(t[r], tw.w1[r - 1]);
+      if constexpr (P == 2) t[r] = cmul(t[r], tw.w2[r - 1]);
+    }
+    Dft<R>::run(t);
+    const int j = ts + i * T;
+#pragma unroll
+    for (int r = 0; r < R; ++r) seq[swz((j / NS) * NS * R + (j % NS) + r * NS)] = t[r];
+  }
+}
+
+template <int L>
+__device__ __forceinline__ void wide_chain(float2 (&v)[16], int ts, const WideTw<L>& tw, float2* __restrict__ seq) {
+  constexpr int T = L / 16;
+  wide_pass<L, 0>(v, tw, ts, seq);
+  exchange_sync<8 * T>();  // within the wave for one-wave rows, else a workgroup barrier
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = seq[swz(ts + k * T)];
+  exchange_sync<8 * T>();
+  wide_pass<L, 1>(v, tw, ts, seq);
+  exchange_sync<8 * T>();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = seq[swz(ts + k * T)];
+  exchange_sync<8 * T>();
+  wide_pass<L, 2>(v, tw, ts, seq);
 }
 
 // FP64 complex arithmetic

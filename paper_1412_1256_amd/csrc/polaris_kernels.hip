@@ -289,11 +289,21 @@ __device__ __forceinline__ void stokes_write(const OutArgs& a, const int p, cons
 // With STOKES (one accumulator slot, the integration's last launch), the owners of the channel slots also
 // write the calibrated Stokes of their channels from the final sums (exactly what the output kernel
 // computes from the stored accumulators).
+// threads of a row-pass workgroup: UB units of two rows, FB frames, SQ sequences per thread, and L/8 threads
+// per row (L/16 for the wide rows of 1024 and 2048 points)
+template <int L, int UB, int FB, int SQ>
+constexpr int rowpass_threads() {
+  return UB * FB * 2 * (L >= 1024 ? L / 16 : L / 8) / SQ;
+}
+
 template <int L, int UB, int FB, int SQ, bool STOKES = false>
 __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, const int p, const int g,
                                              const OutArgs* o = nullptr) {
-  constexpr int NT = UB * FB * L / (4 * SQ);
-  constexpr int TPS = L / 8;                       // threads per row sequence
+  constexpr bool WIDE = L >= 1024;
+  static_assert(!WIDE || SQ == 1, "one wide row per thread");
+  constexpr int PT = WIDE ? 16 : 8;                 // points per thread and sequence
+  constexpr int NT = rowpass_threads<L, UB, FB, SQ>();
+  constexpr int TPS = L / PT;                      // threads per row sequence
   constexpr int NCH = UB * L < NT ? UB * L : NT;   // threads that own channel slots
   constexpr int SPT = (UB * L) / NCH;              // channel slots per owning thread
   constexpr int FS = FB / SQ;                      // frame stride between a thread's sequences
@@ -312,8 +322,10 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
 #pragma unroll
   for (int j = 0; j < SQ; ++j) seq[j] = buf + ((ub * FB + fs + j * FS) * 2 + rr) * SEQ;
 
-  PassTw<L> tw;
+  using Tw = typename std::conditional<WIDE, WideTw<L>, PassTw<L>>::type;
+  Tw tw;
   tw.load(a.tw_row, ts);
+
 
   // this slot's frames of the launch: f = f_first + j G, j < n_loc (absolute frame a = F0 + f, a mod G = g)
   const int f_first = (int)(((int64_t)g - a.F0 % a.G + a.G) % a.G);
@@ -341,18 +353,24 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
   const int64_t fstride = (int64_t)a.P * a.N1 * L;  // float2 per frame
   const float2* src = a.T + ((int64_t)p * a.N1 + row) * (int64_t)L + ts;
   // local frames past the end repeat the last one (their products are never accumulated)
-  auto fetch = [&](float2 (&d)[SQ][8], int f0) {
+  auto fetch = [&](float2 (&d)[SQ][PT], int f0) {
 #pragma unroll
     for (int j = 0; j < SQ; ++j) {
       const float2* pj = src + (int64_t)(f_first + min(f0 + fs + j * FS, n_loc - 1) * a.G) * fstride;
+      if constexpr (WIDE) {
 #pragma unroll
-      for (int i = 0; i < 8 / R0; ++i)
+        for (int k = 0; k < PT; ++k) d[j][k] = pj[k * TPS];
+      } else {
 #pragma unroll
-        for (int r = 0; r < R0; ++r) d[j][i * R0 + r] = pj[i * (L / 8) + r * (L / R0)];
+        for (int i = 0; i < 8 / R0; ++i)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) d[j][i * R0 + r] = pj[i * (L / 8) + r * (L / R0)];
+      }
     }
   };
-  auto batch = [&](float2 (&v)[SQ][8], int f0) {
-    row_chain<L, SQ, 0>(v, ts, tw, seq);
+  auto batch = [&](float2 (&v)[SQ][PT], int f0) {
+    if constexpr (WIDE) wide_chain<L>(v[0], ts, tw, seq[0]);
+    else row_chain<L, SQ, 0>(v, ts, tw, seq);
     __syncthreads();
     if (owner) {
       const int nf = min(FB, n_loc - f0);
@@ -384,7 +402,7 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
   // Both prefetches are unconditional (past the end they re-read the last frame, which is never
   // accumulated): each batch then waits only for its own loads, with the next batch's still in flight.
   // A prefetch skipped on some path made every first batch of the pair wait for both.
-  float2 va[SQ][8], vb[SQ][8];
+  float2 va[SQ][PT], vb[SQ][PT];
   fetch(va, 0);
   for (int f0 = 0; f0 < n_loc; f0 += 2 * FB) {
     fetch(vb, f0 + FB);
@@ -417,7 +435,7 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
 }
 
 template <int L, int UB, int FB, int SQ>
-__global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
+__global__ void __launch_bounds__((rowpass_threads<L, UB, FB, SQ>())) k_rowpass(RowArgs a) {
   rowpass_tile<L, UB, FB, SQ>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z);
 }
 
@@ -425,14 +443,14 @@ __global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass(RowArgs a) {
 // (channel k2 N1 + row), so the units are renumbered to keep runs of consecutive rows on one XCD: the 4-byte
 // writes of neighbouring rows then meet in that XCD's L2 and leave it as whole sectors.
 template <int L, int UB, int FB, int SQ>
-__global__ void __launch_bounds__(UB * FB * L / (4 * SQ)) k_rowpass_stokes(RowArgs a, OutArgs o) {
+__global__ void __launch_bounds__((rowpass_threads<L, UB, FB, SQ>())) k_rowpass_stokes(RowArgs a, OutArgs o) {
   const int nbx = (int)gridDim.x;
   const int lin = xcd_remap((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
   rowpass_tile<L, UB, FB, SQ, true>(a, lin % nbx, lin / nbx, 0, &o);
 }
 
 template <int L, int UB, int FB, int SQ>
-__global__ void __launch_bounds__(UB * FB * L / (4 * SQ))
+__global__ void __launch_bounds__((rowpass_threads<L, UB, FB, SQ>()))
     k_rowpass_batch(const RowArgs* __restrict__ tasks, const int32_t* __restrict__ tile_end, int n_tasks) {
   const int tile = (int)blockIdx.x;
   const int t = batch_task(tile_end, n_tasks, tile);
@@ -668,7 +686,7 @@ hipError_t launch_colpass(int N1, int cols, int bits, int mode, const ColArgs& a
 
 template <int L, int UB, int FB, int SQ>
 static hipError_t rowpass_launch(const RowArgs& a, const Launch& s, const OutArgs* o) {
-  const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P, (unsigned)a.G), block(UB * FB * L / (4 * SQ));
+  const dim3 grid((unsigned)(a.N1 / 2 / UB), (unsigned)a.P, (unsigned)a.G), block(rowpass_threads<L, UB, FB, SQ>());
   if (o) {
     if (a.G != 1) return hipErrorInvalidValue;
     PS_LAUNCH((k_rowpass_stokes<L, UB, FB, SQ>), grid, block, s, a, *o);
@@ -699,8 +717,8 @@ hipError_t launch_rowpass(int N2, int fb, const RowArgs& a, const Launch& s, con
     case 128: return rowpass_launch<128, 2, 8, 2>(a, s, o);
     case 256: return rowpass_launch<256, 1, 8, SQ>(a, s, o);
     case 512: return rowpass_launch<512, 1, 8, SQ>(a, s, o);
-    case 1024: return rowpass_launch<1024, 1, 4, 2>(a, s, o);
-    case 2048: return rowpass_launch<2048, 1, 2, 2>(a, s, o);
+    case 1024: return rowpass_launch<1024, 1, 4, 1>(a, s, o);
+    case 2048: return rowpass_launch<2048, 1, 2, 1>(a, s, o);
     default: return hipErrorInvalidValue;
   }
 }
@@ -757,7 +775,7 @@ hipError_t launch_colpass_batch(int N1, int cols, int bits, int mode, const Batc
 
 template <int L, int UB, int FB, int SQ>
 static hipError_t rowpass_batch_launch(const BatchArgs& b, const Launch& s) {
-  constexpr int block = UB * FB * L / (4 * SQ);
+  constexpr int block = rowpass_threads<L, UB, FB, SQ>();
   PS_LAUNCH_BATCH((k_rowpass_batch<L, UB, FB, SQ>), block, b.total, s,
                   static_cast<const RowArgs*>(b.tasks), b.tile_end, b.n_tasks);
   return hipGetLastError();
@@ -777,8 +795,8 @@ hipError_t launch_rowpass_batch(int N2, int fb, const BatchArgs& b, const Launch
     case 128: return rowpass_batch_launch<128, 2, 8, 2>(b, s);
     case 256: return rowpass_batch_launch<256, 1, 8, SQ>(b, s);
     case 512: return rowpass_batch_launch<512, 1, 8, SQ>(b, s);
-    case 1024: return rowpass_batch_launch<1024, 1, 4, 2>(b, s);
-    case 2048: return rowpass_batch_launch<2048, 1, 2, 2>(b, s);
+    case 1024: return rowpass_batch_launch<1024, 1, 4, 1>(b, s);
+    case 2048: return rowpass_batch_launch<2048, 1, 2, 1>(b, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -50,6 +50,38 @@ def test_every_candidate_matches_oracle(env, log2n, bits):
         assert e < 1e-5, s
 
 
+# rows of 1024 and 2048 points are held as 16 points per lane (passes of radix 8, 8 or 16, and 16): splits that put
+# 1024 or 2048 points in the row pass, through the plain, fused-Stokes and grouped row passes
+@pytest.mark.parametrize("log2n,log2n1,bits,F", [(19, 9, 8, 8), (20, 10, 2, 4), (20, 9, 8, 4), (19, 8, 2, 8)])
+def test_wide_rows_match_oracle(env, log2n, log2n1, bits, F):
+    torch, pk, dev = env
+    inst = synth.make_correlated_noise(bits, 0.3, 1 << log2n, F, seed_extra=log2n + 7)
+    acc, nf, s2, _ = oracle.run_instance(inst)
+    ref = oracle.stokes(acc, nf, s2)
+    packed = torch.from_numpy(inst["packed"]).to(dev)
+    say(f"N=2^{log2n} as 2^{log2n1} x 2^{log2n - log2n1}, bits={bits}, F={F}")
+    for slots in (1, 2):
+        plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev,
+                       schedules=[pk.Schedule(log2_n1=log2n1, rowpass_slots=slots)])
+        plan.reset()
+        got = plan.accumulate_stokes(packed)[0].cpu().numpy().astype(np.float64)
+        e = np.max(np.abs(got - ref)) / np.mean(ref[:, 0, :])
+        say(f"  slots={slots}: err {e:.2e}")
+        assert e < 1e-5
+    # two instances of this split in one grouped plan: the grouped row pass, bitwise as separate plans
+    other = synth.make_correlated_noise(bits, 0.1, 1 << log2n, F, seed_extra=log2n + 8)
+    p2 = torch.from_numpy(other["packed"]).to(dev)
+    sch = pk.Schedule(log2_n1=log2n1)
+    grp = pk.Plan([pk.Instance.from_synth(inst), pk.Instance.from_synth(other)], device=dev, schedules=[sch, sch])
+    grp.reset()
+    grp.accumulate([packed, p2])
+    for i, (d, buf) in enumerate(((inst, packed), (other, p2))):
+        one = pk.Plan([pk.Instance.from_synth(d)], device=dev, schedules=[sch])
+        one.reset()
+        one.accumulate(buf)
+        assert torch.equal(grp.spectra(i)[0], one.spectra()[0]), i
+
+
 def test_grouped_launches_honour_schedules(env):
     torch, pk, dev = env
     say("grouped plan with per-instance schedules")
