@@ -71,8 +71,8 @@ struct Dft<8> {
   }
 };
 
-// 16- and 32-point DFTs: even/odd split into two half-length DFTs, the odd half rotated by W_R^k
-// (W_32^k = exp(-2 pi i k / 32) rounded to FP32; W_16^k = W_32^(2k)).
+// 16-point DFT: even/odd split into two 8-point DFTs, the odd half rotated by W_16^k (W_32^k =
+// exp(-2 pi i k / 32) rounded to FP32, W_16^k = W_32^(2k); the table serves a 32-point split as well).
 struct W32 {
   static constexpr float c[16] = {1.0f,           9.807852804e-01f, 9.238795325e-01f, 8.314696123e-01f,
                                   7.071067812e-01f, 5.555702330e-01f, 3.826834324e-01f, 1.950903220e-01f,
@@ -114,8 +114,6 @@ struct DftSplit {
 };
 template <>
 struct Dft<16> : DftSplit<16> {};
-template <>
-struct Dft<32> : DftSplit<32> {};
 
 // ------------------------------------------------------------------------------------------------
 // Stockham schedule for a length-L sequence held as 8 points per thread (L/8 threads per sequence).
