@@ -235,6 +235,18 @@ def time_steps(torch, dev, fn, steps, warmup, warmup_s=0.05):
     return (time.perf_counter() - t0) / steps
 
 
+_PIPE = []
+
+
+def pipe_streams(torch, dev, n=2):
+    """The streams that take turns in every two-in-flight measurement, created once per process: streams
+    taken afresh from the runtime's pool may share a hardware queue, which runs their kernels one after the
+    other and hides the overlap being measured."""
+    while len(_PIPE) < n:
+        _PIPE.append(torch.cuda.Stream(dev))
+    return _PIPE[:n]
+
+
 def pipelined_time(torch, dev, plans, run_on, steps, warmup_s=0.05):
     """Seconds per integration with len(plans) integrations in flight: integration i is run_on(plans[i % d], i),
     enqueued on that plan's own stream (each plan holds its own workspace, so one integration's column pass
@@ -387,7 +399,7 @@ def precision_form(pk, torch, dev, steps, warmup, with_oracle=True):
     outs2 = [out, torch.empty_like(out)]
     bufs = [packed, packed2]
     for prec, accum in (("fp16", "kahan32"), ("bf16", "kahan32"), ("fp32", "fp64")):
-        streams = [torch.cuda.Stream(dev) for _ in range(2)]
+        streams = pipe_streams(torch, dev)
         plans2 = [pk.Plan([pk.Instance.from_synth(inst, precision=prec, accum=accum, chunk_frames=128)],
                           device=dev, stream=st) for st in streams]
 
@@ -432,7 +444,7 @@ def batching_form(pk, torch, dev, reps):
         packed.append(buf)
     samples = int(sum(int(F[i]) * (1 << int(e[i])) * 2 for i in range(64)))
     outs = [torch.empty((1, 4, I.channels), dtype=torch.float32, device=dev) for I in insts]
-    side = torch.cuda.Stream(dev)
+    side, side2 = pipe_streams(torch, dev)
     with torch.cuda.stream(side):
         sep = [pk.Plan([I], device=dev, stream=side) for I in insts]
         grp = pk.Plan(insts, device=dev, stream=side)
@@ -466,7 +478,6 @@ def batching_form(pk, torch, dev, reps):
     t_graph = timed(grp.graph_replay)
     # two integrations in flight: a second grouped plan on its own stream, with its own copies of the inputs
     # and outputs, replays its own graph; the two graphs alternate
-    side2 = torch.cuda.Stream(dev)
     with torch.cuda.stream(side2):
         packed2 = [b.clone() for b in packed]
         outs2 = [torch.empty_like(o) for o in outs]
@@ -565,7 +576,7 @@ def power_form(pk, torch, dev, inst, packed, steps):
 def _ring_integrations(pk, torch, dev, inst, ring, steps, warmup=3):
     """Whole integrations (reset, accumulate, Stokes of every pair) of an instance, each from the next
     HBM-resident buffer of a ring; returns the mean time per integration and per-kernel averages."""
-    side = torch.cuda.Stream(dev)
+    side, st2 = pipe_streams(torch, dev)
     with torch.cuda.stream(side):
         plan = pk.Plan([pk.Instance.from_synth(inst)], device=dev, stream=side)
         out = torch.empty((len(inst["pairs"]), 4, inst["fft_len"] // 2), dtype=torch.float32, device=dev)
@@ -588,7 +599,6 @@ def _ring_integrations(pk, torch, dev, inst, ring, steps, warmup=3):
     plan.profile_enable(False)
     kern = {k: {"launches": n / steps, "avg_us": ms / n * 1e3} for k, (ms, n) in prof.items()}
     # two integrations in flight (a second plan on its own stream with its own output takes every other one)
-    st2 = torch.cuda.Stream(dev)
     with torch.cuda.stream(st2):
         plan2 = pk.Plan([pk.Instance.from_synth(inst)], device=dev, stream=st2)
         out2 = torch.empty_like(out)
@@ -792,7 +802,7 @@ def main():
     # (inter-pass buffer and accumulators) on its own stream, so one integration's column pass overlaps the
     # previous one's row pass and Stokes output.
     depth = max(1, args.depth)
-    streams = [torch.cuda.Stream(dev) for _ in range(depth)]
+    streams = pipe_streams(torch, dev, depth)
     side = streams[0]
     with torch.cuda.stream(side):
         ring = [packed.clone() for _ in range(max(1, args.ring))]

@@ -270,7 +270,6 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
       __syncthreads();
       // ---- stage B and the four-step twiddle
       const uint32_t* Tf = a.T + ((int64_t)__builtin_amdgcn_readfirstlane(f) * c.P + p) * (int64_t)N1 * N2;
-      const __amdgpu_buffer_rsrc_t rout = buffer_rsrc(Tf, (uint32_t)(N1 * N2 * 4));
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int kap = w + 4 * t;
@@ -283,8 +282,10 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
           for (int i = 0; i < 4; ++i) {
             // k1 = kap + 16 (H (4g + i) + h): lane part 16 H 4g, uniform part kap + 16 (H i + h)
             const float2 v = cmul(make_float2(o[0][i], o[1][i]), cmul(t1[t], t2[h][i]));
-            __builtin_amdgcn_raw_buffer_store_b32(pk<PREC>(v.x, v.y), rout, lane_o,
-                                                  (uint32_t)((kap + 16 * (H * i + h)) * N2 * 4), 0);
+            // global stores (the next kernel reads the buffer from every XCD), frame base and row offset in
+            // scalar registers, the lane's offset one 32-bit register
+            const gbytes ob = uniform_gptr(reinterpret_cast<const uint8_t*>(Tf + (kap + 16 * (H * i + h)) * N2));
+            *(__attribute__((address_space(1))) uint32_t*)(ob + lane_o) = pk<PREC>(v.x, v.y);
           }
         }
       }
