@@ -981,8 +981,8 @@ ps_status ps_plan_scheduled(const ps_instance* inst, const ps_schedule* sched, i
       I.off_sumacc = off; off = align_up(off + I.slot_doubles() * 8);
       I.off_sumpart = off; off = align_up(off + (size_t)ps::slot_reduce_chunks(I.G) * I.slot_doubles() * 8);
     }
-    const size_t U = (size_t)(I.N1 / 2), P = (size_t)I.cfg.n_pairs;
-    I.off_red = off; off = align_up(off + P * U * 5 * sizeof(double));
+    const size_t P = (size_t)I.cfg.n_pairs;
+    I.off_red = off; off = align_up(off + P * (size_t)ps::bw_parts((int)I.N1, (int)I.N2) * 5 * sizeof(double));
     I.off_norm = off; off = align_up(off + P * sizeof(double));
     if (I.taps()) {
       I.off_wpart = off; off = align_up(off + (size_t)ps::window_taps_blocks(I.N) * sizeof(double));
@@ -1444,6 +1444,7 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
   ca.d_dterms = grad->d_dterms;
   ca.g_a = want_taps ? ws_ptr<float>(plan, I.off_ga) : nullptr;
   ca.red = ws_ptr<double>(plan, I.off_red);
+  ca.parts = ps::bw_parts((int)I.N1, (int)I.N2);
   ca.norm = ws_ptr<double>(plan, I.off_norm);
   // with the one-pass tap gradient, that kernel also reduces the channel kernel's unit partials
   const bool taps_reduce = want_taps && ps::bw_taps_block_form(I.N, I.cfg.n_taps);
@@ -1538,7 +1539,7 @@ ps_status ps_calibrate_backward(ps_plan_t plan, int32_t inst, const void* packed
   ta.d_taps = grad->d_taps;
   ta.part = ws_ptr<double>(plan, I.off_tpart);
   ta.red = ca.red;
-  ta.U = (int32_t)(I.N1 / 2);
+  ta.U = ca.parts;
   ta.d_dterms = taps_reduce ? grad->d_dterms : nullptr;
   e = timed(plan, PS_KERNEL_BACKWARD, [&](const ps::Launch& l) { return ps::launch_bw_taps(ta, l); });
   if (e != hipSuccess) return hip_fail(e, "tap gradient launch");

@@ -93,11 +93,18 @@ __device__ __forceinline__ cm2 madd(const cm2& x, const cm2& y) {
 
 constexpr int kBwRed = 5;  // block partials: Re/Im Gb(d_x), Re/Im Gb(d_y), Re tr(Gb(M)^H M)
 
+// One wave per 64 channel slots of a unit (workgroups of 64 threads, so that every CU takes part: one
+// workgroup per unit left half the device idle); the wave's partials are added by a fixed tree and written
+// as partial (unit, quarter) of the pair: bw_parts(N1, L) = N1/2 * max(1, L/64) partials per pair.
+constexpr int kBwChanThreads = 64;
+
 template <int L>
-__global__ void __launch_bounds__(L) k_bw_channel(BwChanArgs a) {
-  __shared__ double red[kBwRed][L];
+__global__ void __launch_bounds__(kBwChanThreads) k_bw_channel(BwChanArgs a) {
+  constexpr int NQ = L > kBwChanThreads ? L / kBwChanThreads : 1, TPB = L < kBwChanThreads ? L : kBwChanThreads;
+  __shared__ double red[kBwRed][TPB];
   const int U = a.N1 / 2;
-  const int u = (int)blockIdx.x, p = (int)blockIdx.y, s = (int)threadIdx.x;
+  const int u = (int)blockIdx.x / NQ, qq = (int)blockIdx.x % NQ, p = (int)blockIdx.y;
+  const int s = qq * TPB + (int)threadIdx.x;
   const int half = s / (L / 2), k2 = s % (L / 2);
   const int row = (u == 0) ? (half ? a.N1 / 2 : 0) : (half ? a.N1 - u : u);
   const int64_t k = (int64_t)row + (int64_t)a.N1 * k2;
@@ -162,25 +169,26 @@ __global__ void __launch_bounds__(L) k_bw_channel(BwChanArgs a) {
   }
   const double nt = GM.a.x * M.a.x + GM.a.y * M.a.y + GM.b.x * M.b.x + GM.b.y * M.b.y + GM.c.x * M.c.x +
                     GM.c.y * M.c.y + GM.d.x * M.d.x + GM.d.y * M.d.y;
-  red[0][s] = GJ.b.x;
-  red[1][s] = GJ.b.y;
-  red[2][s] = GJ.c.x;
-  red[3][s] = GJ.c.y;
-  red[4][s] = nt;
+  const int t = (int)threadIdx.x;
+  red[0][t] = GJ.b.x;
+  red[1][t] = GJ.b.y;
+  red[2][t] = GJ.c.x;
+  red[3][t] = GJ.c.y;
+  red[4][t] = nt;
   __syncthreads();
-  for (int h = L / 2; h > 0; h >>= 1) {
-    if (s < h)
-      for (int r = 0; r < kBwRed; ++r) red[r][s] += red[r][s + h];
+  for (int h = TPB / 2; h > 0; h >>= 1) {
+    if (t < h)
+      for (int r = 0; r < kBwRed; ++r) red[r][t] += red[r][t + h];
     __syncthreads();
   }
-  if (s < kBwRed) a.red[((int64_t)p * U + u) * kBwRed + s] = red[s][0];
+  if (t < kBwRed) a.red[(((int64_t)p * U + u) * NQ + qq) * kBwRed + t] = red[t][0];
 }
 
 // per pair: leakage gradients and the normaliser term.  Lane t sums the units t, t + 64, ... (in order), then
 // the 64 lanes' sums are added pairwise in a fixed tree, so the result does not depend on timing.
 __global__ void __launch_bounds__(64) k_bw_reduce(BwChanArgs a) {
   __shared__ double sh[kBwRed][64];
-  const int U = a.N1 / 2, p = (int)blockIdx.x, t = (int)threadIdx.x;
+  const int U = a.parts, p = (int)blockIdx.x, t = (int)threadIdx.x;  // U: the pair's partials
   double v[kBwRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int u = t; u < U; u += 64)
 #pragma unroll
@@ -582,12 +590,15 @@ int window_taps_blocks(int64_t N) {
 
 template <int L>
 static hipError_t bw_channel_launch(const BwChanArgs& a, const Launch& l, bool with_reduce) {
-  PS_LAUNCH((k_bw_channel<L>), dim3((unsigned)(a.N1 / 2), (unsigned)a.P), dim3(L), l, a);
+  constexpr int NQ = L > kBwChanThreads ? L / kBwChanThreads : 1, TPB = L < kBwChanThreads ? L : kBwChanThreads;
+  PS_LAUNCH((k_bw_channel<L>), dim3((unsigned)(a.N1 / 2 * NQ), (unsigned)a.P), dim3(TPB), l, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !with_reduce) return e;
   hipLaunchKernelGGL(k_bw_reduce, dim3((unsigned)a.P), dim3(64), 0, l.stream, a);
   return hipGetLastError();
 }
+
+int bw_parts(int N1, int N2) { return N1 / 2 * (N2 > kBwChanThreads ? N2 / kBwChanThreads : 1); }
 
 hipError_t launch_bw_channel(int N2, const BwChanArgs& a, const Launch& l, bool with_reduce) {
   switch (N2) {

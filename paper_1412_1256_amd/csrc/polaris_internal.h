@@ -128,7 +128,8 @@ struct BwChanArgs {         // per-channel adjoint of Eq. 2 and the calibration
   float* d_gain_y;
   float* d_dterms;          // [P][4], or nullptr
   float* g_a;               // [P][N1/2][4][N2] Gb(A) (00, 11, Re 01, Im 01), or nullptr
-  double* red;              // [P][N1/2][5] unit partials
+  double* red;              // [P][parts][5] partials of the units' channel slots (bw_parts per pair)
+  int32_t parts;            // partials per pair
   double* norm;             // [P] Re tr(Gb(M)^H M)
 };
 
@@ -162,7 +163,7 @@ struct BwTapArgs {          // tap gradient
   // one-pass form: the channel kernel's per-unit partials [P][U][5], reduced here (normaliser; leakage
   // gradients into d_dterms [P][4] when not nullptr)
   const double* red;
-  int32_t U;
+  int32_t U;                // partials per pair in red
   float* d_dterms;
 };
 
@@ -208,6 +209,7 @@ hipError_t launch_window_taps(const WinArgs& a, int n_blocks, double* sumw2, con
 // it, the one-pass tap gradient reduces them
 hipError_t launch_bw_channel(int N2, const BwChanArgs& a, const Launch& l, bool with_reduce = true);
 hipError_t launch_bw_rowpass(int N2, const BwRowArgs& a, const Launch& l);
+int bw_parts(int N1, int N2);  // partials per pair of the per-channel adjoint
 hipError_t launch_bw_colpass(int N1, int bits, bool fast, const BwColArgs& a, const Launch& l);
 hipError_t launch_bw_taps(const BwTapArgs& a, const Launch& l);
 bool bw_taps_block_form(int64_t N, int n_taps);  // the one-pass tap gradient applies (else two kernels)
