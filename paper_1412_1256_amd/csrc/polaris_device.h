@@ -387,15 +387,33 @@ __device__ __forceinline__ void col_chain(float2 (&v)[V][8], int ts, int cv, con
       }
     __syncthreads();
     constexpr int R2 = SC::radix(P + 1);
+    if constexpr (V == 2) {
+      // 16-byte reads of both columns; each kept whole (the empty asm takes the vector as one operand), as the
+      // compiler otherwise splits some into 8-byte pairs whose lane pattern conflicts on the LDS banks
+      f32x4 q[8];
 #pragma unroll
-    for (int i = 0; i < 8 / R2; ++i)
+      for (int i = 0; i < 8 / R2; ++i)
 #pragma unroll
-      for (int r = 0; r < R2; ++r) {
-        float2 w[V];
-        tile_load<V>(tile, pin<L, R2>(ts, i, r) * COLS + cv * V, w);
+        for (int r = 0; r < R2; ++r)
+          q[i * R2 + r] = *reinterpret_cast<const f32x4*>(tile + pin<L, R2>(ts, i, r) * COLS + cv * V);
+      __builtin_amdgcn_sched_barrier(0);  // all eight reads issued before the first is waited for
 #pragma unroll
-        for (int c = 0; c < V; ++c) v[c][i * R2 + r] = w[c];
+      for (int e = 0; e < 8; ++e) {
+        asm("" : "+v"(q[e]));
+        v[0][e] = make_float2(q[e].x, q[e].y);
+        v[1][e] = make_float2(q[e].z, q[e].w);
       }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8 / R2; ++i)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+          float2 w[V];
+          tile_load<V>(tile, pin<L, R2>(ts, i, r) * COLS + cv * V, w);
+#pragma unroll
+          for (int c = 0; c < V; ++c) v[c][i * R2 + r] = w[c];
+        }
+    }
     if constexpr (NB == 1) __syncthreads();
     col_chain<L, COLS, V, NB, P + 1>(v, ts, cv, tw, tiles);
   }
