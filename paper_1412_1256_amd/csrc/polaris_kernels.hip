@@ -310,7 +310,16 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
   constexpr int SEQ = L;                           // sequence length in LDS
   using SC = Sched<L>;
   constexpr int R0 = SC::R0;
-  __shared__ __align__(16) float2 buf[UB * FB * 2 * SEQ];
+  // Long rows keep two LDS buffers, taken by the batches in turn: a batch's transform then writes the buffer
+  // the previous batch's channel stage may still be reading only once every thread has passed the barrier
+  // that follows the previous batch's last pass, so no barrier is needed after the channel stage (and rows of
+  // two waves also take their middle pass to the other buffer, one barrier per exchange).  Rows of 512
+  // points in batches of 4 frames still fit two workgroups per CU with both buffers.
+  // The two buffers are interleaved by row (row q of buffer b at (2 q + b) L), so a row's place in either
+  // buffer is within the reach of an LDS instruction's immediate offset from the same address register.
+  constexpr bool ALT = WIDE || (L == 512 && UB * FB <= 4);
+  constexpr int RS = (ALT ? 2 : 1) * SEQ;  // LDS stride between rows
+  __shared__ __align__(16) float2 buf[UB * FB * 2 * RS];
   const int tid = (int)threadIdx.x;
   const int U = a.N1 / 2;
   // transform role: slot ts of row rr of frames fs + j FS (j < SQ) of unit ub
@@ -320,7 +329,7 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
   const int row = (u == 0) ? (rr ? a.N1 / 2 : 0) : (rr ? a.N1 - u : u);
   float2* seq[SQ];
 #pragma unroll
-  for (int j = 0; j < SQ; ++j) seq[j] = buf + ((ub * FB + fs + j * FS) * 2 + rr) * SEQ;
+  for (int j = 0; j < SQ; ++j) seq[j] = buf + ((ub * FB + fs + j * FS) * 2 + rr) * RS;
 
   using Tw = typename std::conditional<WIDE, WideTw<L>, PassTw<L>>::type;
   Tw tw;
@@ -368,9 +377,13 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
       }
     }
   };
-  auto batch = [&](float2 (&v)[SQ][PT], int f0) {
-    if constexpr (WIDE) wide_chain<L>(v[0], ts, tw, seq[0]);
-    else row_chain<L, SQ, 0>(v, ts, tw, seq);
+  auto batch = [&](float2 (&v)[SQ][PT], int f0, const int par) {
+    const int bo = ALT ? par * SEQ : 0;  // this batch's buffer
+    float2* sq[SQ];
+#pragma unroll
+    for (int j = 0; j < SQ; ++j) sq[j] = seq[j] + bo;
+    if constexpr (WIDE) wide_chain<L>(v[0], ts, tw, sq[0], ALT ? seq[0] + (SEQ - bo) : nullptr);
+    else row_chain<L, SQ, 0>(v, ts, tw, sq);
     __syncthreads();
     if (owner) {
       const int nf = min(FB, n_loc - f0);
@@ -383,11 +396,11 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
         // bin (row, k2) pairs with bin N - k: rows k1 and N1 - k1 swap, k2 -> N2 - 1 - k2; row 0 -> N2 - k2
         const int phalf = (uc == 0) ? half : 1 - half;
         const int pk2 = (uc == 0 && half == 0) ? ((L - k2) & (L - 1)) : (L - 1 - k2);
-        const float2* fa = buf + (ubc * FB * 2 + half) * SEQ + swz(k2);
-        const float2* fb = buf + (ubc * FB * 2 + phalf) * SEQ + swz(pk2);
+        const float2* fa = buf + bo + (ubc * FB * 2 + half) * RS + swz(k2);
+        const float2* fb = buf + bo + (ubc * FB * 2 + phalf) * RS + swz(pk2);
         for (int g = 0; g < nf; ++g) {
-          const float2 A = fa[g * 2 * SEQ];
-          const float2 B = fb[g * 2 * SEQ];
+          const float2 A = fa[g * 2 * RS];
+          const float2 B = fb[g * 2 * RS];
           const float sx_ = A.x + B.x, sy_ = A.y - B.y;   // A + conj(B) = 2 X
           const float dx_ = A.x - B.x, dy_ = A.y + B.y;   // A - conj(B) = 2i Y
           sxx[k] += (double)(sx_ * sx_ + sy_ * sy_);
@@ -397,7 +410,8 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
         }
       }
     }
-    __syncthreads();
+    if constexpr (!ALT) __syncthreads();
+    else __builtin_amdgcn_sched_barrier(0);  // keeps the next batch's transform after this channel stage
   };
   // Both prefetches are unconditional (past the end they re-read the last frame, which is never
   // accumulated): each batch then waits only for its own loads, with the next batch's still in flight.
@@ -406,9 +420,9 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
   fetch(va, 0);
   for (int f0 = 0; f0 < n_loc; f0 += 2 * FB) {
     fetch(vb, f0 + FB);
-    batch(va, f0);
+    batch(va, f0, 0);
     fetch(va, f0 + 2 * FB);
-    if (f0 + FB < n_loc) batch(vb, f0 + FB);
+    if (f0 + FB < n_loc) batch(vb, f0 + FB, 1);
   }
   if (owner) {
 #pragma unroll
