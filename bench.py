@@ -318,8 +318,16 @@ def differentiation_form(pk, torch, dev, steps, warmup):
     t_fwd = time_steps(torch, dev, fwd, steps, warmup)
     t_fb = time_steps(torch, dev, fwd_bwd, steps, warmup)
     t_fbr = time_steps(torch, dev, fwd_bwd_recompute, steps, warmup)
+    # the backward alone (forward + backward less the forward) against its algorithmic bytes: the adjoint row
+    # pass reads the inter-pass buffer and writes its adjoint (8 + 8 B per complex point), the adjoint column
+    # pass reads that and the packed samples once (8 + S bits/8 B), and the channel adjoint reads the FP64
+    # accumulators and the upstream gradient and writes the per-channel terms (32 + 16 + 16 B per channel)
+    t_bwd = t_fb - t_fwd
+    bwd_bytes = F * N * (8 + 8 + 8) + F * N * S * inst["bits"] / 8 + (N // 2) * (32 + 16 + 16)
     return {"workload": "2 int8 pols, 2^16-pt frames, 128 frames (0.524 s), learnable gains, leakage and 64 taps",
             "plain_us": t_plain * 1e6, "fwd_us": t_fwd * 1e6, "fwd_bwd_us": t_fb * 1e6,
+            "bwd_us": t_bwd * 1e6, "bwd_alg_bytes": bwd_bytes, "bwd_GBps": bwd_bytes / t_bwd / 1e9,
+            "bwd_frac_hbm": bwd_bytes / t_bwd / 1e9 / HBM_PEAK_GBS,
             "fwd_bwd_recompute_us": t_fbr * 1e6, "fwd_bwd_recompute_vs_fwd": t_fbr / t_fwd,
             "fwd_bwd_vs_plain": t_fb / t_plain, "fwd_bwd_vs_fwd": t_fb / t_fwd,
             "fwd_bwd_Gsamples_per_s": samples / t_fb / 1e9, "fwd_bwd_x_realtime": F * N / SAMPLE_RATE / t_fb}

@@ -497,7 +497,16 @@ __global__ void __launch_bounds__(kWinThreads) k_allan_window(AllanArgs a) {
     }
     int k0 = 0;                // slot of row r0
     int bt = kWinRing - lmax;  // slot of row r0 - lmax (lmax <= kWinMaxLag < kWinRing)
-    auto step = [&](const int r0, f2& d) {
+    // the point t = r0 - lmax + q of step r0 counts for lag L when L <= t < P - L: every point of the step
+    // counts for every lag of this half (the same for every lane) in a contiguous middle range of steps
+    auto step_all = [&](const int r0) {
+      bool all = true;
+#pragma unroll
+      for (int l = 0; l < kWinHalfLags; ++l)
+        all = all && Lh[l] >= 1 && r0 - lmax >= Lh[l] && r0 - lmax + kWinStep - 1 < P - Lh[l];
+      return all;
+    };
+    auto step = [&](const int r0, f2& d, auto masked) {
       __syncthreads();  // every thread is done with the previous step's rows
       {
         if (!(pin && r0 + q < P)) d = f2{0.f, 0.f};
@@ -517,40 +526,50 @@ __global__ void __launch_bounds__(kWinThreads) k_allan_window(AllanArgs a) {
       }
       fetch(d, r0 + kWinAhead * kWinStep + q);
       __syncthreads();
-      // the point t = r0 - lmax + q counts for lag L when L <= t < P - L
       const int t = r0 - lmax + q;
       const f4 b = rd(bt + q);
       const double xb[4] = {b.x, b.y, b.z, b.w};
-      bool all = true;  // every point of the step counts for every lag of this half (the same for every lane)
 #pragma unroll
-      for (int l = 0; l < kWinHalfLags; ++l)
-        all = all && Lh[l] >= 1 && r0 - lmax >= Lh[l] && r0 - lmax + kWinStep - 1 < P - Lh[l];
-      auto terms = [&](const bool masked) {
+      for (int l = 0; l < kWinHalfLags; ++l) {
+        const f4 ua = rd(wrap(bt + Lh[l]) + q);
+        const f4 dc = rd((bt >= Lh[l] ? bt - Lh[l] : bt - Lh[l] + kWinRing) + q);
+        const double xa[4] = {ua.x, ua.y, ua.z, ua.w}, xc[4] = {dc.x, dc.y, dc.z, dc.w};
+        const bool use = !decltype(masked)::value || (Lh[l] >= 1 && t >= Lh[l] && t < P - Lh[l]);
 #pragma unroll
-        for (int l = 0; l < kWinHalfLags; ++l) {
-          const f4 ua = rd(wrap(bt + Lh[l]) + q);
-          const f4 dc = rd((bt >= Lh[l] ? bt - Lh[l] : bt - Lh[l] + kWinRing) + q);
-          const double xa[4] = {ua.x, ua.y, ua.z, ua.w}, xc[4] = {dc.x, dc.y, dc.z, dc.w};
-          const bool use = !masked || (Lh[l] >= 1 && t >= Lh[l] && t < P - Lh[l]);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const double dd = xa[c] - 2.0 * xb[c] + xc[c];
-            const double e = use ? dd : 0.0;  // an exact zero term outside the lag's range
-            S[l][c] = fma(e, e, S[l][c]);
-          }
+        for (int c = 0; c < 4; ++c) {
+          const double dd = xa[c] - 2.0 * xb[c] + xc[c];
+          const double e = use ? dd : 0.0;  // an exact zero term outside the lag's range
+          S[l][c] = fma(e, e, S[l][c]);
         }
-      };
-      if (all) terms(false);  // the bulk of the steps: no range test
-      else terms(true);
+      }
       k0 = wrap(k0 + kWinStep);
       bt = wrap(bt + kWinStep);
     };
     // Every step of an unrolled group runs: a step past the last point writes zero rows and adds exact
     // zeros (its points are out of every lag's range), and no load then sits behind a branch, so each step
     // waits only for its own rows while the later steps' loads stay in flight.
-    for (int r0 = 0; r0 < P + lmax; r0 += kWinAhead * kWinStep) {
+    // Three loops over the step groups: those before the middle range, the middle range (no range test), and
+    // those after it; each loop then has one definition of the sums (a test inside one loop had the compiler
+    // copy all sixteen FP64 sums on every step).
+    constexpr int GS = kWinAhead * kWinStep;  // rows per step group
+    auto group_all = [&](const int r0) {
+      bool all = true;
 #pragma unroll
-      for (int u = 0; u < kWinAhead; ++u) step(r0 + u * kWinStep, pre[u]);
+      for (int u = 0; u < kWinAhead; ++u) all = all && step_all(r0 + u * kWinStep);
+      return all;
+    };
+    int r0 = 0;
+    for (; r0 < P + lmax && !group_all(r0); r0 += GS) {
+#pragma unroll
+      for (int u = 0; u < kWinAhead; ++u) step(r0 + u * kWinStep, pre[u], std::true_type{});
+    }
+    for (; r0 < P + lmax && group_all(r0); r0 += GS) {
+#pragma unroll
+      for (int u = 0; u < kWinAhead; ++u) step(r0 + u * kWinStep, pre[u], std::false_type{});
+    }
+    for (; r0 < P + lmax; r0 += GS) {
+#pragma unroll
+      for (int u = 0; u < kWinAhead; ++u) step(r0 + u * kWinStep, pre[u], std::true_type{});
     }
     __syncthreads();  // the ring is free: it holds the phase sums from here on
     if (l0 == 0 && a.normalize) {  // series means: [2][phase][series] sums, added in phase order
