@@ -485,12 +485,14 @@ template <int L>
 struct WideTw {
   static constexpr int T = L / 16, R1 = L / 128;
   float2 w1[R1 - 1], w2[15];
-  __device__ __forceinline__ void load(const float2* __restrict__ table, int ts) {  // table: W_L^m, m < L
+  // table: W_(L ST)^m, m < L ST (ST = 2: the table of a transform twice as long)
+  template <int ST = 1>
+  __device__ __forceinline__ void load(const float2* __restrict__ table, int ts) {
     const int m1 = ts & 7, m2 = ts & (8 * R1 - 1);
 #pragma unroll
-    for (int r = 1; r < R1; ++r) w1[r - 1] = table[r * m1 * 16];  // W_(8 R1)^(r m1)
+    for (int r = 1; r < R1; ++r) w1[r - 1] = table[r * m1 * 16 * ST];  // W_(8 R1)^(r m1)
 #pragma unroll
-    for (int r = 1; r < 16; ++r) w2[r - 1] = table[r * m2];       // W_L^(r m2)
+    for (int r = 1; r < 16; ++r) w2[r - 1] = table[r * m2 * ST];       // W_L^(r m2)
   }
 };
 

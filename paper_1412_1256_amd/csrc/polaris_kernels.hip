@@ -301,6 +301,11 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
                                              const OutArgs* o = nullptr) {
   constexpr bool WIDE = L >= 1024;
   static_assert(!WIDE || SQ == 1, "one wide row per thread");
+  // 2048-point rows by decimation in time: wave h of a row transforms its samples 2 m + h (1024 points, 16
+  // per lane, exchanges within the wave), and the channel stage forms each bin from the two halves,
+  // Z[k] = E[k mod 1024] + W_2048^k O[k mod 1024]
+  constexpr bool DIT = L == 2048;
+  constexpr int LH = DIT ? L / 2 : L;  // points of the transform a wave group runs
   constexpr int PT = WIDE ? 16 : 8;                 // points per thread and sequence
   constexpr int NT = rowpass_threads<L, UB, FB, SQ>();
   constexpr int TPS = L / PT;                      // threads per row sequence
@@ -324,6 +329,7 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
   const int U = a.N1 / 2;
   // transform role: slot ts of row rr of frames fs + j FS (j < SQ) of unit ub
   const int ts = tid % TPS, q = tid / TPS;
+  const int hw = DIT ? ts / 64 : 0, tl = DIT ? ts % 64 : ts;  // half of the row and lane within it
   const int rr = q & 1, fs = (q >> 1) % FS, ub = (q >> 1) / FS;
   const int u = bx * UB + ub;
   const int row = (u == 0) ? (rr ? a.N1 / 2 : 0) : (rr ? a.N1 - u : u);
@@ -331,9 +337,10 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
 #pragma unroll
   for (int j = 0; j < SQ; ++j) seq[j] = buf + ((ub * FB + fs + j * FS) * 2 + rr) * RS;
 
-  using Tw = typename std::conditional<WIDE, WideTw<L>, PassTw<L>>::type;
+  using Tw = typename std::conditional<WIDE, WideTw<LH>, PassTw<L>>::type;
   Tw tw;
-  tw.load(a.tw_row, ts);
+  if constexpr (DIT) tw.template load<2>(a.tw_row, tl);
+  else tw.load(a.tw_row, ts);
 
 
   // this slot's frames of the launch: f = f_first + j G, j < n_loc (absolute frame a = F0 + f, a mod G = g)
@@ -359,8 +366,24 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
     }
   }
 
+  // decimation in time: each slot's twiddles W_2048^k2 and, for its partner bin, +-W_2048^(pk2 mod 1024)
+  float2 dwa[DIT ? SPT : 1], dwb[DIT ? SPT : 1];
+  if constexpr (DIT) {
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      const int id = tid + k * NCH;
+      const int ubc = id / L, s = id % L;
+      const int uc = bx * UB + ubc;
+      const int half = s / (L / 2), k2 = s % (L / 2);
+      const int pk2 = (uc == 0 && half == 0) ? ((L - k2) & (L - 1)) : (L - 1 - k2);
+      dwa[k] = a.tw_row[k2];
+      const float2 w = a.tw_row[pk2 & (LH - 1)];
+      dwb[k] = pk2 >= LH ? make_float2(-w.x, -w.y) : w;
+    }
+  }
+
   const int64_t fstride = (int64_t)a.P * a.N1 * L;  // float2 per frame
-  const float2* src = a.T + ((int64_t)p * a.N1 + row) * (int64_t)L + ts;
+  const float2* src = a.T + ((int64_t)p * a.N1 + row) * (int64_t)L + (DIT ? 2 * tl + hw : ts);
   // local frames past the end repeat the last one (their products are never accumulated)
   auto fetch = [&](float2 (&d)[SQ][PT], int f0) {
 #pragma unroll
@@ -382,7 +405,8 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
     float2* sq[SQ];
 #pragma unroll
     for (int j = 0; j < SQ; ++j) sq[j] = seq[j] + bo;
-    if constexpr (WIDE) wide_chain<L>(v[0], ts, tw, sq[0], ALT ? seq[0] + (SEQ - bo) : nullptr);
+    if constexpr (DIT) wide_chain<LH>(v[0], tl, tw, sq[0] + hw * LH);
+    else if constexpr (WIDE) wide_chain<L>(v[0], ts, tw, sq[0], ALT ? seq[0] + (SEQ - bo) : nullptr);
     else row_chain<L, SQ, 0>(v, ts, tw, sq);
     __syncthreads();
     if (owner) {
@@ -397,10 +421,19 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
         const int phalf = (uc == 0) ? half : 1 - half;
         const int pk2 = (uc == 0 && half == 0) ? ((L - k2) & (L - 1)) : (L - 1 - k2);
         const float2* fa = buf + bo + (ubc * FB * 2 + half) * RS + swz(k2);
-        const float2* fb = buf + bo + (ubc * FB * 2 + phalf) * RS + swz(pk2);
+        const float2* fb = buf + bo + (ubc * FB * 2 + phalf) * RS + swz(DIT ? pk2 & (LH - 1) : pk2);
         for (int g = 0; g < nf; ++g) {
-          const float2 A = fa[g * 2 * RS];
-          const float2 B = fb[g * 2 * RS];
+          float2 A, B;
+          if constexpr (DIT) {  // the bins from the even-sample (E) and odd-sample (O) halves of each row
+            const float2 ea = fa[g * 2 * RS], oa = fa[g * 2 * RS + LH];
+            const float2 eb = fb[g * 2 * RS], ob = fb[g * 2 * RS + LH];
+            const float2 ta = cmul(dwa[k], oa), tb = cmul(dwb[k], ob);
+            A = make_float2(ea.x + ta.x, ea.y + ta.y);
+            B = make_float2(eb.x + tb.x, eb.y + tb.y);
+          } else {
+            A = fa[g * 2 * RS];
+            B = fb[g * 2 * RS];
+          }
           const float sx_ = A.x + B.x, sy_ = A.y - B.y;   // A + conj(B) = 2 X
           const float dx_ = A.x - B.x, dy_ = A.y + B.y;   // A - conj(B) = 2i Y
           sxx[k] += (double)(sx_ * sx_ + sy_ * sy_);
