@@ -469,7 +469,13 @@ __global__ void __launch_bounds__(kWinThreads) k_allan_window(AllanArgs a) {
   // (the zeros are substituted when the pair enters the ring, so the load is not waited for until then)
   auto fetch = [&](f2& d, int r) { d = *reinterpret_cast<const f2*>(xl + (int64_t)(r < P ? r : P - 1) * st); };
   auto wrap = [](int k) { return k >= kWinRing ? k - kWinRing : k; };
-  auto rd = [&](int slot) { return *reinterpret_cast<const f4*>(&buf[slot * kWinSeries + 4 * g]); };
+  // ring slot X + q of this lane: a per-lane byte offset plus the wave-uniform X times the row bytes (one
+  // vector add per read)
+  const uint32_t lane_b = (uint32_t)(q * kWinSeries + 4 * g) * 4u;
+  auto rdq = [&](int x) {
+    const uint32_t off = lane_b + (uint32_t)__builtin_amdgcn_readfirstlane(x) * (kWinSeries * 4u);
+    return *reinterpret_cast<const f4*>(reinterpret_cast<const char*>(buf) + off);
+  };
   double xs[2] = {0, 0}, xn[2] = {0, 0};  // finite samples of the loaded series (normalisation), first sweep
   for (int l0 = 0; l0 < a.n_lags; l0 += kWinLags) {
     int L[kWinLags];
@@ -527,12 +533,12 @@ __global__ void __launch_bounds__(kWinThreads) k_allan_window(AllanArgs a) {
       fetch(d, r0 + kWinAhead * kWinStep + q);
       __syncthreads();
       const int t = r0 - lmax + q;
-      const f4 b = rd(bt + q);
+      const f4 b = rdq(bt);
       const double xb[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
       for (int l = 0; l < kWinHalfLags; ++l) {
-        const f4 ua = rd(wrap(bt + Lh[l]) + q);
-        const f4 dc = rd((bt >= Lh[l] ? bt - Lh[l] : bt - Lh[l] + kWinRing) + q);
+        const f4 ua = rdq(wrap(bt + Lh[l]));
+        const f4 dc = rdq(bt >= Lh[l] ? bt - Lh[l] : bt - Lh[l] + kWinRing);
         const double xa[4] = {ua.x, ua.y, ua.z, ua.w}, xc[4] = {dc.x, dc.y, dc.z, dc.w};
         const bool use = !decltype(masked)::value || (Lh[l] >= 1 && t >= Lh[l] && t < P - Lh[l]);
 #pragma unroll
