@@ -517,35 +517,19 @@ __device__ __forceinline__ void wide_pass(float2 (&v)[16], const WideTw<L>& tw, 
   }
 }
 
-// Rows of two waves exchange through a workgroup barrier.  With a second buffer (alt: the same row's place
-// in the other of two LDS buffers) the middle pass writes there: a pass then never overwrites what another
-// thread may still be reading, and each exchange needs one barrier, after its writes.
 template <int L>
-__device__ __forceinline__ void wide_chain(float2 (&v)[16], int ts, const WideTw<L>& tw, float2* __restrict__ seq,
-                                           float2* __restrict__ alt = nullptr) {
+__device__ __forceinline__ void wide_chain(float2 (&v)[16], int ts, const WideTw<L>& tw, float2* __restrict__ seq) {
   constexpr int T = L / 16;
   wide_pass<L, 0>(v, tw, ts, seq);
   exchange_sync<8 * T>();  // within the wave for one-wave rows, else a workgroup barrier
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = seq[swz(ts + k * T)];
-  float2* __restrict__ mid = seq;
-  if constexpr (T > 64) {
-    if (alt) mid = alt;
-    else exchange_sync<8 * T>();
-    __builtin_amdgcn_sched_barrier(0);
-  } else {
-    exchange_sync<8 * T>();
-  }
-  wide_pass<L, 1>(v, tw, ts, mid);
+  exchange_sync<8 * T>();
+  wide_pass<L, 1>(v, tw, ts, seq);
   exchange_sync<8 * T>();
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = mid[swz(ts + k * T)];
-  if constexpr (T > 64) {
-    if (!alt) exchange_sync<8 * T>();
-    __builtin_amdgcn_sched_barrier(0);
-  } else {
-    exchange_sync<8 * T>();
-  }
+  for (int k = 0; k < 16; ++k) v[k] = seq[swz(ts + k * T)];
+  exchange_sync<8 * T>();
   wide_pass<L, 2>(v, tw, ts, seq);
 }
 

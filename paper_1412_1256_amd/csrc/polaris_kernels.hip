@@ -317,9 +317,8 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
   constexpr int R0 = SC::R0;
   // Long rows keep two LDS buffers, taken by the batches in turn: a batch's transform then writes the buffer
   // the previous batch's channel stage may still be reading only once every thread has passed the barrier
-  // that follows the previous batch's last pass, so no barrier is needed after the channel stage (and rows of
-  // two waves also take their middle pass to the other buffer, one barrier per exchange).  Rows of 512
-  // points in batches of 4 frames still fit two workgroups per CU with both buffers.
+  // that follows the previous batch's last pass, so no barrier is needed after the channel stage.  Rows of
+  // 512 points in batches of 4 frames still fit two workgroups per CU with both buffers.
   // The two buffers are interleaved by row (row q of buffer b at (2 q + b) L), so a row's place in either
   // buffer is within the reach of an LDS instruction's immediate offset from the same address register.
   constexpr bool ALT = WIDE || (L == 512 && UB * FB <= 4);
@@ -406,7 +405,7 @@ __device__ __forceinline__ void rowpass_tile(const RowArgs& a, const int bx, con
 #pragma unroll
     for (int j = 0; j < SQ; ++j) sq[j] = seq[j] + bo;
     if constexpr (DIT) wide_chain<LH>(v[0], tl, tw, sq[0] + hw * LH);
-    else if constexpr (WIDE) wide_chain<L>(v[0], ts, tw, sq[0], ALT ? seq[0] + (SEQ - bo) : nullptr);
+    else if constexpr (WIDE) wide_chain<L>(v[0], ts, tw, sq[0]);
     else row_chain<L, SQ, 0>(v, ts, tw, sq);
     __syncthreads();
     if (owner) {
