@@ -249,6 +249,26 @@ def test_pure_tone_lands_in_one_channel(pk, torch_dev):
     assert abs(ph - (0.3 - 1.1)) < 1e-5
 
 
+@pytest.mark.parametrize("logn,k0", [(19, 54321), (20, 12345), (20, 512 * 700), (20, 256 + 512 * 77)])
+def test_pure_tone_long_rows(pk, torch_dev, logn, k0):
+    """Pure tones through the long rows (2^19: 512 x 1024, 2^20: 512 x 2048, whose rows are transformed as
+    two halves of even and odd samples): the closed-form peak in channel k0 and nothing elsewhere, including
+    tones on row 0 and row N1/2, where a bin pairs with its own row."""
+    torch, dev = torch_dev
+    say(f"pure tone 2^{logn} k0={k0}")
+    N, A = 1 << logn, 3.0
+    inst = synth.make_tone_f32(N, 2, k0, amp=A, phase=0.3, phase_y=1.1)
+    spec, nf, st = run_gpu(pk, torch, dev, inst)
+    peak = (A * N / 2) ** 2 * 2
+    err = abs(spec[0, 0, k0] - peak) / peak
+    others = np.delete(spec[0, 0], k0)
+    say(f"  peak err {err} leakage {np.max(others) / peak}")
+    assert err < 2e-6
+    assert np.max(others) < 1e-9 * peak
+    ph = math.atan2(spec[0, 3, k0], spec[0, 2, k0])
+    assert abs(ph - (0.3 - 1.1)) < 1e-5
+
+
 def test_split_calls_are_bitwise_identical(pk, torch_dev):
     torch, dev = torch_dev
     say("split calls")
