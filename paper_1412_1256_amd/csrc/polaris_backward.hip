@@ -112,13 +112,26 @@ __global__ void __launch_bounds__(kBwChanThreads) k_bw_channel(BwChanArgs a) {
   const double fs = a.n_frames * a.sumw2[0];
   // normalised coherency M (stored sums are 4 XX*, 4 YY*, 4 XY*)
   const double q = 0.25 / fs;
+  // the slots' sums, added in slot order; the loads are issued four slots at a time (one slot at a time, each
+  // add waiting for its load, the chain of round trips set the kernel's duration)
   double sum[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    double v = a.acc[slot + c * L];
-    for (int g = 1; g < a.slots; ++g) v += a.acc[(int64_t)g * a.slot_stride + slot + c * L];
-    sum[c] = v;
+  for (int c = 0; c < 4; ++c) sum[c] = a.acc[slot + c * L];
+  int sg = 1;
+  for (; sg + 4 <= a.slots; sg += 4) {
+    double v[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[j][c] = a.acc[(int64_t)(sg + j) * a.slot_stride + slot + c * L];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sum[c] += v[j][c];
   }
+  for (; sg < a.slots; ++sg)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sum[c] += a.acc[(int64_t)sg * a.slot_stride + slot + c * L];
   const cd mxy = {sum[2] * q, sum[3] * q};
   const cm2 M = {{sum[0] * q, 0.0}, mxy, cdc(mxy), {sum[1] * q, 0.0}};
   cd gx = {1.0, 0.0}, gy = {1.0, 0.0}, dx = {0.0, 0.0}, dy = {0.0, 0.0};
