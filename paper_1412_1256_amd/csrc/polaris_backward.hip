@@ -42,7 +42,9 @@ __device__ __forceinline__ double tap_window(const float* __restrict__ taps, int
   return (1.0 - t) * (double)taps[j] + t * (double)taps[j + 1];
 }
 
-constexpr int kWinThreads = 256, kWinPerThread = 16;
+// two points per thread: every CU takes part (16 points per thread left 16 workgroups at 2^16 points, each
+// thread waiting on 16 dependent FP64 divisions)
+constexpr int kWinThreads = 256, kWinPerThread = 2;
 
 // w[n] in FP32 for the transforms, and per-block partial sums of w^2 in FP64 (fixed order)
 __global__ void __launch_bounds__(kWinThreads) k_window_taps(WinArgs a) {
@@ -66,13 +68,20 @@ __global__ void __launch_bounds__(kWinThreads) k_window_taps(WinArgs a) {
   if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0];
 }
 
-// sum of the block partials in block order
+// sum of the block partials: lane t adds the t-th of 64 contiguous runs in block order, then the 64 run sums
+// are added by a fixed tree (the result does not depend on timing)
 __global__ void __launch_bounds__(64) k_sum_partials(const double* __restrict__ partial, int n, double* out) {
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += partial[i];
-    out[0] = s;
+  __shared__ double red[64];
+  const int t = (int)threadIdx.x, run = (n + 63) / 64;
+  double s = 0.0;
+  for (int i = t * run; i < n && i < (t + 1) * run; ++i) s += partial[i];
+  red[t] = s;
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
   }
+  if (t == 0) out[0] = red[0];
 }
 
 // ------------------------------------------------------------------------------------------------
