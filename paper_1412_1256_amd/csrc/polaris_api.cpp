@@ -1077,15 +1077,15 @@ ps_status ps_set_window_taps(ps_plan_t plan, int32_t inst, const float* taps_dev
   if (!I.taps()) return fail(PS_ERR_ARG, "instance %d does not use a PS_WIN_TAPS window", inst);
   if (!taps_dev) return fail(PS_ERR_ARG, "null taps");
   plan->touch(I);
-  hipError_t e = ps::launch_copy(taps_dev, plan->ws + I.off_taps, (size_t)I.cfg.n_taps * 4, plan->stream);
-  if (e != hipSuccess) return hip_fail(e, "taps copy");
+  // the window kernel reads the caller's taps and keeps a copy in the workspace for the adjoint
   ps::WinArgs w{};
-  w.taps = ws_ptr<float>(plan, I.off_taps);
+  w.taps = taps_dev;
+  w.taps_copy = ws_ptr<float>(plan, I.off_taps);
   w.n_taps = I.cfg.n_taps;
   w.N = I.N;
   w.win = ws_ptr<float>(plan, I.off_win);
   w.partial = ws_ptr<double>(plan, I.off_wpart);
-  e = timed(plan, PS_KERNEL_OTHER, [&](const ps::Launch& l) {
+  hipError_t e = timed(plan, PS_KERNEL_OTHER, [&](const ps::Launch& l) {
     return ps::launch_window_taps(w, ps::window_taps_blocks(I.N), ws_ptr<double>(plan, I.off_sumw2), l);
   });
   if (e != hipSuccess) return hip_fail(e, "window launch");

@@ -49,6 +49,8 @@ constexpr int kWinThreads = 256, kWinPerThread = 2;
 // w[n] in FP32 for the transforms, and per-block partial sums of w^2 in FP64 (fixed order)
 __global__ void __launch_bounds__(kWinThreads) k_window_taps(WinArgs a) {
   __shared__ double red[kWinThreads];
+  if (blockIdx.x == 0)
+    for (int i = (int)threadIdx.x; i < a.n_taps; i += kWinThreads) a.taps_copy[i] = a.taps[i];
   const int64_t base = (int64_t)blockIdx.x * kWinThreads * kWinPerThread;
   double s = 0.0;
   for (int e = 0; e < kWinPerThread; ++e) {

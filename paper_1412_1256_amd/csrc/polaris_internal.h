@@ -104,7 +104,8 @@ struct MxRowArgs {
 // ---- differentiation form ----------------------------------------------------------------------
 
 struct WinArgs {            // learnable window from its control points
-  const float* taps;
+  const float* taps;        // the caller's control points
+  float* taps_copy;         // [n_taps] the plan's copy of them (for the adjoint), written by the first block
   int32_t n_taps;
   int64_t N;
   float* win;               // [N]
