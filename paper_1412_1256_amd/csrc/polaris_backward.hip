@@ -536,10 +536,15 @@ __global__ void __launch_bounds__(kTapThreads) k_bw_taps_block(BwTapArgs a) {
   }
 }
 
-// tap j: the blocks whose samples can touch it (segments j - 1 and j), in block order
-__global__ void __launch_bounds__(256) k_bw_taps_sum(BwTapArgs a) {
-  const int j = (int)(blockIdx.x * 256 + threadIdx.x), T = a.n_taps;
-  if (j >= T) return;
+// tap j: the blocks whose samples can touch it (segments j - 1 and j).  One wave per tap: lane l adds the
+// blocks b_lo + l, b_lo + l + 64, ... in order (their loads independent of each other: one lane walking all
+// the blocks waited for each load in turn), then the 64 lane sums are added by a fixed butterfly
+constexpr int kTapSumWaves = 4;
+
+__global__ void __launch_bounds__(64 * kTapSumWaves) k_bw_taps_sum(BwTapArgs a) {
+  const int lane = (int)threadIdx.x % 64;
+  const int j = (int)blockIdx.x * kTapSumWaves + (int)threadIdx.x / 64, T = a.n_taps;
+  if (j >= T) return;  // the same for the whole wave
   // samples of segments j - 1 and j, widened by one on each side (a block that does not touch tap j
   // holds zero in its slot for it; the last segment takes the tail)
   const double seg = (double)(a.N - 1) / (double)(T - 1);
@@ -548,14 +553,16 @@ __global__ void __launch_bounds__(256) k_bw_taps_sum(BwTapArgs a) {
   if (lo < 0) lo = 0;
   if (hi > a.N - 1) hi = a.N - 1;
   double s = 0.0;
-  for (int64_t b = lo / kTapThreads; b <= hi / kTapThreads; ++b) {
+  for (int64_t b = lo / kTapThreads + lane; b <= hi / kTapThreads; b += 64) {
     int jl;
     double t;
     tap_position(b * kTapThreads, a.N, T, jl, t);  // the same segment as tap_segment (both exact floors)
     const int i = j - jl;
     if (i >= 0 && i < kTapSpan) s += a.part[b * kTapSpan + i];
   }
-  a.d_taps[j] = (float)s;
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
+  if (lane == 0) a.d_taps[j] = (float)s;
 }
 
 __global__ void __launch_bounds__(kTapThreads) k_bw_taps(BwTapArgs a) {
@@ -702,8 +709,8 @@ hipError_t launch_bw_taps(const BwTapArgs& a, const Launch& l) {
     // one block per kTapThreads samples, and one for the leakage gradients
     hipExtLaunchKernelGGL(k_bw_taps_block, dim3((unsigned)((a.N + kTapThreads - 1) / kTapThreads + 1)),
                           dim3(kTapThreads), 0, l.stream, l.start, nullptr, 0, a);
-    hipExtLaunchKernelGGL(k_bw_taps_sum, dim3((unsigned)((a.n_taps + 255) / 256)), dim3(256), 0, l.stream, nullptr,
-                          l.stop, 0, a);
+    hipExtLaunchKernelGGL(k_bw_taps_sum, dim3((unsigned)((a.n_taps + kTapSumWaves - 1) / kTapSumWaves)),
+                          dim3(64 * kTapSumWaves), 0, l.stream, nullptr, l.stop, 0, a);
     return hipGetLastError();
   }
   hipExtLaunchKernelGGL(k_bw_dw_sum, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, l.stream, l.start, nullptr, 0,
