@@ -729,8 +729,9 @@ def short_form(pk, torch, dev, steps):
 
 
 def post_form(pk, torch, dev, reps):
-    """The post-integration reductions at the paper's sizes (device time per call, events on the current
-    stream): channel averaging of one integration's Stokes spectra 131072 -> 4096 channels with a flagged
+    """The post-integration reductions at the paper's sizes (time per call: events on the current stream around
+    back-to-back calls, so a short reduction shows the binding's call rate; the kernels' own durations come
+    from a kernel trace): channel averaging of one integration's Stokes spectra 131072 -> 4096 channels with a flagged
     channel (Sec. 4); the bandpass table of 131072 channels (128-channel knots, 6 % edges) and the variation
     of 30 integrations H^_k = H_k / (G_k H), averaged over 256 channels, with mean and SD (Sec. 3.3.2); the
     TAV (Eq. 3) of every channel over 1800 1-s integrations and the SAV (Eq. 4) of 30 spectra, 8 lags each."""
