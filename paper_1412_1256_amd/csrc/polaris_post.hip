@@ -347,22 +347,40 @@ __global__ void __launch_bounds__(kNT) k_allan_total(AllanArgs a, int64_t chunks
   const int64_t s_ = (int64_t)blockIdx.x * kNT + threadIdx.x;
   if (s_ >= a.n_series) return;
   const double* part = a.part + s_ * chunks * (a.n_lags + 1) * 2;
+  // the chunks' (sum, count) pairs of field f added in chunk order, their loads issued eight chunks at a time
+  // (one chunk at a time, each add waited for its own load)
+  auto chunk_sum = [&](int f, double& s, double& n) {
+    const int64_t rec = (int64_t)(a.n_lags + 1) * 2;
+    const double* q = part + 2 * f;
+    int64_t c = 0;
+    for (; c + 8 <= chunks; c += 8) {
+      double v[8][2];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        v[j][0] = q[(c + j) * rec];
+        v[j][1] = q[(c + j) * rec + 1];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        s += v[j][0];
+        n += v[j][1];
+      }
+    }
+    for (; c < chunks; ++c) {
+      s += q[c * rec];
+      n += q[c * rec + 1];
+    }
+  };
   double mean2 = 1.0;
   if (a.normalize) {
     double s = 0.0, n = 0.0;
-    for (int64_t c = 0; c < chunks; ++c) {
-      s += part[(c * (a.n_lags + 1) + a.n_lags) * 2];
-      n += part[(c * (a.n_lags + 1) + a.n_lags) * 2 + 1];
-    }
+    chunk_sum(a.n_lags, s, n);
     const double m = s / n;
     mean2 = m * m;
   }
   for (int l = 0; l < a.n_lags; ++l) {
     double s = 0.0, n = 0.0;
-    for (int64_t c = 0; c < chunks; ++c) {
-      s += part[(c * (a.n_lags + 1) + l) * 2];
-      n += part[(c * (a.n_lags + 1) + l) * 2 + 1];
-    }
+    chunk_sum(l, s, n);
     const double tau = (double)a.lags[l] * a.spacing;
     a.out[s_ * a.n_lags + l] = n > 0.0 ? s / n / (2.0 * tau * tau) / mean2 : NAN;
   }
