@@ -162,13 +162,19 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
           }
         }
     }
+    // The next frame's loads and this frame's stores are issued at raised wave priority, so that they reach
+    // the memory system before the other waves' arithmetic (column pass 41.3 -> 40.4 us, two integrations
+    // in flight 62.0 -> 61.1 us on the paper workload)
+    __builtin_amdgcn_s_setprio(3);
     if (f + 1 < f_end) ld.template fetch<L, R0>(a, (int64_t)(f + 1) * a.hop, ts, n2b);
+    __builtin_amdgcn_s_setprio(0);
     col_chain<L, COLS, V, NB, 0>(v, ts, cv, tw, tile);
     // with an odd number of exchanges per frame the next frame's first exchange reuses the tile the last
     // one read: wait for every reader first
     if constexpr (NB == 2 && (SC::NPASS - 1) % 2 == 1) __syncthreads();
     // write T[f][p][k1][n2b ..] for k1 = ts + r L/8 (global stores: the next kernel reads them from every XCD)
     const uint32_t voff = 8u * (uint32_t)(ts * a.N2 + n2b);
+    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const gbytes base = uniform_gptr(reinterpret_cast<const uint8_t*>(
@@ -183,6 +189,7 @@ __device__ __forceinline__ void colpass_tile(const ColArgs& a, const int blk) {
         *(__attribute__((address_space(1))) f32x2*)(base + voff) = q;
       }
     }
+    __builtin_amdgcn_s_setprio(0);
   };
   // One loop from the first frame: the wait for a frame's input words then also waits for the previous
   // frame's stores (issued after those words).  Peeling the first frame, so that the stores stay in flight
