@@ -265,16 +265,11 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
       // see the row pass
       if (pp == NPP - 1) {
         __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_s_setprio(3);  // the loads issued ahead of the other waves' arithmetic
         fetch(min(f + 1, f_end - 1));
-        __builtin_amdgcn_s_setprio(0);
       }
       __syncthreads();
       // ---- stage B and the four-step twiddle
       const uint32_t* Tf = a.T + ((int64_t)__builtin_amdgcn_readfirstlane(f) * c.P + p) * (int64_t)N1 * N2;
-      // stage B and its stores at raised wave priority (with the raised fetch: pass 106-108 -> 101 us per
-      // launch of 122 frames, one 10-s integration 912 -> 890 us)
-      __builtin_amdgcn_s_setprio(2);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int kap = w + 4 * t;
@@ -294,7 +289,6 @@ __global__ void __launch_bounds__(256, 2) k_colpass_mx(MxColArgs a) {
           }
         }
       }
-      __builtin_amdgcn_s_setprio(0);
       __syncthreads();
     }
   }
