@@ -123,6 +123,17 @@ __global__ void __launch_bounds__(kBwChanThreads) k_bw_channel(BwChanArgs a) {
   const double fs = a.n_frames * a.sumw2[0];
   // normalised coherency M (stored sums are 4 XX*, 4 YY*, 4 XY*)
   const double q = 0.25 / fs;
+  // the calibration and the upstream gradient are loaded first, so their round trip overlaps the sums'
+  cd gx = {1.0, 0.0}, gy = {1.0, 0.0}, dx = {0.0, 0.0}, dy = {0.0, 0.0};
+  const int64_t gi = 2 * ((int64_t)p * a.C + k);
+  if (a.gain_x) gx = {(double)a.gain_x[gi], (double)a.gain_x[gi + 1]};
+  if (a.gain_y) gy = {(double)a.gain_y[gi], (double)a.gain_y[gi + 1]};
+  if (a.dterms) {
+    dx = {(double)a.dterms[4 * p + 0], (double)a.dterms[4 * p + 1]};
+    dy = {(double)a.dterms[4 * p + 2], (double)a.dterms[4 * p + 3]};
+  }
+  const float* g = a.g_iquv + (int64_t)p * 4 * a.C + k;
+  const double gI = g[0], gQ = g[a.C], gU = g[2 * a.C], gV = g[3 * a.C];
   // the slots' sums, added in slot order; the loads are issued four slots at a time (one slot at a time, each
   // add waiting for its load, the chain of round trips set the kernel's duration)
   double sum[4];
@@ -145,14 +156,6 @@ __global__ void __launch_bounds__(kBwChanThreads) k_bw_channel(BwChanArgs a) {
     for (int c = 0; c < 4; ++c) sum[c] += a.acc[(int64_t)sg * a.slot_stride + slot + c * L];
   const cd mxy = {sum[2] * q, sum[3] * q};
   const cm2 M = {{sum[0] * q, 0.0}, mxy, cdc(mxy), {sum[1] * q, 0.0}};
-  cd gx = {1.0, 0.0}, gy = {1.0, 0.0}, dx = {0.0, 0.0}, dy = {0.0, 0.0};
-  const int64_t gi = 2 * ((int64_t)p * a.C + k);
-  if (a.gain_x) gx = {(double)a.gain_x[gi], (double)a.gain_x[gi + 1]};
-  if (a.gain_y) gy = {(double)a.gain_y[gi], (double)a.gain_y[gi + 1]};
-  if (a.dterms) {
-    dx = {(double)a.dterms[4 * p + 0], (double)a.dterms[4 * p + 1]};
-    dy = {(double)a.dterms[4 * p + 2], (double)a.dterms[4 * p + 3]};
-  }
   const cm2 G = {gx, {0.0, 0.0}, {0.0, 0.0}, gy};
   const cm2 J = {{1.0, 0.0}, dx, dy, {1.0, 0.0}};
   const cm2 E = mmul(G, J);
@@ -161,8 +164,6 @@ __global__ void __launch_bounds__(kBwChanThreads) k_bw_channel(BwChanArgs a) {
   const cd id = {det.x * inv, -det.y * inv};
   const cm2 Fi = {cdm(E.d, id), cdm({-E.b.x, -E.b.y}, id), cdm({-E.c.x, -E.c.y}, id), cdm(E.a, id)};
   // Gb(C) from the upstream gradient on I, Q, U, V (Eq. 2 rows; real outputs)
-  const float* g = a.g_iquv + (int64_t)p * 4 * a.C + k;
-  const double gI = g[0], gQ = g[a.C], gU = g[2 * a.C], gV = g[3 * a.C];
   const double c2 = a.cos2psi, s2 = a.sin2psi;
   const cd gc00 = {0.5 * (gI + c2 * gQ + s2 * gU), 0.0};
   const cd gc11 = {0.5 * (gI - c2 * gQ - s2 * gU), 0.0};
@@ -645,9 +646,9 @@ hipError_t launch_bw_channel(int N2, const BwChanArgs& a, const Launch& l, bool 
 
 template <int L, int UB, int FB>
 static hipError_t bw_rowpass_launch(const BwRowArgs& a, const Launch& l) {
-  // enough frame groups for about 256 workgroups
+  // enough frame groups for about 512 workgroups: two per CU for the 512-thread shapes (their registers allow two)
   const int units = a.N1 / 2 / UB * a.P;
-  int groups = (256 + units - 1) / units;
+  int groups = (512 + units - 1) / units;
   if (groups > a.n_frames) groups = a.n_frames > 0 ? a.n_frames : 1;
   const int fpg = (a.n_frames + groups - 1) / groups;
   groups = (a.n_frames + fpg - 1) / fpg;
