@@ -646,9 +646,13 @@ hipError_t launch_bw_channel(int N2, const BwChanArgs& a, const Launch& l, bool 
 
 template <int L, int UB, int FB>
 static hipError_t bw_rowpass_launch(const BwRowArgs& a, const Launch& l) {
-  // enough frame groups for about 512 workgroups: two per CU for the 512-thread shapes (their registers allow two)
+  // enough frame groups for about 16 waves on each of the 256 CUs (four per SIMD, what the kernel's 120-odd
+  // VGPRs allow): with fewer, the transforms' LDS round trips went unhidden; at N2 = 256 the workgroups hold
+  // four frames (256 threads), whose barriers wait on fewer waves than those of eight-frame workgroups
+  constexpr int NT = UB * FB * L / 4;
   const int units = a.N1 / 2 / UB * a.P;
-  int groups = (512 + units - 1) / units;
+  const int target = 256 * 16 * 64 / NT;
+  int groups = (target + units - 1) / units;
   if (groups > a.n_frames) groups = a.n_frames > 0 ? a.n_frames : 1;
   const int fpg = (a.n_frames + groups - 1) / groups;
   groups = (a.n_frames + fpg - 1) / fpg;
@@ -663,7 +667,7 @@ hipError_t launch_bw_rowpass(int N2, const BwRowArgs& a, const Launch& l) {
     case 32: return bw_rowpass_launch<32, 8, 4>(a, l);
     case 64: return bw_rowpass_launch<64, 4, 4>(a, l);
     case 128: return bw_rowpass_launch<128, 2, 4>(a, l);
-    case 256: return bw_rowpass_launch<256, 1, 8>(a, l);
+    case 256: return bw_rowpass_launch<256, 1, 4>(a, l);
     case 512: return bw_rowpass_launch<512, 1, 4>(a, l);
     default: return hipErrorInvalidValue;
   }
